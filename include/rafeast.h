@@ -1,0 +1,250 @@
+/*
+ * rafeast.h -- RA-FEAST partial symmetric eigensolver on one AMD MI355X (gfx950).
+ *
+ * Computes the eigenpairs (lambda_i, v_i) of a real symmetric sparse matrix A
+ * whose eigenvalues lie in a closed interval [lmin, lmax] (the partial
+ * eigenproblem of eq. partial-eig, Section 1), by
+ *   Phase 1  randomized warmstart: Gaussian sketch, power iterations with
+ *            orthonormalisation, Rayleigh-Ritz truncation (Algorithm 2,
+ *            eq. rand-range, eq. B-def);
+ *   Phase 2  FEAST iterations: shifted solves (z_j I - A) X_j = RHS at the
+ *            N_c quadrature nodes (eq. projector-quad), combination,
+ *            orthonormalisation, Rayleigh-Ritz (Algorithm 1).
+ * The shifted systems are solved matrix-free by COCG (conjugate orthogonal CG
+ * for complex-symmetric matrices) on CSR sparse-matrix products.
+ *
+ * Conventions
+ *  - Every call returns a rafeast_status; no exception crosses this ABI.
+ *  - Host arrays in the high-level calls (rafeast_plan/warmstart/solve) are
+ *    column-major n x k (element (i, c) at [c*n + i]) unless stated.
+ *  - Device arrays in the step-level calls (rafeast_spmm ... rafeast_gaussian)
+ *    are row-major n x k (element (i, c) at [i*ld + c]), allocated and owned
+ *    by the caller, and must be valid on the current HIP device.
+ *  - The caller owns every buffer it passes; the plan owns its own copies of
+ *    A and all workspace.  A plan is not thread-safe; distinct plans are
+ *    independent.  All work is enqueued on the plan's stream
+ *    (rafeast_params.hip_stream, or a stream the plan creates when NULL);
+ *    every call returns after its work on that stream has completed.
+ */
+#ifndef RAFEAST_H
+#define RAFEAST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rafeast_status {
+  RAFEAST_OK = 0,
+  RAFEAST_INVALID_ARG = 1,        /* null pointer, n <= 0, lmin >= lmax, m0 < 1 or m0 > n,
+                                     nc < 1 or nc > 64, q < 0, 0 <= p < 4 (Assumption 1.5),
+                                     tolerances <= 0, unknown enum value */
+  RAFEAST_BAD_CSR = 2,            /* rowptr not monotone, rowptr[0] != base, column out of
+                                     range, columns unsorted or duplicated, non-finite value */
+  RAFEAST_NOT_SYMMETRIC = 3,      /* pattern or values not symmetric:
+                                     |a_ij - a_ji| > 1e-14 * ||A||_inf */
+  RAFEAST_OOM = 4,                /* device allocation failed */
+  RAFEAST_DEVICE = 5,             /* HIP runtime error or no usable device; see last_error */
+  RAFEAST_NO_CONVERGENCE = 6,     /* max_iter reached; results are still written */
+  RAFEAST_SUBSPACE_TOO_SMALL = 7, /* M >= m0: the window may hold more eigenvalues than the
+                                     subspace; results are still written */
+  RAFEAST_BREAKDOWN = 8,          /* COCG or orthonormalisation broke down and was not
+                                     recovered; results are still written */
+  RAFEAST_EMPTY_WINDOW = 9,       /* no Ritz value in the window (M = 0); a warning */
+  RAFEAST_UNSUPPORTED = 10        /* valid request this build does not serve (reason in
+                                     last_error) */
+} rafeast_status;
+
+/* rafeast_params.precision: arithmetic of the shifted solves. */
+enum { RAFEAST_FP64 = 0,          /* complex FP64 COCG */
+       RAFEAST_FP32_REFINED = 1 };/* complex FP32 COCG with FP64 true-residual refinement */
+
+/* rafeast_params.ws_op: Phase-1 operator (eq. B-def and Assumption 1.2). */
+enum { RAFEAST_WS_AUTO = 0,       /* FLIP for a bottom window, LITERAL for a top window,
+                                     FOLD for an interior window (Gershgorin bounds) */
+       RAFEAST_WS_LITERAL = 1,    /* B = (A - lmin I)/(lmax - lmin) */
+       RAFEAST_WS_FLIP = 2,       /* C = (s_hi I - A)/(s_hi - lmin) */
+       RAFEAST_WS_FOLD = 3,       /* F = I - ((A - cI)/R)^2, c = window centre,
+                                     R = max(c - s_lo, s_hi - c) */
+       RAFEAST_WS_NONE = 4 };     /* plain FEAST start: orthonormalised sketch, no power steps */
+
+/* rafeast_params.rhs_form: right-hand sides of the shifted solves. */
+enum { RAFEAST_RHS_RESIDUAL = 0,  /* solve against Ritz residuals r_i and use
+                                     (zI-A)^{-1} q = (q + (zI-A)^{-1} r)/(z - theta) */
+       RAFEAST_RHS_LITERAL = 1 }; /* solve against the Ritz vectors q_i (Algorithm 1) */
+
+/* rafeast_params.engine: COCG engine. */
+enum { RAFEAST_ENGINE_AUTO = 0,
+       RAFEAST_ENGINE_RESIDENT = 1,  /* one workgroup per system, vectors on chip (small n) */
+       RAFEAST_ENGINE_STREAM = 2 };  /* all systems per kernel, vectors in HBM (large n) */
+
+/* rafeast_result.flags */
+enum { RAFEAST_PTR_DEVICE = 1 };  /* lambda/resid/X are device pointers */
+
+/* rafeast_result.t_ms phases */
+enum { RAFEAST_PH_RR = 0, RAFEAST_PH_SOLVE = 1, RAFEAST_PH_COMBINE = 2, RAFEAST_PH_ORTH = 3,
+       RAFEAST_PH_TOTAL = 4, RAFEAST_NPHASE = 5 };
+
+typedef struct rafeast_plan_s* rafeast_plan_t;
+
+/* Symmetric matrix in CSR, host memory.  The full symmetric pattern is
+ * required (a triangle-only input fails the symmetry check).  Within a row,
+ * column indices must be strictly increasing. */
+typedef struct rafeast_csr {
+  int64_t n;               /* order, 1 <= n < 2^31 */
+  const int32_t* rowptr;   /* [n+1], rowptr[0] == index_base */
+  const int32_t* colind;   /* [nnz], index_base-based */
+  const double* values;    /* [nnz] */
+  int32_t index_base;      /* 0 or 1 */
+} rafeast_csr;
+
+typedef struct rafeast_params {
+  double lmin, lmax;       /* search interval (closed) */
+  int32_t m0;              /* subspace size (>= number of eigenvalues in the window) */
+  int32_t nc;              /* quadrature nodes on the upper half circle, 1..64 */
+  int32_t q;               /* power iterations of Phase 1 (op applied 2q+1 times) */
+  int32_t p;               /* oversampling; < 0 selects Remark 1's rule:
+                              p = 10 if m0 <= 50 else min(20, ceil(m0/2)) */
+  double tol_eig;          /* stop when every in-window Ritz pair has
+                              ||A q - theta q|| / (max(|lmin|,|lmax|) ||q||) <= tol_eig */
+  double tol_solve;        /* relative residual of each COCG solve */
+  int32_t max_iter;        /* FEAST iterations (filter applications) */
+  int32_t max_cocg;        /* COCG iterations per system, refinement restarts included */
+  int32_t precision;       /* RAFEAST_FP64 | RAFEAST_FP32_REFINED */
+  int32_t ws_op;           /* RAFEAST_WS_* */
+  int32_t rhs_form;        /* RAFEAST_RHS_* */
+  int32_t engine;          /* RAFEAST_ENGINE_* */
+  uint64_t seed;           /* Philox key of the device-generated sketch */
+  void* hip_stream;        /* hipStream_t to run on; NULL: the plan creates its own */
+} rafeast_params;
+
+/* Phase-1 diagnostics (Remark 1's post-hoc check of the power-count condition,
+ * eq. power-cond): op-Ritz estimates of beta_{m0}, beta_{m0+1}. */
+typedef struct rafeast_ws_info {
+  double beta_m0;
+  double beta_m0p1;        /* NaN when p == 0 */
+  double ratio;            /* (beta_m0p1 / beta_m0)^(2q+1) */
+  int32_t op;              /* the RAFEAST_WS_* operator actually used */
+  double t_ms;             /* device time of Phase 1 */
+} rafeast_ws_info;
+
+typedef struct rafeast_result {
+  int32_t flags;           /* in: RAFEAST_PTR_DEVICE or 0 */
+  double* lambda;          /* in: [m0] buffer; out: first M entries, ascending */
+  double* resid;           /* in: [m0] buffer; out: scaled residuals of those pairs */
+  double* X;               /* in: nullable [n*m0] buffer; out: n x M column-major unit
+                              eigenvectors, largest-magnitude entry positive */
+  int32_t M;               /* out: eigenvalues found in [lmin, lmax] */
+  int32_t iters;           /* out: FEAST filter applications performed */
+  int64_t cocg_iters;      /* out: COCG iterations summed over all systems */
+  int32_t cocg_max;        /* out: largest COCG iteration count of one system */
+  int32_t refinements;     /* out: FP64 residual restarts summed over all systems */
+  double max_resid;        /* out: max scaled residual over the M pairs */
+  double t_ms[RAFEAST_NPHASE]; /* out: device time per phase (HIP events) */
+} rafeast_result;
+
+/* Fills *p with defaults: m0 = 0 (must be set), nc = 8, q = 2, p = -1,
+ * tol_eig = 1e-10, tol_solve = 1e-6, max_iter = 20, max_cocg = 20000,
+ * precision FP32_REFINED, ws_op AUTO, rhs_form RESIDUAL, engine AUTO, seed 0. */
+void rafeast_params_default(rafeast_params* p);
+
+/* Validates A and the parameters, copies A to the device (FP64 values plus an
+ * FP32 shadow), computes the Gershgorin interval and the quadrature table
+ * (Gauss-Legendre on the upper half circle over [lmin, lmax]; eq. projector-quad),
+ * and allocates all workspace.  On success *out owns everything; release it
+ * with rafeast_destroy.  On failure *out is NULL and the status says why
+ * (rafeast_last_error(NULL) holds the text). */
+rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm, rafeast_plan_t* out);
+
+/* Phase 1 of Algorithm 2.  omega: nullable host array, column-major
+ * n x (m0+p), the Gaussian sketch; NULL draws it on the device from
+ * Philox4x32-10 keyed by prm.seed (rafeast_gaussian).  The op (chosen by
+ * ws_op) is applied 2q+1 times with CholQR2 after each application; then
+ * Rayleigh-Ritz of A on the result keeps the m0 Ritz vectors with the largest
+ * |op| values.  With ws_op NONE the start is the orthonormalised first m0
+ * sketch columns.  The start block stays in the plan for rafeast_solve.
+ * Q0: nullable host n x m0 column-major output copy.  info: nullable. */
+rafeast_status rafeast_warmstart(rafeast_plan_t plan, const double* omega, double* Q0,
+                                 rafeast_ws_info* info);
+
+/* Phase 2 (Algorithms 1/2).  Q_init: nullable host n x m0 column-major start
+ * block (orthonormalised on entry; a checkpointed subspace resumes the
+ * iteration).  NULL uses the block of the last rafeast_warmstart if no solve
+ * has consumed it, otherwise the orthonormalised first m0 columns of the
+ * device sketch (the ws_op NONE start).  Each iteration: Rayleigh-Ritz and residuals;
+ * stop test; shifted COCG solves for all (node, column) pairs; combination
+ * Q~ = sum_j Re[w_j (z_j I - A)^{-1} Q]; CholQR2.  Writes *res as documented
+ * in rafeast_result.  Returns OK, NO_CONVERGENCE, SUBSPACE_TOO_SMALL,
+ * EMPTY_WINDOW or BREAKDOWN with results written, or an error. */
+rafeast_status rafeast_solve(rafeast_plan_t plan, const double* Q_init, rafeast_result* res);
+
+/* Releases the plan and all its device memory.  NULL is a no-op. */
+void rafeast_destroy(rafeast_plan_t plan);
+
+/* Text of the last error on this plan (or of the last failed rafeast_plan when
+ * plan is NULL).  Valid until the next call on the same plan. */
+const char* rafeast_last_error(rafeast_plan_t plan);
+
+/* Static name of a status code. */
+const char* rafeast_status_string(rafeast_status s);
+
+/* Gershgorin interval, ||A||_inf, nnz and the quadrature table of a plan.
+ * z and w: nullable host arrays of 2*nc doubles (re, im interleaved). */
+rafeast_status rafeast_plan_info(rafeast_plan_t plan, double* sig_lo, double* sig_hi,
+                                 double* anorm_inf, int64_t* nnz, double* z, double* w);
+
+/* ---------------------------------------------------------------------------
+ * Step-level calls on caller-owned device buffers (row-major, see top).  They
+ * use the plan's matrix, stream and workspace and serve the tests of each
+ * stage of the method.
+ * ------------------------------------------------------------------------- */
+
+/* Y = alpha * A X + beta * X for an n x k block (FP64).  X != Y. */
+rafeast_status rafeast_spmm(rafeast_plan_t plan, int32_t k, const double* X, int32_t ldx,
+                            double* Y, int32_t ldy, double alpha, double beta);
+
+/* G = X^T Y (k1 x k2 row-major, ldg >= k2) for n x k1 X and n x k2 Y (FP64,
+ * MFMA f64 split over row chunks, fixed-order final sum).  n is arbitrary. */
+rafeast_status rafeast_gram(rafeast_plan_t plan, int64_t n, int32_t k1, int32_t k2,
+                            const double* X, int32_t ldx, const double* Y, int32_t ldy,
+                            double* G, int32_t ldg);
+
+/* CholQR2 of an n x k block in place (Y <- Y R^{-1}, twice), k <= 192, with
+ * column scaling; when the first Cholesky fails, the shifted variant is used
+ * and a third pass added.  *info (host, nullable): 0 plain, 1 shifted,
+ * 2 failed (Y unchanged from the last good pass). */
+rafeast_status rafeast_cholqr2(rafeast_plan_t plan, int64_t n, int32_t k, double* Y, int32_t ldy,
+                               int32_t* info);
+
+/* Symmetric eigendecomposition of a k x k matrix H (k <= 192, read-only;
+ * the symmetric part is used) by parallel cyclic Jacobi in FP64: theta[k]
+ * ascending, S k x k row-major with column c the unit eigenvector of theta[c]. */
+rafeast_status rafeast_syev(rafeast_plan_t plan, int32_t k, const double* H, double* theta,
+                            double* S);
+
+/* Shifted solves (z_j I - A) X_{j,c} = B_c for nz shifts and k right-hand
+ * sides by COCG at the plan's precision and engine.  z: host [2*nz] (re, im).
+ * B: device n x k FP64.  X: device n x (nz*k) complex (re, im interleaved),
+ * FP64 when the plan's precision is FP64, FP32 otherwise; column j*k + c.
+ * The solution is accumulated in FP64 and rounded to X's precision on output.
+ * iters: nullable host [nz*k] COCG iterations per system.  resid: nullable
+ * host [nz*k], ||B_c - (z_j I - A) x|| / ||B_c|| of the FP64 solution (the
+ * stopping test is resid <= tol, tol relative).  Zero right-hand sides give
+ * zero solutions. */
+rafeast_status rafeast_shifted_solve(rafeast_plan_t plan, int32_t nz, const double* z, int32_t k,
+                                     const double* B, int32_t ldb, void* X, double tol,
+                                     int32_t* iters, double* resid);
+
+/* Gaussian sketch Omega (n x w, FP64) from Philox4x32-10 and Box-Muller:
+ * entry (i, c) uses counter (i lo, i hi, c/2, 0) and key (seed lo, seed hi);
+ * u1, u2 are the two 64-bit output halves mapped to (0, 1) with 53 bits;
+ * even c takes sqrt(-2 ln u1) cos(2 pi u2), odd c the sin. */
+rafeast_status rafeast_gaussian(rafeast_plan_t plan, int32_t w, uint64_t seed, double* Omega,
+                                int32_t ld);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAFEAST_H */

@@ -1,0 +1,466 @@
+// COCG for the shifted systems (z_j I - A) d = b of the FEAST filter
+// (Section 2.1: the dominant cost, one solve per quadrature node and subspace
+// column).  COCG (van der Vorst & Melissen, 1990) is CG with the unconjugated
+// bilinear form x^T y, valid for the complex-symmetric z I - A.
+//
+// Resident engine: one 1024-thread workgroup owns one system for its whole
+// solve.  The search direction p (gathered by the SpMM) and the residual r
+// live in LDS, w = (zI - A) p lives in registers (RPT slots per thread), and
+// the iterate x, only read-modify-written, lives in a per-workgroup global
+// buffer (L2-resident).  A is streamed from L2 in the row-sorted
+// SELL-64 layout of kernels.h (one 8- or 16-byte load per nonzero, coalesced
+// across the wave, the column already an LDS byte offset).  Both COCG
+// reductions per iteration are workgroup reductions: no grid-wide
+// synchronisation, and systems with different iteration counts retire
+// independently.  Workgroups take systems from an atomic work counter in the
+// order given (longest first).
+//
+// Per system: b is scaled to unit norm.  Mixed-precision iterative
+// refinement: each cycle runs COCG in T (float or double; per-thread sums in
+// T, cross-thread sums in FP64) on the current residual until its recurrence
+// residual is <= max(tol, eps_inner * its starting norm) (eps_inner 1e-6 in
+// FP32), accumulating the correction in T; the correction is then added to
+// the FP64 solution x_hi (a per-workgroup global buffer, indexed by slot),
+// and the true residual s = b - (zI - A) x_hi is formed in FP64 with FP64
+// values of A.  If ||s|| > tol the next cycle starts from r = p = s, at most
+// max_refine times.  A breakdown (p^T w = 0 or a non-finite step) also ends
+// the cycle.
+#include "device.h"
+#include "kernels.h"
+
+namespace rafeast {
+
+constexpr int kResThreads = 1024;
+constexpr int kResWaves = kResThreads / 64;
+
+// Workgroup sum of NV values given per-thread partials of type A (float or
+// double): DPP wave sums (no LDS), one LDS slot per wave, a barrier, then
+// every thread adds the kResWaves wave sums in the same order in FP64.
+template <int NV, typename A>
+__device__ __forceinline__ void block_sum(const A (&part)[NV], double (&v)[NV],
+                                          double (*red)[kResWaves][4], int set) {
+  const int wv = threadIdx.x >> 6;
+  double ws[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if constexpr (sizeof(A) == 4)
+      ws[q] = (double)wave_sum_f32(part[q]);
+    else
+      ws[q] = wave_sum_f64(part[q]);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[set][wv][q] = ws[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kResWaves; ++w) s += red[set][w][q];
+    v[q] = s;
+  }
+}
+
+template <typename T>
+struct EntryOf;
+template <>
+struct EntryOf<float> {
+  using type = SellEntry32;
+};
+template <>
+struct EntryOf<double> {
+  using type = SellEntry64;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> gather(const char* __restrict__ base, int byte_off) {
+  return *reinterpret_cast<const cpx<T>*>(base + byte_off);
+}
+
+// Gather from an absolute LDS byte address: p is the first object of the
+// kernel's LDS (no static LDS; checked at launch), so the stored offset is
+// the address and the load needs no address arithmetic.
+template <typename T>
+__device__ __forceinline__ cpx<T> lds_gather(int byte_addr) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef const __attribute__((address_space(3))) cpx<T> lds_t;
+  return *reinterpret_cast<lds_t*>((size_t)(unsigned)byte_addr);
+#else
+  (void)byte_addr;  // device-only function; the host pass never calls it
+  return cpx<T>{T(0), T(0)};
+#endif
+}
+
+// sum_k a_k v[c_k] over one slot's entries (width a multiple of 4), in
+// batches of four entry loads issued before their gathers.
+template <typename T, typename AccT, typename E>
+__device__ __forceinline__ void sell_dot(const E* __restrict__ ep, int wdt,
+                                         const char* __restrict__ vbase, AccT& ar, AccT& ai) {
+  for (int kk = 0; kk < wdt; kk += 4) {
+    E e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e[u] = ep[(kk + u) * 64];
+    cpx<T> g[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) g[u] = gather<T>(vbase, e[u].c);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ar += (AccT)e[u].v * (AccT)g[u].re;
+      ai += (AccT)e[u].v * (AccT)g[u].im;
+    }
+  }
+}
+
+template <typename E>
+__device__ __forceinline__ E load_entry(const E* __restrict__ base, unsigned idx) {
+  // 32-bit byte offset from a uniform base: one VGPR of address per load
+  return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) +
+                                     idx * (unsigned)sizeof(E));
+}
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(kResThreads) void k_cocg_resident(
+    int nslices, const int* __restrict__ sbase, const int* __restrict__ perm,
+    const typename EntryOf<T>::type* __restrict__ ent, const SellEntry64* __restrict__ ent64,
+    int nitems, const int* __restrict__ items, const double* __restrict__ zs,
+    const double* __restrict__ Bm, int ldb, int kcols, cpx<T>* __restrict__ D, int ldd,
+    double tol, int maxit, int max_refine, int* __restrict__ counter, int* __restrict__ iters,
+    int* __restrict__ stats, double* __restrict__ resid_out, cpx<double>* __restrict__ xhi_all,
+    cpx<T>* __restrict__ xlo_all, int zero_base) {
+  // Dynamic LDS only (so p starts at address 0 and a gather address is the
+  // entry's stored byte offset): p | r | reduction slots | work item.
+  extern __shared__ unsigned char smem_raw[];
+  const int npad = nslices * 64;
+  cpx<T>* P = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* R = P + npad;
+  double(*red)[kResWaves][4] =
+      reinterpret_cast<double(*)[kResWaves][4]>(smem_raw + (size_t)npad * 2 * sizeof(cpx<T>));
+  int& s_item = *reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(red) +
+                                        2 * kResWaves * 4 * sizeof(double));
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double tol2 = tol * tol;
+  cpx<double>* __restrict__ XH = xhi_all + (size_t)blockIdx.x * npad;
+  cpx<T>* __restrict__ XL = xlo_all + (size_t)blockIdx.x * npad;
+  const char* Pb = reinterpret_cast<const char*>(P);
+
+  cpx<T> w[RPT];
+
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= nitems) break;
+    const int j = items[2 * item], ci = items[2 * item + 1];
+    const double zr = zs[2 * j], zi = zs[2 * j + 1];
+    const int ocol = j * kcols + ci;
+
+    // ---- right-hand side, scaled to unit norm ----
+    double acc1[1] = {0.0};
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int slice = wv + kResWaves * t;
+      if (slice < nslices) {
+        const int row = perm[slice * 64 + lane];
+        const double b = row >= 0 ? Bm[(unsigned)row * (unsigned)ldb + ci] : 0.0;
+        acc1[0] += b * b;
+      }
+    }
+    double bsum[1];
+    block_sum<1>(acc1, bsum, red, 0);
+    const double bn2 = bsum[0];
+    if (!(bn2 > 0.0) || !isfinite(bn2)) {
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int slice = wv + kResWaves * t;
+        if (slice < nslices) {
+          const int row = perm[slice * 64 + lane];
+          if (row >= 0) D[(unsigned)row * (unsigned)ldd + ocol] = cpx<T>{T(0), T(0)};
+        }
+      }
+      if (tid == 0) {
+        iters[ocol] = 0;
+        if (resid_out) resid_out[ocol] = 0.0;
+      }
+      continue;
+    }
+    const double scale = 1.0 / sqrt(bn2);
+    double rho3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int slice = wv + kResWaves * t;
+      if (slice < nslices) {
+        const int s = slice * 64 + lane;
+        const int row = perm[s];
+        const double b = row >= 0 ? Bm[(unsigned)row * (unsigned)ldb + ci] * scale : 0.0;
+        const cpx<T> rv{T(b), T(0)};
+        P[s] = rv;
+        R[s] = rv;
+        XL[s] = cpx<T>{T(0), T(0)};
+        XH[s] = cpx<double>{0.0, 0.0};
+        const double rr = (double)rv.re;
+        rho3[0] += rr * rr;
+      }
+    }
+    double rho_s[3];
+    block_sum<3>(rho3, rho_s, red, 1);
+    double rho_re = rho_s[0], rho_im = 0.0;
+    int it = 0, nref = 0, nbd = 0;
+    double last_res = 1.0;
+    // A cycle stops at max(tol, eps_inner * ||r at cycle start||): the
+    // relative reduction one cycle in T can deliver reliably.
+    const double eps_inner = sizeof(T) == 4 ? 1e-6 : 1e-14;
+    double cyc_tol2 = fmax(tol2, eps_inner * eps_inner * rho_s[0]);
+
+    for (;;) {
+      bool verify = false;
+      // Slot addresses are cheap to recompute; hiding the lane index from
+      // loop-invariant code motion keeps them out of the register budget.
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      // ---- w = (zI - A) p,  mu = p^T w ----
+      // All RPT slots of a thread advance together in batches of KB entries:
+      // the entry loads of every slot in a batch are issued before any
+      // gather, so one L2 round trip serves RPT * KB nonzeros per lane.
+      // Slices are sorted by decreasing width, so slot 0 is the widest; a
+      // slot past its width reads the shared zero entries instead (a
+      // wave-uniform select, no branch), which keeps the batch straight-line.
+      constexpr int KB = (sizeof(T) == 4 && RPT <= 4) ? 4 : 2;
+      using E = typename EntryOf<T>::type;
+      T acc_re[RPT], acc_im[RPT];
+      int bse[RPT], wde[RPT];
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        acc_re[t] = T(0);
+        acc_im[t] = T(0);
+        const int slice = wv + kResWaves * t;
+        bse[t] = slice < nslices ? sbase[slice] : zero_base;
+        wde[t] = slice < nslices ? (sbase[slice + 1] - bse[t]) >> 6 : 0;
+      }
+      for (int kk = 0; kk < wde[0]; kk += KB) {
+        E e[RPT][KB];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          // uniform base pointer of this slot's batch (or of the zero entries);
+          // the per-lane part of the address is the fixed ln
+          const E* __restrict__ ep = kk < wde[t] ? ent + bse[t] + kk * 64 : ent + zero_base;
+#pragma unroll
+          for (int u = 0; u < KB; ++u) e[t][u] = ep[u * 64 + ln];
+        }
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+#pragma unroll
+          for (int u = 0; u < KB; ++u) {
+            const cpx<T> g = lds_gather<T>(e[t][u].c);
+            acc_re[t] += e[t][u].v * g.re;
+            acc_im[t] += e[t][u].v * g.im;
+          }
+        }
+      }
+      T mu_t[2] = {T(0), T(0)};
+      const T zrt = T(zr), zit = T(zi);
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int slice = wv + kResWaves * t;
+        if (slice < nslices) {
+          const cpx<T> pr = P[slice * 64 + ln];
+          w[t].re = zrt * pr.re - zit * pr.im - acc_re[t];
+          w[t].im = zrt * pr.im + zit * pr.re - acc_im[t];
+          mu_t[0] += pr.re * w[t].re - pr.im * w[t].im;
+          mu_t[1] += pr.re * w[t].im + pr.im * w[t].re;
+        }
+      }
+      // x is only read-modify-written: its loads go out before the reduction
+      cpx<T> xv[RPT];
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int slice = wv + kResWaves * t;
+        if (slice < nslices) xv[t] = XL[slice * 64 + ln];
+      }
+      double mu[2];
+      block_sum<2>(mu_t, mu, red, 0);
+      const zd alpha = zdiv(zd{rho_re, rho_im}, zd{mu[0], mu[1]});
+      if (!(isfinite(alpha.re) && isfinite(alpha.im)) || (mu[0] == 0.0 && mu[1] == 0.0)) {
+        ++nbd;
+        verify = true;
+      } else {
+        // ---- x += alpha p, r -= alpha w, rho' = r^T r, ||r||^2 ----
+        T s3_t[3] = {T(0), T(0), T(0)};
+        const T alr = T(alpha.re), ali = T(alpha.im);
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          const int slice = wv + kResWaves * t;
+          if (slice < nslices) {
+            const int s = slice * 64 + ln;
+            const cpx<T> pr = P[s];
+            xv[t].re += alr * pr.re - ali * pr.im;
+            xv[t].im += alr * pr.im + ali * pr.re;
+            XL[s] = xv[t];
+            cpx<T> rv = R[s];
+            rv.re -= alr * w[t].re - ali * w[t].im;
+            rv.im -= alr * w[t].im + ali * w[t].re;
+            R[s] = rv;
+            s3_t[0] += rv.re * rv.re - rv.im * rv.im;
+            s3_t[1] += T(2) * rv.re * rv.im;
+            s3_t[2] += rv.re * rv.re + rv.im * rv.im;
+          }
+        }
+        double s3[3];
+        block_sum<3>(s3_t, s3, red, 1);
+        ++it;
+        if (s3[2] <= cyc_tol2 || it >= maxit) {
+          verify = true;
+        } else {
+          const zd beta = zdiv(zd{s3[0], s3[1]}, zd{rho_re, rho_im});
+          rho_re = s3[0];
+          rho_im = s3[1];
+          const T br = T(beta.re), bi = T(beta.im);
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) {
+            const int slice = wv + kResWaves * t;
+            if (slice < nslices) {
+              const int s = slice * 64 + ln;
+              const cpx<T> pr = P[s];
+              const cpx<T> rv = R[s];
+              P[s] = cpx<T>{rv.re + br * pr.re - bi * pr.im, rv.im + br * pr.im + bi * pr.re};
+            }
+          }
+          __syncthreads();
+        }
+      }
+      if (!verify) continue;
+
+      // ---- x_hi += x; true residual s = b - (zI - A) x_hi in FP64 ----
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int slice = wv + kResWaves * t;
+        if (slice < nslices) {
+          const int s = slice * 64 + ln;
+          const cpx<T> xl = XL[s];
+          XL[s] = cpx<T>{T(0), T(0)};
+          cpx<double> xh = XH[s];
+          xh.re += (double)xl.re;
+          xh.im += (double)xl.im;
+          XH[s] = xh;
+        }
+      }
+      __syncthreads();
+      double s3p[3] = {0.0, 0.0, 0.0}, s3[3];
+      const char* XHb = reinterpret_cast<const char*>(XH);
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int slice = wv + kResWaves * t;
+        if (slice < nslices) {
+          const int s = slice * 64 + ln;
+          const int base = sbase[slice];
+          const int wdt = (sbase[slice + 1] - base) >> 6;
+          double ar = 0.0, ai = 0.0;
+          sell_dot<double, double>(ent64 + base + ln, wdt, XHb, ar, ai);
+          const cpx<double> xr = XH[s];
+          const int row = perm[s];
+          const double b = row >= 0 ? Bm[(unsigned)row * (unsigned)ldb + ci] * scale : 0.0;
+          const double sr = b - (zr * xr.re - zi * xr.im - ar);
+          const double si = -(zr * xr.im + zi * xr.re - ai);
+          w[t] = cpx<T>{T(sr), T(si)};  // the next cycle's residual
+          s3p[0] += sr * sr - si * si;
+          s3p[1] += 2.0 * sr * si;
+          s3p[2] += sr * sr + si * si;
+        }
+      }
+      block_sum<3>(s3p, s3, red, 0);
+      last_res = sqrt(s3[2]);
+      if (s3[2] <= tol2 || nref >= max_refine || it >= maxit || nbd > 3) break;
+      ++nref;
+      rho_re = s3[0];
+      rho_im = s3[1];
+      cyc_tol2 = fmax(tol2, eps_inner * eps_inner * s3[2]);
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int slice = wv + kResWaves * t;
+        if (slice < nslices) {
+          const int s = slice * 64 + ln;
+          P[s] = w[t];
+          R[s] = w[t];
+        }
+      }
+      __syncthreads();
+    }
+
+    const double bn = sqrt(bn2);
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int slice = wv + kResWaves * t;
+      if (slice < nslices) {
+        const int row = perm[slice * 64 + lane];
+        const cpx<double> xh = XH[slice * 64 + lane];
+        if (row >= 0)
+          D[(unsigned)row * (unsigned)ldd + ocol] = cpx<T>{T(xh.re * bn), T(xh.im * bn)};
+      }
+    }
+    if (tid == 0) {
+      iters[ocol] = it;
+      if (resid_out) resid_out[ocol] = last_res;
+      if (nref) atomicAdd(&stats[0], nref);
+      if (nbd > 3) atomicAdd(&stats[1], 1);
+    }
+  }
+}
+
+size_t cocg_resident_xhi_slots(int n, int blocks) {
+  return (size_t)blocks * (size_t)((n + 63) / 64) * 64;
+}
+
+// p and r in LDS: 16 B per slot in FP32, 32 B in FP64.
+int cocg_resident_max_n(bool fp32) { return (fp32 ? 8 : 4) * kResWaves * 64; }
+
+size_t cocg_resident_lds(int n, bool fp32) {
+  const size_t nsl = (size_t)(n + 63) / 64;
+  return nsl * 64 * 2 * (fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>)) +
+         2 * kResWaves * 4 * sizeof(double) + 16;
+}
+
+template <typename T, int RPT>
+static hipError_t launch_res(hipStream_t st, const SellMatrix& A, const CocgLaunch& L,
+                             const typename EntryOf<T>::type* ent, int blocks) {
+  // the gathers address LDS absolutely: the kernel must own no static LDS
+  hipFuncAttributes fa;
+  hipError_t fe = hipFuncGetAttributes(&fa, (const void*)k_cocg_resident<T, RPT>);
+  if (fe != hipSuccess) return fe;
+  if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+  const size_t lds = cocg_resident_lds(A.n, sizeof(T) == 4);
+  hipError_t e = hipFuncSetAttribute((const void*)k_cocg_resident<T, RPT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cocg_resident<T, RPT>), dim3(blocks), dim3(kResThreads), lds, st,
+                     A.nslices, A.sbase, A.perm, ent, A.e64, L.nitems, L.items, L.zs, L.B, L.ldb,
+                     L.k, (cpx<T>*)L.D, L.ldd, L.tol, L.maxit, L.max_refine, L.counter, L.iters,
+                     L.stats, L.resid, (cpx<double>*)L.xhi, (cpx<T>*)L.xlo, A.zero_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_cocg_resident(hipStream_t st, const SellMatrix& A, const CocgLaunch& L,
+                                bool fp32, int num_blocks) {
+  if (A.n > cocg_resident_max_n(fp32)) return hipErrorInvalidValue;
+  // 32-bit indexing of the RHS and output blocks
+  if ((int64_t)A.n * L.ldb >= (int64_t(1) << 31) || (int64_t)A.n * L.ldd >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;
+  if (L.nitems <= 0) return hipSuccess;
+  const int need = (A.nslices + kResWaves - 1) / kResWaves;  // slices per wave
+  int blocks = num_blocks < L.nitems ? num_blocks : L.nitems;
+  if (blocks < 1) blocks = 1;
+  if (L.xhi == nullptr || L.xlo == nullptr || (size_t)blocks * A.nslices * 64 > L.xhi_slots)
+    return hipErrorInvalidValue;
+  if (fp32) {
+    if (need <= 1) return launch_res<float, 1>(st, A, L, A.e32, blocks);
+    if (need <= 2) return launch_res<float, 2>(st, A, L, A.e32, blocks);
+    if (need <= 4) return launch_res<float, 4>(st, A, L, A.e32, blocks);
+    return launch_res<float, 8>(st, A, L, A.e32, blocks);
+  }
+  if (need <= 1) return launch_res<double, 1>(st, A, L, A.e64, blocks);
+  if (need <= 2) return launch_res<double, 2>(st, A, L, A.e64, blocks);
+  return launch_res<double, 4>(st, A, L, A.e64, blocks);
+}
+
+}  // namespace rafeast

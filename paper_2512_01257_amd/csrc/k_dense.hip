@@ -1,0 +1,517 @@
+// Dense and sparse x dense kernels of the RA-FEAST path on gfx950:
+//  - CSR SpMM with FP64 real blocks (Rayleigh-Ritz W = A Q, Phase-1 operator
+//    applications, eq. rand-range and eq. B-def),
+//  - tall-skinny Gram X^T Y and X S products on FP64 MFMA (Rayleigh-Ritz
+//    projection Q^T A Q and CholQR),
+//  - Ritz residuals, filter combination (eq. projector-quad), the Philox
+//    Gaussian sketch (Algorithm 2, Phase 1) and layout helpers.
+#include "device.h"
+#include "kernels.h"
+
+namespace rafeast {
+
+// ============================================================================
+// SpMM, FP64 real: Y = alpha*A*X + beta*X + gamma*X2.  One wave per row; the
+// row's nonzeros are wave-uniform (scalar loads), lanes run over the columns
+// of the block, so every gathered row X[j, :] is one coalesced read.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_spmm_f64(int n, int k, const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ X, int ldx,
+                                                  double* __restrict__ Y, int ldy, double alpha,
+                                                  double beta, const double* __restrict__ X2,
+                                                  int ldx2, double gamma) {
+  const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (row >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int s = rowptr[row], e = rowptr[row + 1];
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int c = c0 + lane;
+    const bool ok = c < k;
+    double acc0 = 0.0, acc1 = 0.0;
+    int t = s;
+    for (; t + 1 < e; t += 2) {
+      const int j0 = col[t], j1 = col[t + 1];
+      const double a0 = val[t], a1 = val[t + 1];
+      if (ok) {
+        acc0 += a0 * X[(size_t)j0 * ldx + c];
+        acc1 += a1 * X[(size_t)j1 * ldx + c];
+      }
+    }
+    if (t < e && ok) acc0 += val[t] * X[(size_t)col[t] * ldx + c];
+    if (ok) {
+      double y = alpha * (acc0 + acc1);
+      if (beta != 0.0) y += beta * X[(size_t)row * ldx + c];
+      if (X2 != nullptr) y += gamma * X2[(size_t)row * ldx2 + c];
+      Y[(size_t)row * ldy + c] = y;
+    }
+  }
+}
+
+hipError_t launch_spmm_f64(hipStream_t st, int n, int k, const int* rowptr, const int* col,
+                           const double* val, const double* X, int ldx, double* Y, int ldy,
+                           double alpha, double beta, const double* X2, int ldx2, double gamma) {
+  if (n <= 0 || k <= 0) return hipSuccess;
+  dim3 grid((n + 3) / 4);
+  hipLaunchKernelGGL(k_spmm_f64, grid, dim3(256), 0, st, n, k, rowptr, col, val, X, ldx, Y, ldy,
+                     alpha, beta, X2, ldx2, gamma);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Gram G = X^T Y on v_mfma_f64_16x16x4f64.
+// Operand layout of the 16x16x4 FP64 MFMA (per lane l of the wave):
+//   A (16 x 4):  A[l % 16][l / 16]        B (4 x 16):  B[l / 16][l % 16]
+//   D (16 x 16): D[l / 16 + 4 v][l % 16], v = 0..3
+// For G = X^T Y the A operand is a 4-row slab of X transposed and B the same
+// rows of Y, so lane l reads X[r + l/16][a0 + l%16] and Y[r + l/16][b0 + l%16]:
+// 16 consecutive doubles of a row per quarter-wave.
+// Rows are split into chunks (grid.x); each wave owns one 16-row tile strip of
+// G and four 16-column tiles; partial Grams are summed in chunk order.
+// ============================================================================
+int gram_chunks(int64_t n) {
+  int64_t c = (n + 127) / 128;
+  if (c > 256) c = 256;
+  if (c < 1) c = 1;
+  return (int)c;
+}
+
+size_t gram_partial_doubles(int64_t n, int k1, int k2) {
+  return (size_t)gram_chunks(n) * (size_t)k1 * (size_t)k2;
+}
+
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k1, int k2,
+                                                      const double* __restrict__ X, int ldx,
+                                                      const double* __restrict__ Y, int ldy,
+                                                      double* __restrict__ part,
+                                                      int64_t rows_per_chunk) {
+  const int chunk = blockIdx.x;
+  const int64_t r_begin = (int64_t)chunk * rows_per_chunk;
+  int64_t r_end = r_begin + rows_per_chunk;
+  if (r_end > n) r_end = n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ta_n = (k1 + 15) >> 4, tb_n = (k2 + 15) >> 4;
+  const int gpr = (tb_n + 3) >> 2;  // groups of 4 column tiles per tile row
+  const int tg = blockIdx.y * 4 + wave;
+  const int ta = tg / gpr, tb0 = (tg % gpr) * 4;
+  if (ta >= ta_n) return;
+  v4d acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int li = lane & 15, lk = lane >> 4;
+  const int a_col = ta * 16 + li;
+  const bool a_ok = a_col < k1;
+  int b_col[4];
+  bool b_ok[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    b_col[t] = (tb0 + t) * 16 + li;
+    b_ok[t] = (tb0 + t) < tb_n && b_col[t] < k2;
+  }
+  for (int64_t r = r_begin; r < r_end; r += 4) {
+    const int64_t rr = r + lk;
+    const bool r_ok = rr < r_end;
+    const double a = (a_ok && r_ok) ? X[rr * ldx + a_col] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double b = (b_ok[t] && r_ok) ? Y[rr * ldy + b_col[t]] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  double* P = part + (size_t)chunk * k1 * k2;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (!((tb0 + t) < tb_n)) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ta * 16 + lk + 4 * v;
+      const int j = (tb0 + t) * 16 + li;
+      if (i < k1 && j < k2) P[(size_t)i * k2 + j] = acc[t][v];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(int chunks, int k1, int k2,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ G, int ldg) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= k1 * k2) return;
+  const size_t stride = (size_t)k1 * k2;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * stride + e];
+  G[(size_t)(e / k2) * ldg + (e % k2)] = s;
+}
+
+hipError_t launch_gram(hipStream_t st, int64_t n, int k1, int k2, const double* X, int ldx,
+                       const double* Y, int ldy, double* G, int ldg, double* part) {
+  if (k1 <= 0 || k2 <= 0) return hipSuccess;
+  const int chunks = gram_chunks(n);
+  int64_t rpc = (n + chunks - 1) / chunks;
+  rpc = (rpc + 3) & ~int64_t(3);
+  const int ta_n = (k1 + 15) / 16, tb_n = (k2 + 15) / 16;
+  const int groups = ta_n * ((tb_n + 3) / 4);
+  dim3 grid(chunks, (groups + 3) / 4);
+  hipLaunchKernelGGL(k_gram_partial, grid, dim3(256), 0, st, n, k1, k2, X, ldx, Y, ldy, part,
+                     rpc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((k1 * k2 + 255) / 256), dim3(256), 0, st, chunks, k1,
+                     k2, part, G, ldg);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// TSMM Y = X S on v_mfma_f64_16x16x4f64: each wave computes a 16-row strip of
+// Y for four 16-column tiles; A operand lane l reads X[r0 + l%16][a0 + l/16],
+// B operand reads S[a0 + l/16][b0 + l%16].
+// ============================================================================
+__global__ __launch_bounds__(256) void k_tsmm(int64_t n, int k, int k2,
+                                              const double* __restrict__ X, int ldx,
+                                              const double* __restrict__ S, int lds,
+                                              double* __restrict__ Y, int ldy) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (r0 >= n) return;
+  const int tb_n = (k2 + 15) >> 4;
+  const int tb0 = blockIdx.y * 4;
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t arow = r0 + li;
+  const bool r_ok = arow < n;
+  int bcol[4];
+  bool bok[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    bcol[t] = (tb0 + t) * 16 + li;
+    bok[t] = (tb0 + t) < tb_n && bcol[t] < k2;
+  }
+  for (int a0 = 0; a0 < k; a0 += 4) {
+    const int acol = a0 + lk;
+    const bool aok = acol < k;
+    const double a = (aok && r_ok) ? X[arow * ldx + acol] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double b = (aok && bok[t]) ? S[(size_t)acol * lds + bcol[t]] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (!bok[t]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = r0 + lk + 4 * v;
+      if (r < n) Y[r * ldy + bcol[t]] = acc[t][v];
+    }
+  }
+}
+
+hipError_t launch_tsmm(hipStream_t st, int64_t n, int k, int k2, const double* X, int ldx,
+                       const double* S, int lds, double* Y, int ldy) {
+  if (n <= 0 || k2 <= 0) return hipSuccess;
+  const int tb_n = (k2 + 15) / 16;
+  dim3 grid((unsigned)((n + 63) / 64), (tb_n + 3) / 4);
+  hipLaunchKernelGGL(k_tsmm, grid, dim3(256), 0, st, n, k, k2, X, ldx, S, lds, Y, ldy);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Ritz residuals R = W - Q diag(theta) and column norms.  Threads are laid out
+// 4 rows x 64 columns; per-thread sums are combined in a fixed order.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_resid_partial(int64_t n, int k,
+                                                       const double* __restrict__ W,
+                                                       const double* __restrict__ Q, int ld,
+                                                       const double* __restrict__ theta,
+                                                       double* __restrict__ R,
+                                                       double* __restrict__ part,
+                                                       int64_t rows_per_chunk) {
+  __shared__ double sh[2][4][64];
+  const int chunk = blockIdx.x;
+  const int64_t rb = (int64_t)chunk * rows_per_chunk;
+  int64_t re = rb + rows_per_chunk;
+  if (re > n) re = n;
+  const int ty = threadIdx.x >> 6, tx = threadIdx.x & 63;
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int c = c0 + tx;
+    double s1 = 0.0, s2 = 0.0;
+    if (c < k) {
+      const double th = theta[c];
+      for (int64_t r = rb + ty; r < re; r += 4) {
+        const double q = Q[r * ld + c];
+        const double v = W[r * ld + c] - th * q;
+        R[r * ld + c] = v;
+        s1 += v * v;
+        s2 += q * q;
+      }
+    }
+    sh[0][ty][tx] = s1;
+    sh[1][ty][tx] = s2;
+    __syncthreads();
+    if (ty == 0 && c < k) {
+      const double a = ((sh[0][0][tx] + sh[0][1][tx]) + sh[0][2][tx]) + sh[0][3][tx];
+      const double b = ((sh[1][0][tx] + sh[1][1][tx]) + sh[1][2][tx]) + sh[1][3][tx];
+      part[(size_t)chunk * 2 * k + c] = a;
+      part[(size_t)chunk * 2 * k + k + c] = b;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_resid_final(int chunks, int k, const double* __restrict__ part, double s_win,
+                              double* __restrict__ res, double* __restrict__ qn) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  double a = 0.0, b = 0.0;
+  for (int ch = 0; ch < chunks; ++ch) {
+    a += part[(size_t)ch * 2 * k + c];
+    b += part[(size_t)ch * 2 * k + k + c];
+  }
+  const double q = sqrt(b);
+  res[c] = sqrt(a) / (s_win * q);
+  qn[c] = q;
+}
+
+hipError_t launch_residual(hipStream_t st, int64_t n, int k, const double* W, const double* Q,
+                           int ld, const double* theta, double s_win, double* R, double* res,
+                           double* qn, double* part) {
+  const int chunks = gram_chunks(n);
+  const int64_t rpc = (n + chunks - 1) / chunks;
+  hipLaunchKernelGGL(k_resid_partial, dim3(chunks), dim3(256), 0, st, n, k, W, Q, ld, theta, R,
+                     part, rpc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_resid_final, dim3((k + 63) / 64), dim3(64), 0, st, chunks, k, part, s_win,
+                     res, qn);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Filter combination (eq. projector-quad, upper-half nodes, real part).
+// ============================================================================
+__global__ void k_gamma(int nc, int k, const double* __restrict__ zw,
+                        const double* __restrict__ theta, double* __restrict__ gamma) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc * k) return;
+  const int j = e / k, i = e % k;
+  const zd z{zw[2 * j], zw[2 * j + 1]};
+  const zd w{zw[2 * nc + 2 * j], zw[2 * nc + 2 * j + 1]};
+  const zd g = zdiv(w, zd{z.re - theta[i], z.im});
+  gamma[2 * e] = g.re;
+  gamma[2 * e + 1] = g.im;
+}
+
+hipError_t launch_gamma(hipStream_t st, int nc, int k, const double* zw, const double* theta,
+                        double* gamma) {
+  const int tot = nc * k;
+  hipLaunchKernelGGL(k_gamma, dim3((tot + 255) / 256), dim3(256), 0, st, nc, k, zw, theta, gamma);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine(int64_t n, int nc, int k,
+                                                 const double* __restrict__ gamma,
+                                                 const double* __restrict__ zw, int residual,
+                                                 const double* __restrict__ Q, int ldq,
+                                                 const cpx<T>* __restrict__ D, int ldd,
+                                                 double* __restrict__ Qt, int ldt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t r = e / k;
+  const int i = (int)(e % k);
+  double acc = 0.0;
+  if (residual) {
+    const double q = Q[r * ldq + i];
+    for (int j = 0; j < nc; ++j) {
+      const cpx<T> d = D[r * ldd + (size_t)j * k + i];
+      const double gr = gamma[2 * (j * k + i)], gi = gamma[2 * (j * k + i) + 1];
+      acc += gr * (q + (double)d.re) - gi * (double)d.im;
+    }
+  } else {
+    for (int j = 0; j < nc; ++j) {
+      const cpx<T> d = D[r * ldd + (size_t)j * k + i];
+      const double wr = zw[2 * nc + 2 * j], wi = zw[2 * nc + 2 * j + 1];
+      acc += wr * (double)d.re - wi * (double)d.im;
+    }
+  }
+  Qt[r * ldt + i] = acc;
+}
+
+hipError_t launch_combine(hipStream_t st, int64_t n, int nc, int k, const double* gamma,
+                          const double* zw, bool residual_form, const double* Q, int ldq,
+                          const void* D, int ldd, bool d32, double* Qt, int ldt) {
+  const int64_t tot = n * k;
+  dim3 grid((unsigned)((tot + 255) / 256));
+  if (d32)
+    hipLaunchKernelGGL(k_combine<float>, grid, dim3(256), 0, st, n, nc, k, gamma, zw,
+                       residual_form ? 1 : 0, Q, ldq, (const cpx<float>*)D, ldd, Qt, ldt);
+  else
+    hipLaunchKernelGGL(k_combine<double>, grid, dim3(256), 0, st, n, nc, k, gamma, zw,
+                       residual_form ? 1 : 0, Q, ldq, (const cpx<double>*)D, ldd, Qt, ldt);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Gaussian sketch: Philox4x32-10 (Salmon et al., SC'11) + Box-Muller.
+// ============================================================================
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    const uint32_t lo0 = M0 * c[0], hi0 = __umulhi(M0, c[0]);
+    const uint32_t lo1 = M1 * c[2], hi1 = __umulhi(M1, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__global__ void k_gaussian(int64_t n, int w, uint32_t s0, uint32_t s1, double* __restrict__ O,
+                           int ld) {
+  const int pairs = (w + 1) >> 1;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * pairs) return;
+  const int64_t i = e / pairs;
+  const int kp = (int)(e % pairs);
+  uint32_t c[4] = {(uint32_t)(i & 0xFFFFFFFF), (uint32_t)((uint64_t)i >> 32), (uint32_t)kp, 0u};
+  philox10(c, s0, s1);
+  const uint64_t x1 = ((uint64_t)c[0] << 32) | c[1];
+  const uint64_t x2 = ((uint64_t)c[2] << 32) | c[3];
+  const double u1 = (double)(x1 >> 11) * 0x1.0p-53 + 0x1.0p-54;
+  const double u2 = (double)(x2 >> 11) * 0x1.0p-53 + 0x1.0p-54;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 6.283185307179586476925287 * u2;
+  O[i * ld + 2 * kp] = rad * cos(ang);
+  if (2 * kp + 1 < w) O[i * ld + 2 * kp + 1] = rad * sin(ang);
+}
+
+hipError_t launch_gaussian(hipStream_t st, int64_t n, int w, uint64_t seed, double* O, int ld) {
+  const int64_t tot = n * ((w + 1) / 2);
+  hipLaunchKernelGGL(k_gaussian, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, w,
+                     (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), O, ld);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Layout helpers.
+// ============================================================================
+__global__ void k_col2row(int64_t n, int k, const double* __restrict__ src,
+                          double* __restrict__ dst, int ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t r = e / k;
+  const int c = (int)(e % k);
+  dst[r * ldd + c] = src[(int64_t)c * n + r];
+}
+
+hipError_t launch_colmajor_to_rowmajor(hipStream_t st, int64_t n, int k, const double* src,
+                                       double* dst, int ldd) {
+  const int64_t tot = n * k;
+  hipLaunchKernelGGL(k_col2row, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, k, src,
+                     dst, ldd);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_cols(int64_t n, int k, const double* __restrict__ src, int lds,
+                            double* __restrict__ dst, int ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t r = e / k;
+  const int c = (int)(e % k);
+  dst[r * ldd + c] = src[r * lds + c];
+}
+
+hipError_t launch_copy_cols(hipStream_t st, int64_t n, int k, const double* src, int lds,
+                            double* dst, int ldd) {
+  const int64_t tot = n * k;
+  hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, k,
+                     src, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+__global__ void k_row2col(int64_t n, int k, const double* __restrict__ src, int lds,
+                          double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const int c = (int)(e / n);
+  const int64_t r = e % n;
+  dst[e] = src[r * lds + c];
+}
+
+hipError_t launch_rowmajor_to_colmajor(hipStream_t st, int64_t n, int k, const double* src,
+                                       int lds, double* dst) {
+  const int64_t tot = n * k;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row2col, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, k, src,
+                     lds, dst);
+  return hipGetLastError();
+}
+
+// One block per exported column: norm, first index of the largest |entry|,
+// then the scaled column into column-major dst.
+__global__ __launch_bounds__(256) void k_export(int64_t n, const int* __restrict__ sel,
+                                                const double* __restrict__ src, int lds,
+                                                double* __restrict__ dst) {
+  __shared__ double s_sq[4], s_mx[4];
+  __shared__ int64_t s_ix[4];
+  const int c = blockIdx.x;
+  const int col = sel[c];
+  double sq = 0.0, mx = -1.0;
+  int64_t ix = n;
+  for (int64_t r = threadIdx.x; r < n; r += 256) {
+    const double v = src[r * lds + col];
+    sq += v * v;
+    const double a = fabs(v);
+    if (a > mx) {  // rows visited in increasing order: keeps the first maximum
+      mx = a;
+      ix = r;
+    }
+  }
+  // wave reduction: (max, lowest index) and sum
+  for (int off = 32; off > 0; off >>= 1) {
+    const double omx = __shfl_xor(mx, off, 64);
+    const int64_t oix = __shfl_xor(ix, off, 64);
+    if (omx > mx || (omx == mx && oix < ix)) {
+      mx = omx;
+      ix = oix;
+    }
+    sq += __shfl_xor(sq, off, 64);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_sq[wv] = sq;
+    s_mx[wv] = mx;
+    s_ix[wv] = ix;
+  }
+  __syncthreads();
+  double tsq = 0.0, tmx = -1.0;
+  int64_t tix = n;
+  for (int w = 0; w < 4; ++w) {
+    tsq += s_sq[w];
+    if (s_mx[w] > tmx || (s_mx[w] == tmx && s_ix[w] < tix)) {
+      tmx = s_mx[w];
+      tix = s_ix[w];
+    }
+  }
+  const double sgn = (tix < n && src[tix * lds + col] < 0.0) ? -1.0 : 1.0;
+  const double sc = sgn / sqrt(tsq);
+  for (int64_t r = threadIdx.x; r < n; r += 256) dst[(int64_t)c * n + r] = src[r * lds + col] * sc;
+}
+
+hipError_t launch_export_vectors(hipStream_t st, int64_t n, int cnt, const int* sel,
+                                 const double* src, int lds, double* dst, double* part) {
+  (void)part;
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_export, dim3(cnt), dim3(256), 0, st, n, sel, src, lds, dst);
+  return hipGetLastError();
+}
+
+}  // namespace rafeast

@@ -1,0 +1,141 @@
+// Host-side launchers of the RA-FEAST kernels.  Every launcher enqueues on
+// `st` and returns the launch status; none synchronises.  Blocks are
+// row-major (element (i, c) at [i * ld + c]).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rafeast {
+
+// ---- sparse x dense (FP64, real) ------------------------------------------
+// Y = alpha * A X + beta * X + gamma * X2 (X2 may be null), CSR A (FP64).
+hipError_t launch_spmm_f64(hipStream_t st, int n, int k, const int* rowptr, const int* col,
+                           const double* val, const double* X, int ldx, double* Y, int ldy,
+                           double alpha, double beta, const double* X2, int ldx2, double gamma);
+
+// ---- tall-skinny products (FP64 MFMA) ----------------------------------------
+// Number of row chunks the Gram splits n into, and the partial buffer it needs.
+int gram_chunks(int64_t n);
+size_t gram_partial_doubles(int64_t n, int k1, int k2);
+// G = X^T Y; `part` holds gram_partial_doubles(n, k1, k2) doubles.
+hipError_t launch_gram(hipStream_t st, int64_t n, int k1, int k2, const double* X, int ldx,
+                       const double* Y, int ldy, double* G, int ldg, double* part);
+// Y = X S, X n x k, S k x k2 (row-major, lds), Y n x k2.  Y must not alias X.
+hipError_t launch_tsmm(hipStream_t st, int64_t n, int k, int k2, const double* X, int ldx,
+                       const double* S, int lds, double* Y, int ldy);
+
+// ---- Rayleigh-Ritz residual ---------------------------------------------------
+// R = W - Q diag(theta); res[c] = ||R_c|| / (s_win ||Q_c||); qn[c] = ||Q_c||.
+// `part` holds 2 * k * gram_chunks(n) doubles.
+hipError_t launch_residual(hipStream_t st, int64_t n, int k, const double* W, const double* Q,
+                           int ld, const double* theta, double s_win, double* R, double* res,
+                           double* qn, double* part);
+
+// ---- filter combination ------------------------------------------------------
+// gamma[j*k + i] = w_j / (z_j - theta_i) (complex, re/im interleaved).
+hipError_t launch_gamma(hipStream_t st, int nc, int k, const double* zw /*[4*nc]: z, w*/,
+                        const double* theta, double* gamma);
+// Residual form:  Qt[r][i] = sum_j Re[gamma_ji (Q[r][i] + D[r][j*k+i])]
+// Literal form:   Qt[r][i] = sum_j Re[w_j D[r][j*k+i]]
+// D is complex (FP32 if d32 else FP64), row-major with ldd complex entries.
+hipError_t launch_combine(hipStream_t st, int64_t n, int nc, int k, const double* gamma,
+                          const double* zw, bool residual_form, const double* Q, int ldq,
+                          const void* D, int ldd, bool d32, double* Qt, int ldt);
+
+// ---- Gaussian sketch (Philox4x32-10 + Box-Muller) ---------------------------
+hipError_t launch_gaussian(hipStream_t st, int64_t n, int w, uint64_t seed, double* O, int ld);
+
+// ---- layout helpers -----------------------------------------------------------
+// dst (row-major, ldd) <- src (column-major n x k, ld n) and back.
+hipError_t launch_colmajor_to_rowmajor(hipStream_t st, int64_t n, int k, const double* src,
+                                       double* dst, int ldd);
+// dst (column-major n x cnt) <- columns sel[0..cnt) of src, each scaled to unit
+// norm with its largest-magnitude entry positive (lowest index on ties).
+// `part` holds 3 * cnt * gram_chunks(n) doubles + cnt ints of scratch.
+hipError_t launch_export_vectors(hipStream_t st, int64_t n, int cnt, const int* sel,
+                                 const double* src, int lds, double* dst, double* part);
+hipError_t launch_copy_cols(hipStream_t st, int64_t n, int k, const double* src, int lds,
+                            double* dst, int ldd);
+
+// ---- small dense (one workgroup) ------------------------------------------------
+// M such that Y M has orthonormal columns for G = Y^T Y (k x k): column
+// scaling, Cholesky (shifted when it fails), triangular inverse.  flag: 0 ok,
+// 1 shifted, 2 failed (M = diagonal scaling).
+hipError_t launch_chol_inv(hipStream_t st, int k, int64_t nrows, const double* G, int ldg,
+                           double* M, int ldm, int* flag);
+// Parallel cyclic Jacobi: theta ascending, S row-major (column c = vector c).
+// `work` holds 2 * k * k doubles.
+hipError_t launch_jacobi(hipStream_t st, int k, const double* H, int ldh, double* theta,
+                         double* S, int lds, double* work);
+// Keep the m0 of k Ritz values with the largest |phi(theta)|,
+// phi(t) = a + b t + c t^2; Ssel (k x m0) <- the kept columns of S in
+// ascending-theta order; info[0] = m0-th largest |phi|, info[1] = (m0+1)-th.
+hipError_t launch_select(hipStream_t st, int k, int m0, const double* theta, const double* S,
+                         int lds, double a, double b, double c, double* Ssel, double* info);
+
+// ---- COCG ---------------------------------------------------------------------
+// SELL-64 copy of A for the resident COCG engine.  Rows are reordered by
+// decreasing length (slot s holds row perm[s]; slots >= n are empty), cut
+// into slices of 64 slots, and stored entry-major within a slice so that the
+// k-th entries of a slice's 64 rows are contiguous.  An entry's column is
+// stored as the byte offset of its slot in a complex vector of the entry's
+// precision (slot * 8 for FP32 complex, slot * 16 for FP64 complex), so a
+// gather needs no address arithmetic.  Slice widths are padded to a multiple
+// of 4 with (own slot, 0).
+struct SellEntry32 {
+  int c;    // slot * 8
+  float v;
+};
+struct SellEntry64 {
+  int c;    // slot * 16
+  int pad;
+  double v;
+};
+struct SellMatrix {
+  int n = 0;
+  int nslices = 0;
+  const int* sbase = nullptr;           // [nslices+1] entry offsets (multiples of 256)
+  const int* perm = nullptr;            // [nslices*64] slot -> row (-1: empty slot)
+  const SellEntry32* e32 = nullptr;     // FP32 entries
+  const SellEntry64* e64 = nullptr;     // FP64 entries
+  int zero_base = 0;                    // 256 entries (slot 0, value 0) start here
+};
+
+struct CocgLaunch {
+  int nitems = 0;
+  const int* items = nullptr;   // [2*nitems] (shift j, column i), longest first
+  const double* zs = nullptr;   // [2*nz] shifts (re, im)
+  const double* B = nullptr;    // n x k RHS (FP64), ldb
+  int ldb = 0;
+  int k = 0;                    // RHS columns; output column of item = j*k + i
+  void* D = nullptr;            // n x (nz*k) complex outputs, ldd complex entries
+  int ldd = 0;
+  double tol = 1e-6;
+  int maxit = 20000;
+  int max_refine = 4;
+  int* counter = nullptr;       // zeroed work counter
+  int* iters = nullptr;         // [nz*k] iterations per system
+  int* stats = nullptr;         // [2]: refinements, breakdowns (accumulated)
+  double* resid = nullptr;      // nullable [nz*k]: final relative true residual
+  void* xhi = nullptr;          // FP64 complex solution scratch, xhi_slots entries
+  void* xlo = nullptr;          // working-precision complex iterate scratch, xhi_slots entries
+  size_t xhi_slots = 0;         // >= blocks * nslices * 64
+};
+
+// FP64 scratch entries (complex) the resident engine needs for `blocks` workgroups.
+size_t cocg_resident_xhi_slots(int n, int blocks);
+// Largest n the resident engine takes at this precision.
+int cocg_resident_max_n(bool fp32);
+// Dynamic LDS bytes the resident engine needs for n.
+size_t cocg_resident_lds(int n, bool fp32);
+hipError_t launch_cocg_resident(hipStream_t st, const SellMatrix& A, const CocgLaunch& L,
+                                bool fp32, int num_blocks);
+
+}  // namespace rafeast
+
+namespace rafeast {
+// dst (column-major n x k) <- src (row-major, lds).
+hipError_t launch_rowmajor_to_colmajor(hipStream_t st, int64_t n, int k, const double* src,
+                                       int lds, double* dst);
+}  // namespace rafeast

@@ -1,0 +1,1059 @@
+// RA-FEAST host runtime and C ABI: validation, plan (device copies of A,
+// quadrature table, workspace), Phase 1 (randomized warmstart) and Phase 2
+// (FEAST iterations) drivers.  All arithmetic of the method runs in the
+// kernels declared in kernels.h; the host only sequences launches and reads
+// back the small per-iteration scalars (Ritz values and residual norms).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rafeast.h"
+#include "kernels.h"
+
+using namespace rafeast;
+
+namespace {
+
+thread_local std::string g_plan_error;
+
+constexpr int kMaxSmallK = 192;
+
+}  // namespace
+
+struct rafeast_plan_s {
+  rafeast_params prm{};
+  int64_t n = 0, nnz = 0;
+  int m0 = 0, w = 0, nc = 0, pov = 0;
+  double sig_lo = 0, sig_hi = 0, anorm = 0;
+  std::vector<double> zw;  // z_j (re, im) then w_j (re, im)
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int dev = 0, num_cu = 0;
+  bool fp32 = true;
+  int engine = RAFEAST_ENGINE_RESIDENT;
+  // matrix
+  int* d_rowptr = nullptr;
+  int* d_col = nullptr;
+  double* d_val = nullptr;
+  SellMatrix sell;
+  int* d_sbase = nullptr;
+  int* d_perm = nullptr;
+  SellEntry32* d_e32 = nullptr;
+  SellEntry64* d_e64 = nullptr;
+  size_t sell_entries = 0;
+  // n x w blocks (row-major, ld = w)
+  double* d_Q = nullptr;
+  double* d_W = nullptr;
+  double* d_R = nullptr;
+  double* d_T = nullptr;
+  double* d_Y = nullptr;
+  int ld = 0;
+  // small matrices
+  double* d_G = nullptr;     // kmax^2
+  double* d_M = nullptr;     // kmax^2
+  double* d_S = nullptr;     // kmax^2
+  double* d_Ssel = nullptr;  // kmax * m0
+  double* d_jw = nullptr;    // 2 kmax^2
+  double* d_theta = nullptr; // kmax
+  double* d_res = nullptr;   // kmax
+  double* d_qn = nullptr;    // kmax
+  double* d_gamma = nullptr; // 2 nc m0
+  double* d_info = nullptr;  // 4
+  double* d_zw = nullptr;    // 4 nc
+  double* d_part = nullptr;
+  size_t part_doubles = 0;
+  void* d_D = nullptr;       // n x (nc m0) complex
+  int* d_items = nullptr;    // 2 nc m0
+  int* d_counter = nullptr;  // 1
+  int* d_iters = nullptr;    // nc m0
+  int* d_stats = nullptr;    // 2
+  int* d_flag = nullptr;     // 1
+  int* d_sel = nullptr;      // m0
+  void* d_xhi = nullptr;     // FP64 solution scratch of the resident COCG engine
+  void* d_xlo = nullptr;     // working-precision iterate scratch of the same
+  size_t xhi_slots = 0;
+  int nitems = 0;
+  bool have_start = false;
+  int ws_used = RAFEAST_WS_NONE;
+  std::string err;
+  hipEvent_t ev[8] = {};
+};
+
+// ============================================================================
+// helpers
+// ============================================================================
+namespace {
+
+rafeast_status fail(rafeast_plan_s* P, rafeast_status s, const std::string& msg) {
+  if (P)
+    P->err = msg;
+  else
+    g_plan_error = msg;
+  return s;
+}
+
+rafeast_status hip_fail(rafeast_plan_s* P, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(P, e == hipErrorOutOfMemory ? RAFEAST_OOM : RAFEAST_DEVICE, msg);
+}
+
+#define HIPCHK(P, expr)                                   \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return hip_fail((P), _e, #expr); \
+  } while (0)
+
+#define RCHK(expr)                            \
+  do {                                        \
+    rafeast_status _s = (expr);               \
+    if (_s != RAFEAST_OK) return _s;          \
+  } while (0)
+
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1] by Newton's method
+// on the Legendre three-term recurrence, starting from the Chebyshev-like
+// estimate cos(pi (i + 3/4) / (N + 1/2)).
+void gauss_legendre_newton(int N, std::vector<double>& x, std::vector<double>& wt) {
+  x.assign(N, 0.0);
+  wt.assign(N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (N + 0.5));
+    double dp = 1.0;
+    for (int itn = 0; itn < 100; ++itn) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= N; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = (N == 1) ? 1.0 : N * (t * p1 - p0) / (t * t - 1.0);
+      const double dx = p1 / dp;
+      t -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    // final derivative at the converged node
+    double p0 = 1.0, p1 = t;
+    for (int k = 2; k <= N; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = (N == 1) ? 1.0 : N * (t * p1 - p0) / (t * t - 1.0);
+    x[i] = t;
+    wt[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+  std::vector<int> idx(N);
+  for (int i = 0; i < N; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return x[a] < x[b]; });
+  std::vector<double> xs(N), ws(N);
+  for (int i = 0; i < N; ++i) {
+    xs[i] = x[idx[i]];
+    ws[i] = wt[idx[i]];
+  }
+  x = xs;
+  wt = ws;
+}
+
+rafeast_status validate_params(const rafeast_params* p, int64_t n, std::string& msg) {
+  if (!(std::isfinite(p->lmin) && std::isfinite(p->lmax) && p->lmin < p->lmax)) {
+    msg = "need finite lmin < lmax";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->m0 < 1 || p->m0 > n) {
+    msg = "m0 must be in [1, n]";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->nc < 1 || p->nc > 64) {
+    msg = "nc must be in [1, 64]";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->q < 0 || p->q > 64) {
+    msg = "q must be in [0, 64]";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->p >= 0 && p->p < 4) {
+    msg = "oversampling p must be >= 4 (Assumption 1.5) or < 0 for the default rule";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (!(p->tol_eig > 0.0) || !(p->tol_solve > 0.0) || !(p->tol_solve < 1.0)) {
+    msg = "tolerances must satisfy tol_eig > 0 and 0 < tol_solve < 1";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->max_iter < 0 || p->max_cocg < 1) {
+    msg = "need max_iter >= 0 and max_cocg >= 1";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->precision != RAFEAST_FP64 && p->precision != RAFEAST_FP32_REFINED) {
+    msg = "unknown precision";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->ws_op < RAFEAST_WS_AUTO || p->ws_op > RAFEAST_WS_NONE) {
+    msg = "unknown ws_op";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->rhs_form != RAFEAST_RHS_RESIDUAL && p->rhs_form != RAFEAST_RHS_LITERAL) {
+    msg = "unknown rhs_form";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->engine < RAFEAST_ENGINE_AUTO || p->engine > RAFEAST_ENGINE_STREAM) {
+    msg = "unknown engine";
+    return RAFEAST_INVALID_ARG;
+  }
+  return RAFEAST_OK;
+}
+
+rafeast_status validate_csr(const rafeast_csr* A, int64_t& nnz, double& anorm, double& lo,
+                            double& hi, std::string& msg) {
+  if (A->n < 1 || A->n >= (int64_t(1) << 31)) {
+    msg = "n must be in [1, 2^31)";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (A->index_base != 0 && A->index_base != 1) {
+    msg = "index_base must be 0 or 1";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (!A->rowptr) {
+    msg = "rowptr is NULL";
+    return RAFEAST_INVALID_ARG;
+  }
+  const int64_t n = A->n;
+  const int base = A->index_base;
+  if (A->rowptr[0] != base) {
+    msg = "rowptr[0] != index_base";
+    return RAFEAST_BAD_CSR;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (A->rowptr[i + 1] < A->rowptr[i]) {
+      msg = "rowptr not monotone at row " + std::to_string(i);
+      return RAFEAST_BAD_CSR;
+    }
+  nnz = (int64_t)A->rowptr[n] - base;
+  if (nnz > 0 && (!A->colind || !A->values)) {
+    msg = "colind or values is NULL";
+    return RAFEAST_INVALID_ARG;
+  }
+  anorm = 0.0;
+  lo = INFINITY;
+  hi = -INFINITY;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t s = A->rowptr[i] - base, e = A->rowptr[i + 1] - base;
+    double rs = 0.0, d = 0.0, off = 0.0;
+    int64_t prev = -1;
+    for (int64_t t = s; t < e; ++t) {
+      const int64_t j = (int64_t)A->colind[t] - base;
+      const double v = A->values[t];
+      if (j < 0 || j >= n) {
+        msg = "column out of range in row " + std::to_string(i);
+        return RAFEAST_BAD_CSR;
+      }
+      if (j <= prev) {
+        msg = "columns not strictly increasing in row " + std::to_string(i);
+        return RAFEAST_BAD_CSR;
+      }
+      if (!std::isfinite(v)) {
+        msg = "non-finite value in row " + std::to_string(i);
+        return RAFEAST_BAD_CSR;
+      }
+      prev = j;
+      rs += std::fabs(v);
+      if (j == i)
+        d = v;
+      else
+        off += std::fabs(v);
+    }
+    anorm = std::max(anorm, rs);
+    lo = std::min(lo, d - off);
+    hi = std::max(hi, d + off);
+  }
+  const double stol = 1e-14 * anorm;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t s = A->rowptr[i] - base, e = A->rowptr[i + 1] - base;
+    for (int64_t t = s; t < e; ++t) {
+      const int64_t j = (int64_t)A->colind[t] - base;
+      if (j == i) continue;
+      const int64_t sj = A->rowptr[j] - base, ej = A->rowptr[j + 1] - base;
+      const int32_t* b = A->colind + sj;
+      const int32_t* f = std::lower_bound(b, A->colind + ej, (int32_t)(i + base));
+      if (f == A->colind + ej || *f != (int32_t)(i + base)) {
+        msg = "pattern not symmetric at (" + std::to_string(i) + "," + std::to_string(j) + ")";
+        return RAFEAST_NOT_SYMMETRIC;
+      }
+      const double aji = A->values[sj + (f - b)];
+      if (std::fabs(aji - A->values[t]) > stol) {
+        msg = "values not symmetric at (" + std::to_string(i) + "," + std::to_string(j) + ")";
+        return RAFEAST_NOT_SYMMETRIC;
+      }
+    }
+  }
+  return RAFEAST_OK;
+}
+
+template <typename T>
+rafeast_status dalloc(rafeast_plan_s* P, T** p, size_t count, const char* what) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(P, e, what);
+  }
+  return RAFEAST_OK;
+}
+
+void free_plan(rafeast_plan_s* P) {
+  if (!P) return;
+  void* ptrs[] = {P->d_rowptr, P->d_col,  P->d_val,   P->d_sbase, P->d_perm, P->d_e32,
+                  P->d_e64,   P->d_Q,    P->d_W,     P->d_R,     P->d_T,    P->d_Y,
+                  P->d_G,      P->d_M,    P->d_S,     P->d_Ssel,  P->d_jw,   P->d_theta,
+                  P->d_res,    P->d_qn,   P->d_gamma, P->d_info,  P->d_zw,   P->d_part,
+                  P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
+                  P->d_sel, P->d_xhi, P->d_xlo};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto& e : P->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (P->own_stream && P->st) (void)hipStreamDestroy(P->st);
+  delete P;
+}
+
+// ----------------------------------------------------------------------------
+// building blocks on the plan
+// ----------------------------------------------------------------------------
+rafeast_status spmm(rafeast_plan_s* P, int k, const double* X, int ldx, double* Y, int ldy,
+                    double alpha, double beta, const double* X2 = nullptr, int ldx2 = 0,
+                    double gamma = 0.0) {
+  HIPCHK(P, launch_spmm_f64(P->st, (int)P->n, k, P->d_rowptr, P->d_col, P->d_val, X, ldx, Y, ldy,
+                            alpha, beta, X2, ldx2, gamma));
+  return RAFEAST_OK;
+}
+
+// CholQR2 on Y (n x k, ld) in place through P->d_T; *info as in rafeast_cholqr2.
+rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, int* info,
+                       double* tmp, int ldt) {
+  int worst = 0;
+  int passes = 2;
+  for (int pass = 0; pass < passes; ++pass) {
+    HIPCHK(P, launch_gram(P->st, n, k, k, Y, ldy, Y, ldy, P->d_G, k, P->d_part));
+    HIPCHK(P, launch_chol_inv(P->st, k, n, P->d_G, k, P->d_M, k, P->d_flag));
+    int flag = 0;
+    HIPCHK(P, hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, P->st));
+    HIPCHK(P, hipStreamSynchronize(P->st));
+    if (flag == 2) {
+      if (info) *info = 2;
+      return RAFEAST_OK;  // Y keeps the last good pass
+    }
+    if (flag == 1 && pass == 0) passes = 3;
+    worst = std::max(worst, flag);
+    HIPCHK(P, launch_tsmm(P->st, n, k, k, Y, ldy, P->d_M, k, tmp, ldt));
+    HIPCHK(P, launch_copy_cols(P->st, n, k, tmp, ldt, Y, ldy));
+  }
+  if (info) *info = worst;
+  return RAFEAST_OK;
+}
+
+// Rayleigh-Ritz on Q (n x m0): theta, rotated Q and W = A Q, residual block R,
+// scaled residual norms; theta and res copied to the host arrays.
+rafeast_status rayleigh_ritz(rafeast_plan_s* P, std::vector<double>& theta,
+                             std::vector<double>& res) {
+  const int m0 = P->m0, ld = P->ld;
+  const int64_t n = P->n;
+  RCHK(spmm(P, m0, P->d_Q, ld, P->d_W, ld, 1.0, 0.0));
+  HIPCHK(P, launch_gram(P->st, n, m0, m0, P->d_Q, ld, P->d_W, ld, P->d_G, m0, P->d_part));
+  HIPCHK(P, launch_jacobi(P->st, m0, P->d_G, m0, P->d_theta, P->d_S, m0, P->d_jw));
+  HIPCHK(P, launch_tsmm(P->st, n, m0, m0, P->d_Q, ld, P->d_S, m0, P->d_T, ld));
+  std::swap(P->d_Q, P->d_T);
+  HIPCHK(P, launch_tsmm(P->st, n, m0, m0, P->d_W, ld, P->d_S, m0, P->d_T, ld));
+  std::swap(P->d_W, P->d_T);
+  const double s_win = std::max(std::fabs(P->prm.lmin), std::fabs(P->prm.lmax));
+  HIPCHK(P, launch_residual(P->st, n, m0, P->d_W, P->d_Q, ld, P->d_theta, s_win, P->d_R,
+                            P->d_res, P->d_qn, P->d_part));
+  theta.resize(m0);
+  res.resize(m0);
+  HIPCHK(P, hipMemcpyAsync(theta.data(), P->d_theta, m0 * sizeof(double), hipMemcpyDeviceToHost,
+                           P->st));
+  HIPCHK(P, hipMemcpyAsync(res.data(), P->d_res, m0 * sizeof(double), hipMemcpyDeviceToHost,
+                           P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  return RAFEAST_OK;
+}
+
+// COCG over items (j, i) of the given shift table; outputs into D.
+rafeast_status run_cocg(rafeast_plan_s* P, int nitems, const int* d_items, const double* d_zs,
+                        int k, const double* B, int ldb, void* D, int ldd, double tol,
+                        int* d_iters, double* d_resid = nullptr) {
+  CocgLaunch L;
+  L.nitems = nitems;
+  L.items = d_items;
+  L.zs = d_zs;
+  L.B = B;
+  L.ldb = ldb;
+  L.k = k;
+  L.D = D;
+  L.ldd = ldd;
+  L.tol = tol;
+  L.maxit = P->prm.max_cocg;
+  L.max_refine = 4;
+  L.counter = P->d_counter;
+  L.iters = d_iters;
+  L.stats = P->d_stats;
+  L.resid = d_resid;
+  L.xhi = P->d_xhi;
+  L.xlo = P->d_xlo;
+  L.xhi_slots = P->xhi_slots;
+  HIPCHK(P, hipMemsetAsync(P->d_counter, 0, sizeof(int), P->st));
+  HIPCHK(P, launch_cocg_resident(P->st, P->sell, L, P->fp32, P->num_cu));
+  return RAFEAST_OK;
+}
+
+// Orders (shift, column) pairs longest-first: the smaller Im z, the more COCG
+// iterations a system needs.
+std::vector<int> make_items(int nz, const double* zs, int k) {
+  std::vector<int> js(nz);
+  for (int j = 0; j < nz; ++j) js[j] = j;
+  std::stable_sort(js.begin(), js.end(),
+                   [&](int a, int b) { return std::fabs(zs[2 * a + 1]) < std::fabs(zs[2 * b + 1]); });
+  std::vector<int> items;
+  items.reserve(2 * nz * k);
+  for (int j : js)
+    for (int i = 0; i < k; ++i) {
+      items.push_back(j);
+      items.push_back(i);
+    }
+  return items;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0f;
+  return ms;
+}
+
+int resolve_ws_op(const rafeast_plan_s* P) {
+  const int op = P->prm.ws_op;
+  if (op != RAFEAST_WS_AUTO) return op;
+  if (P->prm.lmin <= P->sig_lo) return RAFEAST_WS_FLIP;
+  if (P->prm.lmax >= P->sig_hi) return RAFEAST_WS_LITERAL;
+  return RAFEAST_WS_FOLD;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+void rafeast_params_default(rafeast_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->lmin = 0.0;
+  p->lmax = 0.0;
+  p->m0 = 0;
+  p->nc = 8;
+  p->q = 2;
+  p->p = -1;
+  p->tol_eig = 1e-10;
+  p->tol_solve = 1e-6;
+  p->max_iter = 20;
+  p->max_cocg = 20000;
+  p->precision = RAFEAST_FP32_REFINED;
+  p->ws_op = RAFEAST_WS_AUTO;
+  p->rhs_form = RAFEAST_RHS_RESIDUAL;
+  p->engine = RAFEAST_ENGINE_AUTO;
+  p->seed = 0;
+  p->hip_stream = nullptr;
+}
+
+const char* rafeast_status_string(rafeast_status s) {
+  switch (s) {
+    case RAFEAST_OK: return "OK";
+    case RAFEAST_INVALID_ARG: return "INVALID_ARG";
+    case RAFEAST_BAD_CSR: return "BAD_CSR";
+    case RAFEAST_NOT_SYMMETRIC: return "NOT_SYMMETRIC";
+    case RAFEAST_OOM: return "OOM";
+    case RAFEAST_DEVICE: return "DEVICE";
+    case RAFEAST_NO_CONVERGENCE: return "NO_CONVERGENCE";
+    case RAFEAST_SUBSPACE_TOO_SMALL: return "SUBSPACE_TOO_SMALL";
+    case RAFEAST_BREAKDOWN: return "BREAKDOWN";
+    case RAFEAST_EMPTY_WINDOW: return "EMPTY_WINDOW";
+    case RAFEAST_UNSUPPORTED: return "UNSUPPORTED";
+  }
+  return "UNKNOWN";
+}
+
+const char* rafeast_last_error(rafeast_plan_t plan) {
+  return plan ? plan->err.c_str() : g_plan_error.c_str();
+}
+
+void rafeast_destroy(rafeast_plan_t plan) { free_plan(plan); }
+
+rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
+                            rafeast_plan_t* out) {
+  g_plan_error.clear();
+  if (!out) return fail(nullptr, RAFEAST_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!A || !prm) return fail(nullptr, RAFEAST_INVALID_ARG, "A or prm is NULL");
+  std::string msg;
+  int64_t nnz = 0;
+  double anorm = 0, lo = 0, hi = 0;
+  rafeast_status s = validate_csr(A, nnz, anorm, lo, hi, msg);
+  if (s != RAFEAST_OK) return fail(nullptr, s, msg);
+  s = validate_params(prm, A->n, msg);
+  if (s != RAFEAST_OK) return fail(nullptr, s, msg);
+  const int64_t n = A->n;
+  int pov = prm->p;
+  if (pov < 0) pov = prm->m0 <= 50 ? 10 : std::min(20, (prm->m0 + 1) / 2);
+  int w = (int)std::min<int64_t>((int64_t)prm->m0 + pov, n);
+  if (w > kMaxSmallK)
+    return fail(nullptr, RAFEAST_UNSUPPORTED,
+                "m0 + p = " + std::to_string(w) + " exceeds the small-matrix limit 192");
+  const bool fp32 = prm->precision == RAFEAST_FP32_REFINED;
+  int engine = prm->engine;
+  if (engine == RAFEAST_ENGINE_AUTO) engine = RAFEAST_ENGINE_RESIDENT;
+  if (engine == RAFEAST_ENGINE_STREAM)
+    return fail(nullptr, RAFEAST_UNSUPPORTED, "streaming COCG engine not available");
+  if (n > cocg_resident_max_n(fp32))
+    return fail(nullptr, RAFEAST_UNSUPPORTED,
+                "n too large for the resident COCG engine at this precision");
+  if ((int64_t)prm->nc * prm->m0 > (int64_t)1 << 20)
+    return fail(nullptr, RAFEAST_UNSUPPORTED, "nc * m0 too large");
+
+  int ndev = 0;
+  hipError_t he = hipGetDeviceCount(&ndev);
+  if (he != hipSuccess || ndev < 1)
+    return fail(nullptr, RAFEAST_DEVICE, "no HIP device available");
+
+  rafeast_plan_s* P = new rafeast_plan_s();
+  P->prm = *prm;
+  P->n = n;
+  P->nnz = nnz;
+  P->m0 = prm->m0;
+  P->pov = pov;
+  P->w = w;
+  P->nc = prm->nc;
+  P->sig_lo = lo;
+  P->sig_hi = hi;
+  P->anorm = anorm;
+  P->fp32 = fp32;
+  P->engine = engine;
+  P->ld = w;
+
+  auto bail = [&](rafeast_status st) {
+    g_plan_error = P->err;
+    free_plan(P);
+    return st;
+  };
+#define PCHK(expr)                                    \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return bail(hip_fail(P, _e, #expr)); \
+  } while (0)
+#define PRCHK(expr)                       \
+  do {                                    \
+    rafeast_status _s = (expr);           \
+    if (_s != RAFEAST_OK) return bail(_s); \
+  } while (0)
+
+  PCHK(hipGetDevice(&P->dev));
+  hipDeviceProp_t props;
+  PCHK(hipGetDeviceProperties(&props, P->dev));
+  P->num_cu = props.multiProcessorCount;
+  if (prm->hip_stream) {
+    P->st = (hipStream_t)prm->hip_stream;
+  } else {
+    PCHK(hipStreamCreateWithFlags(&P->st, hipStreamNonBlocking));
+    P->own_stream = true;
+  }
+  for (auto& e : P->ev) PCHK(hipEventCreate(&e));
+
+  // quadrature table (eq. projector-quad, upper half circle)
+  {
+    std::vector<double> x, om;
+    gauss_legendre_newton(P->nc, x, om);
+    const double c = 0.5 * (prm->lmin + prm->lmax), r = 0.5 * (prm->lmax - prm->lmin);
+    P->zw.assign(4 * P->nc, 0.0);
+    for (int j = 0; j < P->nc; ++j) {
+      const double ph = 0.5 * M_PI * (1.0 - x[j]);
+      const double er = std::cos(ph), ei = std::sin(ph);
+      P->zw[2 * j] = c + r * er;
+      P->zw[2 * j + 1] = r * ei;
+      P->zw[2 * P->nc + 2 * j] = 0.5 * om[j] * r * er;
+      P->zw[2 * P->nc + 2 * j + 1] = 0.5 * om[j] * r * ei;
+    }
+  }
+
+  // CSR (FP64) and SELL-64 copies of A
+  const int base = A->index_base;
+  {
+    std::vector<int> rp(n + 1), cl(nnz);
+    for (int64_t i = 0; i <= n; ++i) rp[i] = A->rowptr[i] - base;
+    for (int64_t t = 0; t < nnz; ++t) cl[t] = A->colind[t] - base;
+    PRCHK(dalloc(P, &P->d_rowptr, n + 1, "rowptr"));
+    PRCHK(dalloc(P, &P->d_col, nnz, "colind"));
+    PRCHK(dalloc(P, &P->d_val, nnz, "values"));
+    PCHK(hipMemcpy(P->d_rowptr, rp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+    if (nnz) {
+      PCHK(hipMemcpy(P->d_col, cl.data(), nnz * sizeof(int), hipMemcpyHostToDevice));
+      PCHK(hipMemcpy(P->d_val, A->values, nnz * sizeof(double), hipMemcpyHostToDevice));
+    }
+    // SELL-64 of the resident engine: rows sorted by decreasing length (ties
+    // by index), slices of 64 slots, widths padded to a multiple of 4
+    const int nsl = (int)((n + 63) / 64);
+    std::vector<int> order(n), slot_of(n);
+    for (int64_t i = 0; i < n; ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return (rp[a + 1] - rp[a]) > (rp[b + 1] - rp[b]);
+    });
+    for (int64_t sl = 0; sl < n; ++sl) slot_of[order[sl]] = (int)sl;
+    std::vector<int> perm((size_t)nsl * 64, -1);
+    for (int64_t sl = 0; sl < n; ++sl) perm[sl] = order[sl];
+    std::vector<int> sb(nsl + 1, 0);
+    for (int s = 0; s < nsl; ++s) {
+      int wd = 0;
+      for (int l = 0; l < 64; ++l) {
+        const int64_t sl = (int64_t)s * 64 + l;
+        if (sl < n) wd = std::max(wd, rp[order[sl] + 1] - rp[order[sl]]);
+      }
+      wd = (wd + 3) & ~3;
+      sb[s + 1] = sb[s] + wd * 64;
+    }
+    const size_t tot = (size_t)sb[nsl] + 256;  // + a block of zero entries
+    std::vector<SellEntry32> e32(tot, SellEntry32{0, 0.0f});
+    std::vector<SellEntry64> e64(tot, SellEntry64{0, 0, 0.0});
+    for (int s = 0; s < nsl; ++s) {
+      const int wd = (sb[s + 1] - sb[s]) / 64;
+      for (int kk = 0; kk < wd; ++kk)
+        for (int l = 0; l < 64; ++l) {
+          const int64_t sl = (int64_t)s * 64 + l;
+          const size_t e = (size_t)sb[s] + (size_t)kk * 64 + l;
+          const int row = sl < n ? order[sl] : -1;
+          if (row >= 0 && kk < rp[row + 1] - rp[row]) {
+            const int t = rp[row] + kk;
+            e32[e] = SellEntry32{slot_of[cl[t]] * 8, (float)A->values[t]};
+            e64[e] = SellEntry64{slot_of[cl[t]] * 16, 0, A->values[t]};
+          } else {
+            e32[e] = SellEntry32{(int)sl * 8, 0.0f};  // padding: own slot, zero value
+            e64[e] = SellEntry64{(int)sl * 16, 0, 0.0};
+          }
+        }
+    }
+    PRCHK(dalloc(P, &P->d_sbase, nsl + 1, "sell base"));
+    PRCHK(dalloc(P, &P->d_perm, (size_t)nsl * 64, "sell perm"));
+    PRCHK(dalloc(P, &P->d_e32, tot, "sell e32"));
+    PRCHK(dalloc(P, &P->d_e64, tot, "sell e64"));
+    PCHK(hipMemcpy(P->d_sbase, sb.data(), (nsl + 1) * sizeof(int), hipMemcpyHostToDevice));
+    PCHK(hipMemcpy(P->d_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (tot) {
+      PCHK(hipMemcpy(P->d_e32, e32.data(), tot * sizeof(SellEntry32), hipMemcpyHostToDevice));
+      PCHK(hipMemcpy(P->d_e64, e64.data(), tot * sizeof(SellEntry64), hipMemcpyHostToDevice));
+    }
+    P->sell.n = (int)n;
+    P->sell.nslices = nsl;
+    P->sell.sbase = P->d_sbase;
+    P->sell.perm = P->d_perm;
+    P->sell.e32 = P->d_e32;
+    P->sell.e64 = P->d_e64;
+    P->sell.zero_base = sb[nsl];
+    P->sell_entries = tot;
+  }
+
+  // workspace
+  const size_t blk = (size_t)n * w;
+  PRCHK(dalloc(P, &P->d_Q, blk, "Q"));
+  PRCHK(dalloc(P, &P->d_W, blk, "W"));
+  PRCHK(dalloc(P, &P->d_R, blk, "R"));
+  PRCHK(dalloc(P, &P->d_T, blk, "T"));
+  PRCHK(dalloc(P, &P->d_Y, blk, "Y"));
+  const size_t kk2 = (size_t)kMaxSmallK * kMaxSmallK;
+  PRCHK(dalloc(P, &P->d_G, kk2, "G"));
+  PRCHK(dalloc(P, &P->d_M, kk2, "M"));
+  PRCHK(dalloc(P, &P->d_S, kk2, "S"));
+  PRCHK(dalloc(P, &P->d_Ssel, (size_t)kMaxSmallK * P->m0, "Ssel"));
+  PRCHK(dalloc(P, &P->d_jw, 2 * kk2, "jacobi work"));
+  PRCHK(dalloc(P, &P->d_theta, kMaxSmallK, "theta"));
+  PRCHK(dalloc(P, &P->d_res, kMaxSmallK, "res"));
+  PRCHK(dalloc(P, &P->d_qn, kMaxSmallK, "qn"));
+  PRCHK(dalloc(P, &P->d_gamma, 2 * (size_t)P->nc * P->m0, "gamma"));
+  PRCHK(dalloc(P, &P->d_info, 4, "info"));
+  PRCHK(dalloc(P, &P->d_zw, 4 * P->nc, "zw"));
+  P->part_doubles = std::max(gram_partial_doubles(n, w, w), (size_t)2 * w * gram_chunks(n));
+  PRCHK(dalloc(P, &P->d_part, P->part_doubles, "partials"));
+  const size_t cs = fp32 ? 2 * sizeof(float) : 2 * sizeof(double);
+  {
+    hipError_t e = hipMalloc(&P->d_D, (size_t)n * P->nc * P->m0 * cs);
+    if (e != hipSuccess) return bail(hip_fail(P, e, "solve block"));
+  }
+  P->nitems = P->nc * P->m0;
+  PRCHK(dalloc(P, &P->d_items, 2 * (size_t)P->nitems, "items"));
+  PRCHK(dalloc(P, &P->d_counter, 1, "counter"));
+  PRCHK(dalloc(P, &P->d_iters, (size_t)P->nitems, "iters"));
+  PRCHK(dalloc(P, &P->d_stats, 2, "stats"));
+  PRCHK(dalloc(P, &P->d_flag, 1, "flag"));
+  PRCHK(dalloc(P, &P->d_sel, P->m0, "sel"));
+  P->xhi_slots = cocg_resident_xhi_slots((int)n, P->num_cu);
+  {
+    hipError_t e = hipMalloc(&P->d_xhi, P->xhi_slots * 2 * sizeof(double));
+    if (e != hipSuccess) return bail(hip_fail(P, e, "solution scratch"));
+    e = hipMalloc(&P->d_xlo, P->xhi_slots * 2 * (fp32 ? sizeof(float) : sizeof(double)));
+    if (e != hipSuccess) return bail(hip_fail(P, e, "iterate scratch"));
+  }
+  PCHK(hipMemcpy(P->d_zw, P->zw.data(), 4 * P->nc * sizeof(double), hipMemcpyHostToDevice));
+  {
+    std::vector<int> items = make_items(P->nc, P->zw.data(), P->m0);
+    PCHK(hipMemcpy(P->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  PCHK(hipMemset(P->d_stats, 0, 2 * sizeof(int)));
+  PCHK(hipDeviceSynchronize());
+#undef PCHK
+#undef PRCHK
+  *out = P;
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_plan_info(rafeast_plan_t P, double* sig_lo, double* sig_hi,
+                                 double* anorm_inf, int64_t* nnz, double* z, double* w) {
+  if (!P) return RAFEAST_INVALID_ARG;
+  if (sig_lo) *sig_lo = P->sig_lo;
+  if (sig_hi) *sig_hi = P->sig_hi;
+  if (anorm_inf) *anorm_inf = P->anorm;
+  if (nnz) *nnz = P->nnz;
+  if (z) std::memcpy(z, P->zw.data(), 2 * P->nc * sizeof(double));
+  if (w) std::memcpy(w, P->zw.data() + 2 * P->nc, 2 * P->nc * sizeof(double));
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_warmstart(rafeast_plan_t P, const double* omega, double* Q0,
+                                 rafeast_ws_info* info) {
+  if (!P) return RAFEAST_INVALID_ARG;
+  P->err.clear();
+  const int64_t n = P->n;
+  const int m0 = P->m0, w = P->w, ld = P->ld;
+  HIPCHK(P, hipEventRecord(P->ev[0], P->st));
+  if (omega) {
+    HIPCHK(P, hipMemcpyAsync(P->d_T, omega, (size_t)n * w * sizeof(double), hipMemcpyHostToDevice,
+                             P->st));
+    HIPCHK(P, launch_colmajor_to_rowmajor(P->st, n, w, P->d_T, P->d_Y, ld));
+  } else {
+    HIPCHK(P, launch_gaussian(P->st, n, w, P->prm.seed, P->d_Y, ld));
+  }
+  const int op = resolve_ws_op(P);
+  double bm0 = NAN, bm1 = NAN;
+  if (op == RAFEAST_WS_NONE) {
+    HIPCHK(P, launch_copy_cols(P->st, n, m0, P->d_Y, ld, P->d_Q, ld));
+    int ci = 0;
+    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
+    if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "orthonormalisation of the sketch failed");
+  } else {
+    const double lmin = P->prm.lmin, lmax = P->prm.lmax;
+    const double c0 = 0.5 * (lmin + lmax);
+    const double Rr = std::max(c0 - P->sig_lo, P->sig_hi - c0);
+    double pa = 0, pb = 0, pc = 0;  // phi(t) = pa + pb t + pc t^2
+    for (int t = 0; t < 2 * P->prm.q + 1; ++t) {
+      if (op == RAFEAST_WS_LITERAL) {
+        const double s = 1.0 / (lmax - lmin);
+        RCHK(spmm(P, w, P->d_Y, ld, P->d_W, ld, s, -s * lmin));
+      } else if (op == RAFEAST_WS_FLIP) {
+        const double s = 1.0 / (P->sig_hi - lmin);
+        RCHK(spmm(P, w, P->d_Y, ld, P->d_W, ld, -s, s * P->sig_hi));
+      } else {
+        RCHK(spmm(P, w, P->d_Y, ld, P->d_T, ld, 1.0 / Rr, -c0 / Rr));
+        RCHK(spmm(P, w, P->d_T, ld, P->d_W, ld, -1.0 / Rr, c0 / Rr, P->d_Y, ld, 1.0));
+      }
+      int ci = 0;
+      RCHK(cholqr2(P, n, w, P->d_W, ld, &ci, P->d_T, ld));
+      if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "orthonormalisation in Phase 1 failed");
+      std::swap(P->d_Y, P->d_W);
+    }
+    if (op == RAFEAST_WS_LITERAL) {
+      const double s = 1.0 / (lmax - lmin);
+      pa = -s * lmin;
+      pb = s;
+    } else if (op == RAFEAST_WS_FLIP) {
+      const double s = 1.0 / (P->sig_hi - lmin);
+      pa = s * P->sig_hi;
+      pb = -s;
+    } else {
+      pa = 1.0 - c0 * c0 / (Rr * Rr);
+      pb = 2.0 * c0 / (Rr * Rr);
+      pc = -1.0 / (Rr * Rr);
+    }
+    // Rayleigh-Ritz truncation to m0 vectors
+    RCHK(spmm(P, w, P->d_Y, ld, P->d_W, ld, 1.0, 0.0));
+    HIPCHK(P, launch_gram(P->st, n, w, w, P->d_Y, ld, P->d_W, ld, P->d_G, w, P->d_part));
+    HIPCHK(P, launch_jacobi(P->st, w, P->d_G, w, P->d_theta, P->d_S, w, P->d_jw));
+    HIPCHK(P, launch_select(P->st, w, m0, P->d_theta, P->d_S, w, pa, pb, pc, P->d_Ssel,
+                            P->d_info));
+    HIPCHK(P, launch_tsmm(P->st, n, w, m0, P->d_Y, ld, P->d_Ssel, m0, P->d_Q, ld));
+    double hinfo[2];
+    HIPCHK(P, hipMemcpyAsync(hinfo, P->d_info, 2 * sizeof(double), hipMemcpyDeviceToHost, P->st));
+    HIPCHK(P, hipStreamSynchronize(P->st));
+    bm0 = hinfo[0];
+    bm1 = hinfo[1];
+  }
+  HIPCHK(P, hipEventRecord(P->ev[1], P->st));
+  HIPCHK(P, hipEventSynchronize(P->ev[1]));
+  P->have_start = true;
+  P->ws_used = op;
+  if (Q0) {
+    HIPCHK(P, launch_rowmajor_to_colmajor(P->st, n, m0, P->d_Q, ld, P->d_T));
+    HIPCHK(P, hipMemcpyAsync(Q0, P->d_T, (size_t)n * m0 * sizeof(double), hipMemcpyDeviceToHost,
+                             P->st));
+    HIPCHK(P, hipStreamSynchronize(P->st));
+  }
+  if (info) {
+    info->beta_m0 = bm0;
+    info->beta_m0p1 = bm1;
+    info->ratio = std::pow(bm1 / bm0, 2.0 * P->prm.q + 1.0);
+    info->op = op;
+    info->t_ms = elapsed(P->ev[0], P->ev[1]);
+  }
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_result* res) {
+  if (!P || !res || !res->lambda || !res->resid) return RAFEAST_INVALID_ARG;
+  P->err.clear();
+  const int64_t n = P->n;
+  const int m0 = P->m0, ld = P->ld, nc = P->nc;
+  const double lmin = P->prm.lmin, lmax = P->prm.lmax;
+  double t_ph[RAFEAST_NPHASE] = {0, 0, 0, 0, 0};
+  HIPCHK(P, hipEventRecord(P->ev[6], P->st));
+  if (Q_init) {
+    HIPCHK(P, hipMemcpyAsync(P->d_T, Q_init, (size_t)n * m0 * sizeof(double),
+                             hipMemcpyHostToDevice, P->st));
+    HIPCHK(P, launch_colmajor_to_rowmajor(P->st, n, m0, P->d_T, P->d_Q, ld));
+    int ci = 0;
+    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
+    if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "Q_init is rank deficient");
+  } else if (!P->have_start) {
+    HIPCHK(P, launch_gaussian(P->st, n, m0, P->prm.seed, P->d_Q, ld));
+    int ci = 0;
+    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
+    if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "random start is rank deficient");
+  }
+  HIPCHK(P, hipMemsetAsync(P->d_stats, 0, 2 * sizeof(int), P->st));
+  std::vector<double> theta, rs;
+  std::vector<int> iters(P->nitems);
+  rafeast_status status = RAFEAST_NO_CONVERGENCE;
+  int it = 0, M = 0;
+  double maxres = 0.0;
+  int64_t cocg_sum = 0;
+  int cocg_max = 0;
+  bool breakdown = false;
+  const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
+  for (;; ++it) {
+    HIPCHK(P, hipEventRecord(P->ev[0], P->st));
+    RCHK(rayleigh_ritz(P, theta, rs));
+    HIPCHK(P, hipEventRecord(P->ev[1], P->st));
+    M = 0;
+    maxres = 0.0;
+    for (int i = 0; i < m0; ++i)
+      if (theta[i] >= lmin && theta[i] <= lmax) {
+        ++M;
+        maxres = std::max(maxres, rs[i]);
+      }
+    if (M > 0 && maxres <= P->prm.tol_eig) {
+      status = RAFEAST_OK;
+      break;
+    }
+    if (M == 0 && it >= 2) {
+      status = RAFEAST_EMPTY_WINDOW;
+      break;
+    }
+    if (it >= P->prm.max_iter) break;
+    // shifted solves for all (node, column) pairs
+    HIPCHK(P, hipEventRecord(P->ev[2], P->st));
+    RCHK(run_cocg(P, P->nitems, P->d_items, P->d_zw, m0, residual_form ? P->d_R : P->d_Q, ld,
+                  P->d_D, nc * m0, P->prm.tol_solve, P->d_iters));
+    HIPCHK(P, hipEventRecord(P->ev[3], P->st));
+    HIPCHK(P, hipMemcpyAsync(iters.data(), P->d_iters, P->nitems * sizeof(int),
+                             hipMemcpyDeviceToHost, P->st));
+    // combination Q~ = sum_j Re[w_j (z_j I - A)^{-1} Q]
+    HIPCHK(P, launch_gamma(P->st, nc, m0, P->d_zw, P->d_theta, P->d_gamma));
+    HIPCHK(P, launch_combine(P->st, n, nc, m0, P->d_gamma, P->d_zw, residual_form, P->d_Q, ld,
+                             P->d_D, nc * m0, P->fp32, P->d_Y, ld));
+    HIPCHK(P, hipEventRecord(P->ev[4], P->st));
+    std::swap(P->d_Q, P->d_Y);
+    int ci = 0;
+    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
+    HIPCHK(P, hipEventRecord(P->ev[5], P->st));
+    HIPCHK(P, hipEventSynchronize(P->ev[5]));
+    if (ci == 2) breakdown = true;
+    t_ph[RAFEAST_PH_RR] += elapsed(P->ev[0], P->ev[1]);
+    t_ph[RAFEAST_PH_SOLVE] += elapsed(P->ev[2], P->ev[3]);
+    t_ph[RAFEAST_PH_COMBINE] += elapsed(P->ev[3], P->ev[4]);
+    t_ph[RAFEAST_PH_ORTH] += elapsed(P->ev[4], P->ev[5]);
+    for (int v : iters) {
+      cocg_sum += v;
+      cocg_max = std::max(cocg_max, v);
+    }
+  }
+  HIPCHK(P, hipEventSynchronize(P->ev[1]));
+  t_ph[RAFEAST_PH_RR] += elapsed(P->ev[0], P->ev[1]);
+  if (status == RAFEAST_OK && M >= m0) status = RAFEAST_SUBSPACE_TOO_SMALL;
+  if (breakdown && status != RAFEAST_OK) status = RAFEAST_BREAKDOWN;
+
+  // outputs: in-window pairs, ascending (theta is sorted)
+  std::vector<int> sel;
+  for (int i = 0; i < m0; ++i)
+    if (theta[i] >= lmin && theta[i] <= lmax) sel.push_back(i);
+  std::vector<double> lam(sel.size()), rsel(sel.size());
+  for (size_t a = 0; a < sel.size(); ++a) {
+    lam[a] = theta[sel[a]];
+    rsel[a] = rs[sel[a]];
+  }
+  const bool dev_out = (res->flags & RAFEAST_PTR_DEVICE) != 0;
+  if (!sel.empty()) {
+    if (dev_out) {
+      HIPCHK(P, hipMemcpyAsync(res->lambda, lam.data(), lam.size() * sizeof(double),
+                               hipMemcpyHostToDevice, P->st));
+      HIPCHK(P, hipMemcpyAsync(res->resid, rsel.data(), rsel.size() * sizeof(double),
+                               hipMemcpyHostToDevice, P->st));
+    } else {
+      std::memcpy(res->lambda, lam.data(), lam.size() * sizeof(double));
+      std::memcpy(res->resid, rsel.data(), rsel.size() * sizeof(double));
+    }
+  }
+  if (res->X && !sel.empty()) {
+    HIPCHK(P, hipMemcpyAsync(P->d_sel, sel.data(), sel.size() * sizeof(int), hipMemcpyHostToDevice,
+                             P->st));
+    double* dst = dev_out ? res->X : P->d_T;
+    HIPCHK(P, launch_export_vectors(P->st, n, (int)sel.size(), P->d_sel, P->d_Q, ld, dst, nullptr));
+    if (!dev_out)
+      HIPCHK(P, hipMemcpyAsync(res->X, P->d_T, (size_t)n * sel.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, P->st));
+  }
+  int stats[2] = {0, 0};
+  HIPCHK(P, hipMemcpyAsync(stats, P->d_stats, 2 * sizeof(int), hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipEventRecord(P->ev[7], P->st));
+  HIPCHK(P, hipEventSynchronize(P->ev[7]));
+  t_ph[RAFEAST_PH_TOTAL] = elapsed(P->ev[6], P->ev[7]);
+  P->have_start = false;  // the next solve without Q_init starts afresh
+  res->M = M;
+  res->iters = it;
+  res->cocg_iters = cocg_sum;
+  res->cocg_max = cocg_max;
+  res->refinements = stats[0];
+  res->max_resid = maxres;
+  for (int i = 0; i < RAFEAST_NPHASE; ++i) res->t_ms[i] = t_ph[i];
+  if (stats[1] > 0 && status != RAFEAST_OK)
+    P->err = std::to_string(stats[1]) + " COCG systems broke down";
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// step-level calls
+// ---------------------------------------------------------------------------
+rafeast_status rafeast_spmm(rafeast_plan_t P, int32_t k, const double* X, int32_t ldx, double* Y,
+                            int32_t ldy, double alpha, double beta) {
+  if (!P || !X || !Y || k < 1 || ldx < k || ldy < k || X == Y) return RAFEAST_INVALID_ARG;
+  RCHK(spmm(P, k, X, ldx, Y, ldy, alpha, beta));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_gram(rafeast_plan_t P, int64_t n, int32_t k1, int32_t k2, const double* X,
+                            int32_t ldx, const double* Y, int32_t ldy, double* G, int32_t ldg) {
+  if (!P || !X || !Y || !G || n < 1 || k1 < 1 || k2 < 1 || ldx < k1 || ldy < k2 || ldg < k2)
+    return RAFEAST_INVALID_ARG;
+  double* part = nullptr;
+  HIPCHK(P, hipMalloc(&part, gram_partial_doubles(n, k1, k2) * sizeof(double)));
+  hipError_t e = launch_gram(P->st, n, k1, k2, X, ldx, Y, ldy, G, ldg, part);
+  if (e == hipSuccess) e = hipStreamSynchronize(P->st);
+  (void)hipFree(part);
+  HIPCHK(P, e);
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_cholqr2(rafeast_plan_t P, int64_t n, int32_t k, double* Y, int32_t ldy,
+                               int32_t* info) {
+  if (!P || !Y || n < 1 || k < 1 || k > kMaxSmallK || ldy < k || k > n) return RAFEAST_INVALID_ARG;
+  double* tmp = nullptr;
+  double* part = nullptr;
+  hipError_t e = hipMalloc(&tmp, (size_t)n * k * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&part, gram_partial_doubles(n, k, k) * sizeof(double));
+  rafeast_status s = RAFEAST_OK;
+  int ci = 0;
+  if (e != hipSuccess) {
+    s = hip_fail(P, e, "cholqr2 workspace");
+  } else {
+    double* keep = P->d_part;
+    P->d_part = part;
+    s = cholqr2(P, n, k, Y, ldy, &ci, tmp, k);
+    P->d_part = keep;
+    if (s == RAFEAST_OK) {
+      e = hipStreamSynchronize(P->st);
+      if (e != hipSuccess) s = hip_fail(P, e, "cholqr2");
+    }
+  }
+  if (tmp) (void)hipFree(tmp);
+  if (part) (void)hipFree(part);
+  if (info) *info = ci;
+  return s;
+}
+
+rafeast_status rafeast_syev(rafeast_plan_t P, int32_t k, const double* H, double* theta,
+                            double* S) {
+  if (!P || !H || !theta || !S || k < 1 || k > kMaxSmallK) return RAFEAST_INVALID_ARG;
+  HIPCHK(P, launch_jacobi(P->st, k, H, k, theta, S, k, P->d_jw));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_shifted_solve(rafeast_plan_t P, int32_t nz, const double* z, int32_t k,
+                                     const double* B, int32_t ldb, void* X, double tol,
+                                     int32_t* iters, double* resid) {
+  if (!P || !z || !B || !X || nz < 1 || k < 1 || ldb < k || !(tol > 0.0) || !(tol < 1.0))
+    return RAFEAST_INVALID_ARG;
+  double* d_z = nullptr;
+  int* d_items = nullptr;
+  int* d_it = nullptr;
+  double* d_rs = nullptr;
+  std::vector<int> items = make_items(nz, z, k);
+  const int nitems = nz * k;
+  rafeast_status s = RAFEAST_OK;
+  hipError_t e = hipMalloc(&d_z, 2 * nz * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&d_items, items.size() * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&d_it, nitems * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&d_rs, nitems * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_z, z, 2 * nz * sizeof(double), hipMemcpyHostToDevice, P->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice,
+                       P->st);
+  if (e != hipSuccess) {
+    s = hip_fail(P, e, "shifted_solve setup");
+  } else {
+    s = run_cocg(P, nitems, d_items, d_z, k, B, ldb, X, nz * k, tol, d_it, d_rs);
+    if (s == RAFEAST_OK && iters) {
+      e = hipMemcpyAsync(iters, d_it, nitems * sizeof(int), hipMemcpyDeviceToHost, P->st);
+      if (e != hipSuccess) s = hip_fail(P, e, "copy iterations");
+    }
+    if (s == RAFEAST_OK && resid) {
+      e = hipMemcpyAsync(resid, d_rs, nitems * sizeof(double), hipMemcpyDeviceToHost, P->st);
+      if (e != hipSuccess) s = hip_fail(P, e, "copy residuals");
+    }
+    if (s == RAFEAST_OK) {
+      e = hipStreamSynchronize(P->st);
+      if (e != hipSuccess) s = hip_fail(P, e, "shifted_solve");
+    }
+  }
+  if (d_z) (void)hipFree(d_z);
+  if (d_items) (void)hipFree(d_items);
+  if (d_it) (void)hipFree(d_it);
+  if (d_rs) (void)hipFree(d_rs);
+  return s;
+}
+
+rafeast_status rafeast_gaussian(rafeast_plan_t P, int32_t w, uint64_t seed, double* Omega,
+                                int32_t ld) {
+  if (!P || !Omega || w < 1 || ld < w) return RAFEAST_INVALID_ARG;
+  HIPCHK(P, launch_gaussian(P->st, P->n, w, seed, Omega, ld));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  return RAFEAST_OK;
+}
+
+}  // extern "C"

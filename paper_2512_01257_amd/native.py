@@ -1,0 +1,335 @@
+"""ctypes binding of librafeast.so (include/rafeast.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Importing this module does not touch the GPU; the library is loaded
+on first use and a missing library raises immediately (there is no fallback).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librafeast.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "rafeast.h")
+
+STATUS = {
+    0: "OK", 1: "INVALID_ARG", 2: "BAD_CSR", 3: "NOT_SYMMETRIC", 4: "OOM", 5: "DEVICE",
+    6: "NO_CONVERGENCE", 7: "SUBSPACE_TOO_SMALL", 8: "BREAKDOWN", 9: "EMPTY_WINDOW",
+    10: "UNSUPPORTED",
+}
+# statuses that still come with results
+RESULT_STATUSES = {0, 6, 7, 8, 9}
+
+PRECISION = {"fp64": 0, "fp32": 1}
+WS_OP = {"auto": 0, "literal": 1, "flip": 2, "fold": 3, "none": 4}
+RHS_FORM = {"residual": 0, "literal": 1}
+ENGINE = {"auto": 0, "resident": 1, "stream": 2}
+NPHASE = 5
+PHASES = ("rr", "solve", "combine", "orth", "total")
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("rowptr", C.POINTER(C.c_int32)),
+                ("colind", C.POINTER(C.c_int32)), ("values", C.POINTER(C.c_double)),
+                ("index_base", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("lmin", C.c_double), ("lmax", C.c_double), ("m0", C.c_int32),
+                ("nc", C.c_int32), ("q", C.c_int32), ("p", C.c_int32),
+                ("tol_eig", C.c_double), ("tol_solve", C.c_double), ("max_iter", C.c_int32),
+                ("max_cocg", C.c_int32), ("precision", C.c_int32), ("ws_op", C.c_int32),
+                ("rhs_form", C.c_int32), ("engine", C.c_int32), ("seed", C.c_uint64),
+                ("hip_stream", C.c_void_p)]
+
+
+class WsInfo(C.Structure):
+    _fields_ = [("beta_m0", C.c_double), ("beta_m0p1", C.c_double), ("ratio", C.c_double),
+                ("op", C.c_int32), ("t_ms", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("flags", C.c_int32), ("lam", C.c_void_p), ("resid", C.c_void_p),
+                ("X", C.c_void_p), ("M", C.c_int32), ("iters", C.c_int32),
+                ("cocg_iters", C.c_int64), ("cocg_max", C.c_int32), ("refinements", C.c_int32),
+                ("max_resid", C.c_double), ("t_ms", C.c_double * NPHASE)]
+
+
+_lib = None
+
+
+class RafeastError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {msg}")
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    L.rafeast_params_default.argtypes = [C.POINTER(Params)]
+    L.rafeast_params_default.restype = None
+    L.rafeast_plan.argtypes = [C.POINTER(Csr), C.POINTER(Params), C.POINTER(P)]
+    L.rafeast_plan.restype = C.c_int
+    L.rafeast_warmstart.argtypes = [P, dp, dp, C.POINTER(WsInfo)]
+    L.rafeast_warmstart.restype = C.c_int
+    L.rafeast_solve.argtypes = [P, dp, C.POINTER(Result)]
+    L.rafeast_solve.restype = C.c_int
+    L.rafeast_destroy.argtypes = [P]
+    L.rafeast_destroy.restype = None
+    L.rafeast_last_error.argtypes = [P]
+    L.rafeast_last_error.restype = C.c_char_p
+    L.rafeast_status_string.argtypes = [C.c_int]
+    L.rafeast_status_string.restype = C.c_char_p
+    L.rafeast_plan_info.argtypes = [P, dp, dp, dp, C.POINTER(C.c_int64), dp, dp]
+    L.rafeast_plan_info.restype = C.c_int
+    L.rafeast_spmm.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, C.c_double, C.c_double]
+    L.rafeast_spmm.restype = C.c_int
+    L.rafeast_gram.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int32, P, C.c_int32,
+                               P, C.c_int32]
+    L.rafeast_gram.restype = C.c_int
+    L.rafeast_cholqr2.argtypes = [P, C.c_int64, C.c_int32, P, C.c_int32, C.POINTER(C.c_int32)]
+    L.rafeast_cholqr2.restype = C.c_int
+    L.rafeast_syev.argtypes = [P, C.c_int32, P, P, P]
+    L.rafeast_syev.restype = C.c_int
+    L.rafeast_shifted_solve.argtypes = [P, C.c_int32, dp, C.c_int32, P, C.c_int32, P, C.c_double,
+                                        C.POINTER(C.c_int32), dp]
+    L.rafeast_shifted_solve.restype = C.c_int
+    L.rafeast_gaussian.argtypes = [P, C.c_int32, C.c_uint64, P, C.c_int32]
+    L.rafeast_gaussian.restype = C.c_int
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names of the rafeast_* functions declared in include/rafeast.h."""
+    import re
+
+    with open(HEADER_PATH) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"\b(rafeast_[a-z0-9_]+)\s*\(", txt)))
+
+
+def kernel_source_sha(name):
+    """SHA-256 of a kernel source under csrc/ (ties stored profiles to a kernel version)."""
+    import hashlib
+
+    with open(os.path.join(_HERE, "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _tptr(t, dtype=None):
+    """Device pointer of a contiguous CUDA/HIP torch tensor."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().rafeast_params_default(C.byref(p))
+    return p
+
+
+class Plan:
+    """A planned RA-FEAST problem (rafeast_plan) on the current HIP device."""
+
+    def __init__(self, csr, lmin, lmax, m0, nc=8, q=2, p=-1, tol_eig=1e-10, tol_solve=1e-6,
+                 max_iter=20, max_cocg=20000, precision="fp32", ws_op="auto",
+                 rhs_form="residual", engine="auto", seed=0, stream=None):
+        L = lib()
+        rowptr = np.ascontiguousarray(csr.rowptr, dtype=np.int32)
+        colind = np.ascontiguousarray(csr.colind, dtype=np.int32)
+        values = np.ascontiguousarray(csr.values, dtype=np.float64)
+        A = Csr(int(csr.n), rowptr.ctypes.data_as(C.POINTER(C.c_int32)),
+                colind.ctypes.data_as(C.POINTER(C.c_int32)),
+                values.ctypes.data_as(C.POINTER(C.c_double)), 0)
+        prm = default_params()
+        prm.lmin, prm.lmax, prm.m0, prm.nc, prm.q, prm.p = lmin, lmax, m0, nc, q, p
+        prm.tol_eig, prm.tol_solve, prm.max_iter, prm.max_cocg = tol_eig, tol_solve, max_iter, max_cocg
+        prm.precision = PRECISION[precision]
+        prm.ws_op = WS_OP[ws_op]
+        prm.rhs_form = RHS_FORM[rhs_form]
+        prm.engine = ENGINE[engine]
+        prm.seed = seed
+        prm.hip_stream = stream
+        h = C.c_void_p()
+        st = L.rafeast_plan(C.byref(A), C.byref(prm), C.byref(h))
+        if st != 0:
+            raise RafeastError(st, L.rafeast_last_error(None).decode())
+        self._h = h
+        self.n = int(csr.n)
+        self.m0 = m0
+        self.nc = nc
+        self.lmin, self.lmax = lmin, lmax
+        self.precision = precision
+        self.w = min(m0 + (p if p >= 0 else (10 if m0 <= 50 else min(20, -(-m0 // 2)))), self.n)
+
+    # ------------------------------------------------------------------ life
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rafeast_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise RafeastError(st, lib().rafeast_last_error(self._h).decode())
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ----------------------------------------------------------------- calls
+    def info(self):
+        lo, hi, an = C.c_double(), C.c_double(), C.c_double()
+        nnz = C.c_int64()
+        z = np.zeros(2 * self.nc)
+        w = np.zeros(2 * self.nc)
+        self._check(lib().rafeast_plan_info(self._h, C.byref(lo), C.byref(hi), C.byref(an),
+                                            C.byref(nnz), _dptr(z), _dptr(w)))
+        return dict(sig_lo=lo.value, sig_hi=hi.value, anorm_inf=an.value, nnz=nnz.value,
+                    z=z[0::2] + 1j * z[1::2], w=w[0::2] + 1j * w[1::2])
+
+    def warmstart(self, omega=None, want_q0=False):
+        om = None
+        if omega is not None:
+            om = np.asfortranarray(omega, dtype=np.float64)
+            if om.shape != (self.n, self.w):
+                raise ValueError(f"omega must be {self.n} x {self.w}")
+        q0 = np.zeros((self.n, self.m0), order="F") if want_q0 else None
+        inf = WsInfo()
+        self._check(lib().rafeast_warmstart(self._h, _dptr(om), _dptr(q0), C.byref(inf)))
+        out = dict(beta_m0=inf.beta_m0, beta_m0p1=inf.beta_m0p1, ratio=inf.ratio,
+                   op={v: k for k, v in WS_OP.items()}[inf.op], t_ms=inf.t_ms)
+        if want_q0:
+            out["Q0"] = q0
+        return out
+
+    def solve(self, Q_init=None, want_vectors=True):
+        qi = None
+        if Q_init is not None:
+            qi = np.asfortranarray(Q_init, dtype=np.float64)
+            if qi.shape != (self.n, self.m0):
+                raise ValueError("Q_init must be n x m0")
+        lam = np.zeros(self.m0)
+        res = np.zeros(self.m0)
+        X = np.zeros((self.n, self.m0), order="F") if want_vectors else None
+        r = Result()
+        r.flags = 0
+        r.lam = lam.ctypes.data
+        r.resid = res.ctypes.data
+        r.X = X.ctypes.data if X is not None else None
+        st = lib().rafeast_solve(self._h, _dptr(qi), C.byref(r))
+        if st not in RESULT_STATUSES:
+            self._check(st)
+        M = r.M
+        return dict(status=STATUS[st], lam=lam[:M].copy(), resid=res[:M].copy(),
+                    X=X[:, :M].copy() if X is not None else None, M=M, iters=r.iters,
+                    cocg_iters=r.cocg_iters, cocg_max=r.cocg_max, refinements=r.refinements,
+                    max_resid=r.max_resid,
+                    t_ms={k: r.t_ms[i] for i, k in enumerate(PHASES)})
+
+    def solve_device(self, lam, resid, X=None, Q_init=None):
+        """rafeast_solve with RAFEAST_PTR_DEVICE outputs into torch tensors."""
+        import torch
+
+        qi = None
+        if Q_init is not None:
+            qi = np.asfortranarray(Q_init, dtype=np.float64)
+        r = Result()
+        r.flags = 1
+        r.lam = _tptr(lam, torch.float64).value
+        r.resid = _tptr(resid, torch.float64).value
+        r.X = _tptr(X, torch.float64).value if X is not None else None
+        st = lib().rafeast_solve(self._h, _dptr(qi), C.byref(r))
+        if st not in RESULT_STATUSES:
+            self._check(st)
+        return dict(status=STATUS[st], M=r.M, iters=r.iters, cocg_iters=r.cocg_iters,
+                    cocg_max=r.cocg_max, refinements=r.refinements, max_resid=r.max_resid,
+                    t_ms={k: r.t_ms[i] for i, k in enumerate(PHASES)})
+
+    # ------------------------------------------------ step-level (device) ---
+    def spmm(self, X, Y, alpha=1.0, beta=0.0):
+        import torch
+
+        k = X.shape[1]
+        self._check(lib().rafeast_spmm(self._h, k, _tptr(X, torch.float64), X.stride(0),
+                                       _tptr(Y, torch.float64), Y.stride(0), alpha, beta))
+
+    def gram(self, X, Y, G):
+        import torch
+
+        self._check(lib().rafeast_gram(self._h, X.shape[0], X.shape[1], Y.shape[1],
+                                       _tptr(X, torch.float64), X.stride(0),
+                                       _tptr(Y, torch.float64), Y.stride(0),
+                                       _tptr(G, torch.float64), G.stride(0)))
+
+    def cholqr2(self, Y):
+        import torch
+
+        info = C.c_int32()
+        self._check(lib().rafeast_cholqr2(self._h, Y.shape[0], Y.shape[1],
+                                          _tptr(Y, torch.float64), Y.stride(0), C.byref(info)))
+        return info.value
+
+    def syev(self, H, theta, S):
+        import torch
+
+        self._check(lib().rafeast_syev(self._h, H.shape[0], _tptr(H, torch.float64),
+                                       _tptr(theta, torch.float64), _tptr(S, torch.float64)))
+
+    def shifted_solve(self, z, B, X, tol):
+        """X[:, j*k + c] = (z_j I - A)^{-1} B[:, c]; X complex64 (fp32 plan) or complex128."""
+        import torch
+
+        z = np.asarray(z, dtype=np.complex128)
+        zz = np.empty(2 * len(z))
+        zz[0::2], zz[1::2] = z.real, z.imag
+        k = B.shape[1]
+        want = torch.complex64 if self.precision == "fp32" else torch.complex128
+        it = (C.c_int32 * (len(z) * k))()
+        rs = np.zeros(len(z) * k)
+        self._check(lib().rafeast_shifted_solve(self._h, len(z), _dptr(zz), k,
+                                                _tptr(B, torch.float64), B.stride(0),
+                                                _tptr(X, want), tol, it, _dptr(rs)))
+        return np.array(it[:], dtype=np.int64), rs
+
+    def gaussian(self, Omega, seed):
+        import torch
+
+        self._check(lib().rafeast_gaussian(self._h, Omega.shape[1], seed,
+                                           _tptr(Omega, torch.float64), Omega.stride(0)))

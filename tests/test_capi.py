@@ -1,0 +1,142 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects invalid input before touching the device."""
+
+import ctypes as C
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import CSR, grid_laplacian
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2512_01257_amd import native as nat
+
+    if not os.path.exists(nat.LIB_PATH):
+        subprocess.run([sys.executable, os.path.join(ROOT, "paper_2512_01257_amd", "build.py")],
+                       check=True)
+    nat.lib()
+    return nat
+
+
+def _has_gpu():
+    try:
+        import torch
+
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def test_every_declared_symbol_is_exported(native):
+    L = native.lib()
+    names = native.exported_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_params_default_and_status_strings(native):
+    p = native.default_params()
+    assert (p.nc, p.q, p.p, p.max_iter, p.max_cocg) == (8, 2, -1, 20, 20000)
+    assert p.tol_eig == 1e-10 and p.tol_solve == 1e-6
+    assert p.precision == native.PRECISION["fp32"] and p.ws_op == 0 and p.rhs_form == 0
+    L = native.lib()
+    for code, name in native.STATUS.items():
+        assert L.rafeast_status_string(code).decode() == name
+    assert L.rafeast_status_string(99).decode() == "UNKNOWN"
+    L.rafeast_destroy(None)  # no-op
+
+
+def _plan_status(native, csr, **kw):
+    args = dict(lmin=0.0, lmax=0.5, m0=8)
+    args.update(kw)
+    try:
+        p = native.Plan(csr, **args)
+        p.close()
+        return "OK"
+    except native.RafeastError as e:
+        return e.name
+
+
+def _copy(csr, **over):
+    d = dict(n=csr.n, rowptr=csr.rowptr.copy(), colind=csr.colind.copy(), values=csr.values.copy())
+    d.update(over)
+    return CSR(**d)
+
+
+def test_bad_csr_rejected(native):
+    csr = grid_laplacian((6, 6), 0.01)
+    rp = csr.rowptr.copy()
+    rp[3], rp[4] = rp[4], rp[3]
+    assert _plan_status(native, _copy(csr, rowptr=rp)) == "BAD_CSR"
+    ci = csr.colind.copy()
+    ci[0], ci[1] = ci[1], ci[0]
+    assert _plan_status(native, _copy(csr, colind=ci)) == "BAD_CSR"
+    ci = csr.colind.copy()
+    ci[5] = 36
+    assert _plan_status(native, _copy(csr, colind=ci)) == "BAD_CSR"
+    v = csr.values.copy()
+    v[7] = np.nan
+    assert _plan_status(native, _copy(csr, values=v)) == "BAD_CSR"
+    rp = csr.rowptr.copy()
+    rp[0] = 1
+    assert _plan_status(native, _copy(csr, rowptr=rp)) == "BAD_CSR"
+
+
+def test_nonsymmetric_rejected(native):
+    csr = grid_laplacian((6, 6), 0.01)
+    v = csr.values.copy()
+    v[1] += 1e-6  # an off-diagonal entry of row 0
+    assert _plan_status(native, _copy(csr, values=v)) == "NOT_SYMMETRIC"
+    # lower triangle only: pattern not symmetric
+    import scipy.sparse as sp
+
+    from workloads import csr_from_scipy
+
+    low = csr_from_scipy(sp.tril(csr.to_scipy()))
+    assert _plan_status(native, low) == "NOT_SYMMETRIC"
+
+
+def test_invalid_params_rejected(native):
+    csr = grid_laplacian((6, 6), 0.01)
+    assert _plan_status(native, csr, lmin=0.5, lmax=0.5) == "INVALID_ARG"
+    assert _plan_status(native, csr, lmin=math.nan) == "INVALID_ARG"
+    assert _plan_status(native, csr, m0=0) == "INVALID_ARG"
+    assert _plan_status(native, csr, m0=37) == "INVALID_ARG"
+    assert _plan_status(native, csr, nc=0) == "INVALID_ARG"
+    assert _plan_status(native, csr, nc=65) == "INVALID_ARG"
+    assert _plan_status(native, csr, p=3) == "INVALID_ARG"
+    assert _plan_status(native, csr, q=-1) == "INVALID_ARG"
+    assert _plan_status(native, csr, tol_eig=0.0) == "INVALID_ARG"
+    assert _plan_status(native, csr, tol_solve=1.0) == "INVALID_ARG"
+
+
+def test_oversized_subspace_unsupported(native):
+    csr = grid_laplacian((20, 20), 0.01)
+    assert _plan_status(native, csr, m0=180, p=20) == "UNSUPPORTED"
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_valid_input_without_device(native):
+    csr = grid_laplacian((6, 6), 0.01)
+    assert _plan_status(native, csr) == "DEVICE"
+    # one-based input passes validation as well
+    one = _copy(csr, rowptr=csr.rowptr + 1, colind=csr.colind + 1)
+    L = native.lib()
+    A = native.Csr(one.n, one.rowptr.ctypes.data_as(C.POINTER(C.c_int32)),
+                   one.colind.ctypes.data_as(C.POINTER(C.c_int32)),
+                   one.values.ctypes.data_as(C.POINTER(C.c_double)), 1)
+    prm = native.default_params()
+    prm.lmin, prm.lmax, prm.m0 = 0.0, 0.5, 8
+    h = C.c_void_p()
+    assert L.rafeast_plan(C.byref(A), C.byref(prm), C.byref(h)) == 5
+    assert h.value is None
+    assert b"device" in L.rafeast_last_error(None)

@@ -1,0 +1,229 @@
+"""End-to-end GPU parity of RA-FEAST / plain FEAST through the C ABI against the
+FP64 oracle and closed-form spectra."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import feast as F
+from oracle.subspace import sin_theta
+from tests.closed_forms import grid_eigs, window_basis
+from workloads import gaussian, grid_laplacian, knn_laplacian, random_symmetric
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+CFG1_WIN = (0.0, 0.20200934091026512)
+
+
+def _gap_out(all_eigs, lmin, lmax):
+    inside = all_eigs[(all_eigs >= lmin) & (all_eigs <= lmax)]
+    outside = all_eigs[(all_eigs < lmin) | (all_eigs > lmax)]
+    return np.min(np.abs(outside[:, None] - inside[None, :]))
+
+
+def _check_against(out, A, lam_ref, V_ref, lmin, lmax, tol_eig, gap):
+    s_win = max(abs(lmin), abs(lmax))
+    assert out["M"] == len(lam_ref)
+    assert np.abs(out["lam"] - lam_ref).max() <= 1e-10 * s_win
+    X = out["X"]
+    R = A @ X - X * out["lam"][None, :]
+    res = np.linalg.norm(R, axis=0) / s_win
+    assert res.max() <= tol_eig * 1.0001
+    np.testing.assert_allclose(out["resid"], res, rtol=1e-3, atol=1e-15)
+    assert np.abs(X.T @ X - np.eye(X.shape[1])).max() < 1e-12
+    st = sin_theta(X, V_ref).max()
+    assert st <= max(1e-8, 2 * np.linalg.norm(R) / gap), st
+    # sign convention: largest-magnitude entry positive
+    idx = np.argmax(np.abs(X), axis=0)
+    assert np.all(X[idx, np.arange(X.shape[1])] > 0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("mode", ["plain16", "ra4"])
+def test_grid2d_40x40(gpu_lib, precision, mode):
+    dims, shift = (40, 40), 0.01
+    csr = grid_laplacian(dims, shift)
+    A = csr.to_scipy()
+    lmin, lmax = CFG1_WIN
+    m0 = 30
+    vals, V = window_basis(dims, shift, lmin, lmax)
+    allv, _ = grid_eigs(dims, shift)
+    gap = _gap_out(allv, lmin, lmax)
+    nc = 16 if mode == "plain16" else 4
+    with gpu_lib.Plan(csr, lmin, lmax, m0, nc=nc, q=2, p=10, precision=precision,
+                      ws_op="none" if mode == "plain16" else "auto") as plan:
+        om = gaussian(csr.n, plan.w, 0)
+        ws = plan.warmstart(omega=om)
+        out = plan.solve()
+    assert out["status"] == "OK"
+    _check_against(out, A, vals, V, lmin, lmax, 1e-10, gap)
+    if mode == "ra4":
+        assert ws["op"] == "flip"
+        ref = F.ra_feast(A, lmin, lmax, m0, nc, om, q=2)
+    else:
+        ref = F.feast(A, lmin, lmax, m0, nc, om[:, :m0])
+    assert np.abs(out["lam"] - ref["lam"]).max() <= 1e-10 * lmax
+    # the iteration count follows the oracle's (exact solves) within one step
+    assert abs(out["iters"] - ref["iters"]) <= 1
+
+
+@pytest.mark.parametrize("op", ["flip", "literal", "fold"])
+def test_warmstart_parity(gpu_lib, op):
+    csr = random_symmetric(700, 3, density=0.02)
+    A = csr.to_scipy()
+    lam = np.linalg.eigvalsh(A.toarray())
+    lmin, lmax = 0.5 * (lam[99] + lam[100]), 0.5 * (lam[119] + lam[120])
+    m0, p, q = 28, 8, 2
+    with gpu_lib.Plan(csr, lmin, lmax, m0, nc=8, q=q, p=p, ws_op=op, precision="fp64") as plan:
+        om = gaussian(csr.n, m0 + p, 9)
+        ws = plan.warmstart(omega=om, want_q0=True)
+    Q0, info = F.warmstart(A, lmin, lmax, m0, om, q, op)
+    assert ws["op"] == op
+    assert np.abs(ws["Q0"].T @ ws["Q0"] - np.eye(m0)).max() < 1e-12
+    assert sin_theta(ws["Q0"], Q0).max() < 1e-9
+    assert abs(ws["beta_m0"] - info["beta_m0"]) <= 1e-10 * abs(info["beta_m0"])
+    assert abs(ws["beta_m0p1"] - info["beta_m0p1"]) <= 1e-10 * abs(info["beta_m0p1"])
+
+
+def test_device_sketch_path(gpu_lib):
+    # no omega: the library draws Philox on the device; same numbers as the oracle's Philox
+    from oracle.philox import gaussian_sketch
+
+    csr = grid_laplacian((20, 20), 0.01)
+    A = csr.to_scipy()
+    lam = np.linalg.eigvalsh(A.toarray())
+    lmin, lmax = 0.0, 0.5 * (lam[9] + lam[10])
+    with gpu_lib.Plan(csr, lmin, lmax, 16, nc=4, q=2, p=10, seed=77, precision="fp64") as plan:
+        ws = plan.warmstart(want_q0=True)
+        out = plan.solve()
+    Q0, _ = F.warmstart(A, lmin, lmax, 16, gaussian_sketch(400, 26, 77), 2, "flip")
+    assert sin_theta(ws["Q0"], Q0).max() < 1e-9
+    assert out["status"] == "OK" and out["M"] == 10
+    np.testing.assert_allclose(out["lam"], lam[:10], atol=1e-10 * lmax)
+
+
+# The literal form stores (zI - A)^{-1} q itself, so its rounding sets the
+# subspace noise floor: it needs FP64 solves for a 1e-10 residual.
+@pytest.mark.parametrize("form,precision,tol_solve",
+                         [("residual", "fp32", 1e-8), ("literal", "fp64", 1e-12)])
+def test_ragged_interior_window(gpu_lib, form, precision, tol_solve):
+    # n not a multiple of 64, odd nc, interior (fold) window, m0 not a multiple of 16
+    csr = random_symmetric(333, 8, density=0.05)
+    A = csr.to_scipy()
+    lam, V = np.linalg.eigh(A.toarray())
+    lmin, lmax = 0.5 * (lam[149] + lam[150]), 0.5 * (lam[157] + lam[158])
+    m0 = 13
+    with gpu_lib.Plan(csr, lmin, lmax, m0, nc=3, q=1, p=5, rhs_form=form, max_iter=60,
+                      tol_solve=tol_solve, precision=precision) as plan:
+        om = gaussian(csr.n, m0 + 5, 4)
+        plan.warmstart(omega=om)
+        out = plan.solve()
+    assert out["status"] == "OK"
+    _check_against(out, A, lam[150:158], V[:, 150:158], lmin, lmax, 1e-10,
+                   _gap_out(lam, lmin, lmax))
+
+
+def test_literal_form_noise_floor(gpu_lib):
+    # Theorem 2 / Remark 2: with solves against Q to relative tolerance tau the
+    # subspace error stalls near tau; solving against the Ritz residuals
+    # (residual-correction form) makes the solve error proportional to the
+    # residual, so the same tau reaches the 1e-10 target.
+    csr = grid_laplacian((40, 40), 0.01)
+    lmin, lmax = CFG1_WIN
+    outs = {}
+    for form in ("literal", "residual"):
+        with gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10, rhs_form=form, max_iter=12,
+                          tol_solve=1e-5) as plan:
+            plan.warmstart(omega=gaussian(csr.n, 40, 0))
+            outs[form] = plan.solve()
+    assert outs["residual"]["status"] == "OK"
+    assert outs["literal"]["status"] == "NO_CONVERGENCE"
+    assert outs["literal"]["max_resid"] > 1e-9
+
+
+def test_empty_window_and_small_subspace(gpu_lib):
+    csr = grid_laplacian((12, 12), 0.01)
+    vals, _ = grid_eigs((12, 12), 0.01)
+    with gpu_lib.Plan(csr, -1.0, -0.5, 8, nc=4, max_iter=6) as plan:
+        out = plan.solve()
+    assert out["status"] == "EMPTY_WINDOW" and out["M"] == 0
+    lmax = 0.5 * (vals[9] + vals[10])
+    with gpu_lib.Plan(csr, 0.0, lmax, 6, nc=8, p=4, max_iter=6) as plan:
+        out = plan.solve()
+    assert out["M"] >= 6
+    assert out["status"] in ("SUBSPACE_TOO_SMALL", "NO_CONVERGENCE")
+
+
+def test_resume_from_checkpoint(gpu_lib):
+    csr = grid_laplacian((30, 30), 0.01)
+    A = csr.to_scipy()
+    lam = np.linalg.eigvalsh(A.toarray())
+    # (3,3) | (2,4),(4,2): the cut after the 11th eigenvalue is a real gap
+    assert lam[11] - lam[10] > 1e-3
+    lmin, lmax = 0.0, 0.5 * (lam[10] + lam[11])
+    with gpu_lib.Plan(csr, lmin, lmax, 18, nc=4, max_iter=1, p=10) as plan:
+        plan.warmstart(omega=gaussian(900, 28, 1))
+        first = plan.solve()
+        assert first["status"] == "NO_CONVERGENCE" and first["iters"] == 1
+    with gpu_lib.Plan(csr, lmin, lmax, 18, nc=4, max_iter=20, p=10) as plan:
+        # restart from the saved n x M in-window vectors padded with random columns
+        Qi = np.concatenate([first["X"], gaussian(900, 18 - first["M"], 3)], axis=1)
+        out = plan.solve(Q_init=Qi)
+    assert out["status"] == "OK"
+    np.testing.assert_allclose(out["lam"], lam[:11], atol=1e-10 * lmax)
+
+
+def test_device_outputs(gpu_lib):
+    import torch
+
+    csr = grid_laplacian((20, 20), 0.01)
+    lam = np.linalg.eigvalsh(csr.to_scipy().toarray())
+    lmin, lmax = 0.0, 0.5 * (lam[9] + lam[10])
+    with gpu_lib.Plan(csr, lmin, lmax, 16, nc=4, p=10) as plan:
+        plan.warmstart(omega=gaussian(400, 26, 0))
+        L = torch.zeros(16, dtype=torch.float64, device="cuda")
+        Rz = torch.zeros(16, dtype=torch.float64, device="cuda")
+        X = torch.zeros((16, 400), dtype=torch.float64, device="cuda")  # n x m0 column-major
+        out = plan.solve_device(L, Rz, X)
+    assert out["status"] == "OK" and out["M"] == 10
+    np.testing.assert_allclose(L.cpu().numpy()[:10], lam[:10], atol=1e-10 * lmax)
+    Xv = X.cpu().numpy()[:10].T
+    assert np.abs(Xv.T @ Xv - np.eye(10)).max() < 1e-12
+
+
+def _knn8000():
+    with open(os.path.join(GOLDEN, "windows.json")) as f:
+        win = json.load(f)["knn8000"]
+    csr = knn_laplacian(8000, 2, 10, seed=1, weighted=True, shift=1e-3)
+    assert csr.nnz == win["nnz"]
+    return csr, win
+
+
+@pytest.mark.parametrize("nc,ws_op", [(4, "auto"), (16, "none")])
+def test_knn8000_parity(gpu_lib, nc, ws_op):
+    csr, win = _knn8000()
+    A = csr.to_scipy()
+    lmin, lmax = win["lmin"], win["lmax"]
+    ev = np.array(win["eigenvalues"])
+    m0, p = 64, 20
+    with gpu_lib.Plan(csr, lmin, lmax, m0, nc=nc, q=2, p=p, tol_solve=1e-6, ws_op=ws_op,
+                      tol_eig=1e-12) as plan:
+        om = gaussian(csr.n, m0 + p, 0)
+        plan.warmstart(omega=om)
+        out = plan.solve()
+    assert out["status"] == "OK" and out["M"] == 50
+    s_win = lmax
+    assert np.abs(out["lam"] - ev[:50]).max() <= 1e-10 * s_win
+    if nc == 4:
+        ref = F.ra_feast(A, lmin, lmax, m0, nc, om, q=2, tol=1e-12)
+    else:
+        ref = F.feast(A, lmin, lmax, m0, nc, om[:, :m0], tol=1e-12)
+    assert ref["M"] == 50
+    assert np.abs(out["lam"] - ref["lam"]).max() <= 1e-10 * s_win
+    X = out["X"]
+    R = A @ X - X * out["lam"][None, :]
+    gap = ev[50] - ev[49]
+    assert sin_theta(X, ref["X"]).max() <= max(1e-8, 2 * np.linalg.norm(R) / gap)
