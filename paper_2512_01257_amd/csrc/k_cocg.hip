@@ -5,9 +5,8 @@
 //
 // Resident engine: one 1024-thread workgroup owns one system for its whole
 // solve.  The search direction p (gathered by the SpMM) and the residual r
-// live in LDS, w = (zI - A) p lives in registers (RPT slots per thread), and
-// the iterate x, only read-modify-written, lives in a per-workgroup global
-// buffer (L2-resident).  A is streamed from L2 in the row-sorted
+// live in LDS; w = (zI - A) p and the iterate x live in registers (RPT slots
+// per thread).  A is streamed from L2 in the row-sorted
 // SELL-64 layout of kernels.h (one 8- or 16-byte load per nonzero, coalesced
 // across the wave, the column already an LDS byte offset).  Both COCG
 // reductions per iteration are workgroup reductions: no grid-wide
@@ -27,6 +26,9 @@
 // the cycle.
 #include "device.h"
 #include "kernels.h"
+
+#include <algorithm>
+#include <vector>
 
 namespace rafeast {
 
@@ -53,14 +55,19 @@ __device__ __forceinline__ void block_sum(const A (&part)[NV], double (&v)[NV],
     for (int q = 0; q < NV; ++q) red[set][wv][q] = ws[q];
   }
   __syncthreads();
+  // lane w < kResWaves reads wave w's sum; a DPP sum over the wave (the
+  // same fixed order in every wave) gives every thread the same total
+  const int ln = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kResWaves; ++w) s += red[set][w][q];
-    v[q] = s;
+    const double x = ln < kResWaves ? red[set][ln][q] : 0.0;
+    v[q] = wave_sum_f64(x);
   }
 }
+
+struct __align__(16) EPair {
+  SellEntry32 a, b;
+};
 
 template <typename T>
 struct EntryOf;
@@ -127,7 +134,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     const double* __restrict__ Bm, int ldb, int kcols, cpx<T>* __restrict__ D, int ldd,
     double tol, int maxit, int max_refine, int* __restrict__ counter, int* __restrict__ iters,
     int* __restrict__ stats, double* __restrict__ resid_out, cpx<double>* __restrict__ xhi_all,
-    cpx<T>* __restrict__ xlo_all, int zero_base) {
+    int zero_base, const int* __restrict__ wave_slices) {
   // Dynamic LDS only (so p starts at address 0 and a gather address is the
   // entry's stored byte offset): p | r | reduction slots | work item.
   extern __shared__ unsigned char smem_raw[];
@@ -142,11 +149,13 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double tol2 = tol * tol;
+  // this wave's slices (-1: none), widest first; fixed for the whole kernel
+  int slc[RPT];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) slc[t] = wave_slices[wv * RPT + t];
   cpx<double>* __restrict__ XH = xhi_all + (size_t)blockIdx.x * npad;
-  cpx<T>* __restrict__ XL = xlo_all + (size_t)blockIdx.x * npad;
-  const char* Pb = reinterpret_cast<const char*>(P);
 
-  cpx<T> w[RPT];
+  cpx<T> w[RPT], xr[RPT];
 
   for (;;) {
     if (tid == 0) s_item = atomicAdd(counter, 1);
@@ -161,8 +170,8 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     double acc1[1] = {0.0};
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int slice = wv + kResWaves * t;
-      if (slice < nslices) {
+      const int slice = slc[t];
+      if (slice >= 0) {
         const int row = perm[slice * 64 + lane];
         const double b = row >= 0 ? Bm[(unsigned)row * (unsigned)ldb + ci] : 0.0;
         acc1[0] += b * b;
@@ -174,8 +183,8 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     if (!(bn2 > 0.0) || !isfinite(bn2)) {
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const int slice = wv + kResWaves * t;
-        if (slice < nslices) {
+        const int slice = slc[t];
+        if (slice >= 0) {
           const int row = perm[slice * 64 + lane];
           if (row >= 0) D[(unsigned)row * (unsigned)ldd + ocol] = cpx<T>{T(0), T(0)};
         }
@@ -187,19 +196,19 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       continue;
     }
     const double scale = 1.0 / sqrt(bn2);
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) xr[t] = cpx<T>{T(0), T(0)};
     double rho3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int slice = wv + kResWaves * t;
-      if (slice < nslices) {
+      const int slice = slc[t];
+      if (slice >= 0) {
         const int s = slice * 64 + lane;
         const int row = perm[s];
         const double b = row >= 0 ? Bm[(unsigned)row * (unsigned)ldb + ci] * scale : 0.0;
         const cpx<T> rv{T(b), T(0)};
         P[s] = rv;
         R[s] = rv;
-        XL[s] = cpx<T>{T(0), T(0)};
-        XH[s] = cpx<double>{0.0, 0.0};
         const double rr = (double)rv.re;
         rho3[0] += rr * rr;
       }
@@ -209,6 +218,9 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     double rho_re = rho_s[0], rho_im = 0.0;
     int it = 0, nref = 0, nbd = 0;
     double last_res = 1.0;
+    // x_hi is first written at the end of the first cycle (kept out of L2
+    // while the cycle iterates)
+    bool first_cycle = true;
     // A cycle stops at max(tol, eps_inner * ||r at cycle start||): the
     // relative reduction one cycle in T can deliver reliably.
     const double eps_inner = sizeof(T) == 4 ? 1e-6 : 1e-14;
@@ -235,9 +247,9 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       for (int t = 0; t < RPT; ++t) {
         acc_re[t] = T(0);
         acc_im[t] = T(0);
-        const int slice = wv + kResWaves * t;
-        bse[t] = slice < nslices ? sbase[slice] : zero_base;
-        wde[t] = slice < nslices ? (sbase[slice + 1] - bse[t]) >> 6 : 0;
+        const int slice = slc[t];
+        bse[t] = slice >= 0 ? sbase[slice] : zero_base;
+        wde[t] = slice >= 0 ? (sbase[slice + 1] - bse[t]) >> 6 : 0;
       }
       for (int kk = 0; kk < wde[0]; kk += KB) {
         E e[RPT][KB];
@@ -246,16 +258,32 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
           // uniform base pointer of this slot's batch (or of the zero entries);
           // the per-lane part of the address is the fixed ln
           const E* __restrict__ ep = kk < wde[t] ? ent + bse[t] + kk * 64 : ent + zero_base;
+          if constexpr (sizeof(E) == 8) {
+            // FP32 entries are pair-major: one 16-byte load per two entries
 #pragma unroll
-          for (int u = 0; u < KB; ++u) e[t][u] = ep[u * 64 + ln];
+            for (int u = 0; u < KB; u += 2) {
+              const EPair pr = reinterpret_cast<const EPair*>(ep + u * 64)[ln];
+              e[t][u] = pr.a;
+              e[t][u + 1] = pr.b;
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < KB; ++u) e[t][u] = ep[u * 64 + ln];
+          }
+        }
+        // all gathers of the batch are issued before the FMAs consume them
+        cpx<T> g[RPT][KB];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+#pragma unroll
+          for (int u = 0; u < KB; ++u) g[t][u] = lds_gather<T>(e[t][u].c);
         }
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
 #pragma unroll
           for (int u = 0; u < KB; ++u) {
-            const cpx<T> g = lds_gather<T>(e[t][u].c);
-            acc_re[t] += e[t][u].v * g.re;
-            acc_im[t] += e[t][u].v * g.im;
+            acc_re[t] += e[t][u].v * g[t][u].re;
+            acc_im[t] += e[t][u].v * g[t][u].im;
           }
         }
       }
@@ -263,21 +291,14 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       const T zrt = T(zr), zit = T(zi);
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const int slice = wv + kResWaves * t;
-        if (slice < nslices) {
+        const int slice = slc[t];
+        if (slice >= 0) {
           const cpx<T> pr = P[slice * 64 + ln];
           w[t].re = zrt * pr.re - zit * pr.im - acc_re[t];
           w[t].im = zrt * pr.im + zit * pr.re - acc_im[t];
           mu_t[0] += pr.re * w[t].re - pr.im * w[t].im;
           mu_t[1] += pr.re * w[t].im + pr.im * w[t].re;
         }
-      }
-      // x is only read-modify-written: its loads go out before the reduction
-      cpx<T> xv[RPT];
-#pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const int slice = wv + kResWaves * t;
-        if (slice < nslices) xv[t] = XL[slice * 64 + ln];
       }
       double mu[2];
       block_sum<2>(mu_t, mu, red, 0);
@@ -291,13 +312,12 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
         const T alr = T(alpha.re), ali = T(alpha.im);
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
-          const int slice = wv + kResWaves * t;
-          if (slice < nslices) {
+          const int slice = slc[t];
+          if (slice >= 0) {
             const int s = slice * 64 + ln;
             const cpx<T> pr = P[s];
-            xv[t].re += alr * pr.re - ali * pr.im;
-            xv[t].im += alr * pr.im + ali * pr.re;
-            XL[s] = xv[t];
+            xr[t].re += alr * pr.re - ali * pr.im;
+            xr[t].im += alr * pr.im + ali * pr.re;
             cpx<T> rv = R[s];
             rv.re -= alr * w[t].re - ali * w[t].im;
             rv.im -= alr * w[t].im + ali * w[t].re;
@@ -319,8 +339,8 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
           const T br = T(beta.re), bi = T(beta.im);
 #pragma unroll
           for (int t = 0; t < RPT; ++t) {
-            const int slice = wv + kResWaves * t;
-            if (slice < nslices) {
+            const int slice = slc[t];
+            if (slice >= 0) {
               const int s = slice * 64 + ln;
               const cpx<T> pr = P[s];
               const cpx<T> rv = R[s];
@@ -335,24 +355,26 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       // ---- x_hi += x; true residual s = b - (zI - A) x_hi in FP64 ----
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const int slice = wv + kResWaves * t;
-        if (slice < nslices) {
+        const int slice = slc[t];
+        if (slice >= 0) {
           const int s = slice * 64 + ln;
-          const cpx<T> xl = XL[s];
-          XL[s] = cpx<T>{T(0), T(0)};
-          cpx<double> xh = XH[s];
+          const cpx<T> xl = xr[t];
+          xr[t] = cpx<T>{T(0), T(0)};
+          cpx<double> xh{0.0, 0.0};
+          if (!first_cycle) xh = XH[s];
           xh.re += (double)xl.re;
           xh.im += (double)xl.im;
           XH[s] = xh;
         }
       }
+      first_cycle = false;
       __syncthreads();
       double s3p[3] = {0.0, 0.0, 0.0}, s3[3];
       const char* XHb = reinterpret_cast<const char*>(XH);
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const int slice = wv + kResWaves * t;
-        if (slice < nslices) {
+        const int slice = slc[t];
+        if (slice >= 0) {
           const int s = slice * 64 + ln;
           const int base = sbase[slice];
           const int wdt = (sbase[slice + 1] - base) >> 6;
@@ -378,8 +400,8 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       cyc_tol2 = fmax(tol2, eps_inner * eps_inner * s3[2]);
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const int slice = wv + kResWaves * t;
-        if (slice < nslices) {
+        const int slice = slc[t];
+        if (slice >= 0) {
           const int s = slice * 64 + ln;
           P[s] = w[t];
           R[s] = w[t];
@@ -391,8 +413,8 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     const double bn = sqrt(bn2);
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int slice = wv + kResWaves * t;
-      if (slice < nslices) {
+      const int slice = slc[t];
+      if (slice >= 0) {
         const int row = perm[slice * 64 + lane];
         const cpx<double> xh = XH[slice * 64 + lane];
         if (row >= 0)
@@ -415,6 +437,46 @@ size_t cocg_resident_xhi_slots(int n, int blocks) {
 // p and r in LDS: 16 B per slot in FP32, 32 B in FP64.
 int cocg_resident_max_n(bool fp32) { return (fp32 ? 8 : 4) * kResWaves * 64; }
 
+int cocg_resident_waves() { return kResWaves; }
+
+// Slice-to-wave table: contiguous runs of the width-sorted slices, as many
+// per wave as keep (slots x widest width) under a common bound C, with C the
+// smallest bound for which kResWaves waves of at most rpt slots suffice.  A
+// wave's batch loop runs to its widest slot and loads every slot at each
+// step, so its cost is its slot count times its widest width.
+std::vector<int> cocg_resident_wave_table(const std::vector<int>& widths, int rpt) {
+  const int nsl = (int)widths.size();
+  auto place = [&](long long C, std::vector<int>* out) {
+    int s = 0;
+    for (int wv = 0; wv < kResWaves; ++wv) {
+      int k = 0;
+      if (s < nsl) {
+        const long long w0 = widths[s] > 0 ? widths[s] : 1;
+        k = (int)std::min<long long>(rpt, C / w0);
+        if (k < 1) return false;
+        k = std::min(k, nsl - s);
+      }
+      if (out)
+        for (int t = 0; t < rpt; ++t) (*out)[wv * rpt + t] = t < k ? s + t : -1;
+      s += k;
+    }
+    return s >= nsl;
+  };
+  long long lo = 1, hi = 1;
+  for (int w : widths) hi = std::max<long long>(hi, (long long)w * rpt);
+  if (!place(hi, nullptr)) return {};
+  while (lo < hi) {
+    const long long mid = (lo + hi) / 2;
+    if (place(mid, nullptr))
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  std::vector<int> tab((size_t)kResWaves * rpt, -1);
+  place(hi, &tab);
+  return tab;
+}
+
 size_t cocg_resident_lds(int n, bool fp32) {
   const size_t nsl = (size_t)(n + 63) / 64;
   return nsl * 64 * 2 * (fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>)) +
@@ -436,7 +498,7 @@ static hipError_t launch_res(hipStream_t st, const SellMatrix& A, const CocgLaun
   hipLaunchKernelGGL((k_cocg_resident<T, RPT>), dim3(blocks), dim3(kResThreads), lds, st,
                      A.nslices, A.sbase, A.perm, ent, A.e64, L.nitems, L.items, L.zs, L.B, L.ldb,
                      L.k, (cpx<T>*)L.D, L.ldd, L.tol, L.maxit, L.max_refine, L.counter, L.iters,
-                     L.stats, L.resid, (cpx<double>*)L.xhi, (cpx<T>*)L.xlo, A.zero_base);
+                     L.stats, L.resid, (cpx<double>*)L.xhi, A.zero_base, A.wave_slices);
   return hipGetLastError();
 }
 
@@ -447,20 +509,22 @@ hipError_t launch_cocg_resident(hipStream_t st, const SellMatrix& A, const CocgL
   if ((int64_t)A.n * L.ldb >= (int64_t(1) << 31) || (int64_t)A.n * L.ldd >= (int64_t(1) << 31))
     return hipErrorInvalidValue;
   if (L.nitems <= 0) return hipSuccess;
-  const int need = (A.nslices + kResWaves - 1) / kResWaves;  // slices per wave
+  const int need = A.wave_rpt;  // slots per wave of the slice table
+  if (A.wave_slices == nullptr || !(need == 1 || need == 2 || need == 4 || need == 8))
+    return hipErrorInvalidValue;
   int blocks = num_blocks < L.nitems ? num_blocks : L.nitems;
   if (blocks < 1) blocks = 1;
-  if (L.xhi == nullptr || L.xlo == nullptr || (size_t)blocks * A.nslices * 64 > L.xhi_slots)
-    return hipErrorInvalidValue;
+  if (L.xhi == nullptr || (size_t)blocks * A.nslices * 64 > L.xhi_slots) return hipErrorInvalidValue;
   if (fp32) {
-    if (need <= 1) return launch_res<float, 1>(st, A, L, A.e32, blocks);
-    if (need <= 2) return launch_res<float, 2>(st, A, L, A.e32, blocks);
-    if (need <= 4) return launch_res<float, 4>(st, A, L, A.e32, blocks);
+    if (need == 1) return launch_res<float, 1>(st, A, L, A.e32, blocks);
+    if (need == 2) return launch_res<float, 2>(st, A, L, A.e32, blocks);
+    if (need == 4) return launch_res<float, 4>(st, A, L, A.e32, blocks);
     return launch_res<float, 8>(st, A, L, A.e32, blocks);
   }
-  if (need <= 1) return launch_res<double, 1>(st, A, L, A.e64, blocks);
-  if (need <= 2) return launch_res<double, 2>(st, A, L, A.e64, blocks);
-  return launch_res<double, 4>(st, A, L, A.e64, blocks);
+  if (need == 1) return launch_res<double, 1>(st, A, L, A.e64, blocks);
+  if (need == 2) return launch_res<double, 2>(st, A, L, A.e64, blocks);
+  if (need == 4) return launch_res<double, 4>(st, A, L, A.e64, blocks);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace rafeast

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace rafeast {
 
 // ---- sparse x dense (FP64, real) ------------------------------------------
@@ -76,9 +78,12 @@ hipError_t launch_select(hipStream_t st, int k, int m0, const double* theta, con
 
 // ---- COCG ---------------------------------------------------------------------
 // SELL-64 copy of A for the resident COCG engine.  Rows are reordered by
-// decreasing length (slot s holds row perm[s]; slots >= n are empty), cut
-// into slices of 64 slots, and stored entry-major within a slice so that the
-// k-th entries of a slice's 64 rows are contiguous.  An entry's column is
+// decreasing length (slot s holds row perm[s]; slots >= n are empty) and cut
+// into slices of 64 slots.  FP64 entries are stored entry-major within a
+// slice (the k-th entries of the 64 rows contiguous, 16 B per lane); FP32
+// entries are stored pair-major (entries 2j and 2j+1 of a row adjacent, then
+// the next row's pair), so one 16-byte lane load fetches two entries: the
+// per-CU load rate from L2 is set by load instructions, not bytes.  An entry's column is
 // stored as the byte offset of its slot in a complex vector of the entry's
 // precision (slot * 8 for FP32 complex, slot * 16 for FP64 complex), so a
 // gather needs no address arithmetic.  Slice widths are padded to a multiple
@@ -100,6 +105,8 @@ struct SellMatrix {
   const SellEntry32* e32 = nullptr;     // FP32 entries
   const SellEntry64* e64 = nullptr;     // FP64 entries
   int zero_base = 0;                    // 256 entries (slot 0, value 0) start here
+  const int* wave_slices = nullptr;     // [waves * wave_rpt] slice of each wave slot, -1 none
+  int wave_rpt = 0;                     // slots per wave (1, 2, 4 or 8)
 };
 
 struct CocgLaunch {
@@ -119,7 +126,6 @@ struct CocgLaunch {
   int* stats = nullptr;         // [2]: refinements, breakdowns (accumulated)
   double* resid = nullptr;      // nullable [nz*k]: final relative true residual
   void* xhi = nullptr;          // FP64 complex solution scratch, xhi_slots entries
-  void* xlo = nullptr;          // working-precision complex iterate scratch, xhi_slots entries
   size_t xhi_slots = 0;         // >= blocks * nslices * 64
 };
 
@@ -127,6 +133,11 @@ struct CocgLaunch {
 size_t cocg_resident_xhi_slots(int n, int blocks);
 // Largest n the resident engine takes at this precision.
 int cocg_resident_max_n(bool fp32);
+// Waves per resident workgroup, and the slice-to-wave table for slice widths
+// (entries per row, in slice order, non-increasing) with at most rpt slots
+// per wave; empty when the slices do not fit.
+int cocg_resident_waves();
+std::vector<int> cocg_resident_wave_table(const std::vector<int>& widths, int rpt);
 // Dynamic LDS bytes the resident engine needs for n.
 size_t cocg_resident_lds(int n, bool fp32);
 hipError_t launch_cocg_resident(hipStream_t st, const SellMatrix& A, const CocgLaunch& L,

@@ -43,6 +43,7 @@ struct rafeast_plan_s {
   SellMatrix sell;
   int* d_sbase = nullptr;
   int* d_perm = nullptr;
+  int* d_wtab = nullptr;
   SellEntry32* d_e32 = nullptr;
   SellEntry64* d_e64 = nullptr;
   size_t sell_entries = 0;
@@ -75,7 +76,6 @@ struct rafeast_plan_s {
   int* d_flag = nullptr;     // 1
   int* d_sel = nullptr;      // m0
   void* d_xhi = nullptr;     // FP64 solution scratch of the resident COCG engine
-  void* d_xlo = nullptr;     // working-precision iterate scratch of the same
   size_t xhi_slots = 0;
   int nitems = 0;
   bool have_start = false;
@@ -305,12 +305,12 @@ rafeast_status dalloc(rafeast_plan_s* P, T** p, size_t count, const char* what) 
 
 void free_plan(rafeast_plan_s* P) {
   if (!P) return;
-  void* ptrs[] = {P->d_rowptr, P->d_col,  P->d_val,   P->d_sbase, P->d_perm, P->d_e32,
+  void* ptrs[] = {P->d_rowptr, P->d_col,  P->d_val,   P->d_sbase, P->d_perm, P->d_wtab, P->d_e32,
                   P->d_e64,   P->d_Q,    P->d_W,     P->d_R,     P->d_T,    P->d_Y,
                   P->d_G,      P->d_M,    P->d_S,     P->d_Ssel,  P->d_jw,   P->d_theta,
                   P->d_res,    P->d_qn,   P->d_gamma, P->d_info,  P->d_zw,   P->d_part,
                   P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
-                  P->d_sel, P->d_xhi, P->d_xlo};
+                  P->d_sel, P->d_xhi};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& e : P->ev)
@@ -401,7 +401,6 @@ rafeast_status run_cocg(rafeast_plan_s* P, int nitems, const int* d_items, const
   L.stats = P->d_stats;
   L.resid = d_resid;
   L.xhi = P->d_xhi;
-  L.xlo = P->d_xlo;
   L.xhi_slots = P->xhi_slots;
   HIPCHK(P, hipMemsetAsync(P->d_counter, 0, sizeof(int), P->st));
   HIPCHK(P, launch_cocg_resident(P->st, P->sell, L, P->fp32, P->num_cu));
@@ -630,12 +629,14 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
           const int64_t sl = (int64_t)s * 64 + l;
           const size_t e = (size_t)sb[s] + (size_t)kk * 64 + l;
           const int row = sl < n ? order[sl] : -1;
+          // FP32: pair-major position of entry kk of lane l
+          const size_t e2 = (size_t)sb[s] + (size_t)(kk / 2) * 128 + (size_t)l * 2 + (kk % 2);
           if (row >= 0 && kk < rp[row + 1] - rp[row]) {
             const int t = rp[row] + kk;
-            e32[e] = SellEntry32{slot_of[cl[t]] * 8, (float)A->values[t]};
+            e32[e2] = SellEntry32{slot_of[cl[t]] * 8, (float)A->values[t]};
             e64[e] = SellEntry64{slot_of[cl[t]] * 16, 0, A->values[t]};
           } else {
-            e32[e] = SellEntry32{(int)sl * 8, 0.0f};  // padding: own slot, zero value
+            e32[e2] = SellEntry32{(int)sl * 8, 0.0f};  // padding: own slot, zero value
             e64[e] = SellEntry64{(int)sl * 16, 0, 0.0};
           }
         }
@@ -658,6 +659,24 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
     P->sell.e64 = P->d_e64;
     P->sell.zero_base = sb[nsl];
     P->sell_entries = tot;
+    // slice-to-wave table for the smallest slot count per wave that fits
+    std::vector<int> widths(nsl);
+    for (int s2 = 0; s2 < nsl; ++s2) widths[s2] = (sb[s2 + 1] - sb[s2]) / 64;
+    std::vector<int> tab;
+    int rpt = 0;
+    for (int cand : {1, 2, 4, 8}) {
+      if (!fp32 && cand > 4) break;
+      tab = cocg_resident_wave_table(widths, cand);
+      if (!tab.empty()) {
+        rpt = cand;
+        break;
+      }
+    }
+    if (rpt == 0) return bail(fail(P, RAFEAST_UNSUPPORTED, "matrix does not fit the resident engine"));
+    PRCHK(dalloc(P, &P->d_wtab, tab.size(), "wave table"));
+    PCHK(hipMemcpy(P->d_wtab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+    P->sell.wave_slices = P->d_wtab;
+    P->sell.wave_rpt = rpt;
   }
 
   // workspace
@@ -697,8 +716,6 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
   {
     hipError_t e = hipMalloc(&P->d_xhi, P->xhi_slots * 2 * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(P, e, "solution scratch"));
-    e = hipMalloc(&P->d_xlo, P->xhi_slots * 2 * (fp32 ? sizeof(float) : sizeof(double)));
-    if (e != hipSuccess) return bail(hip_fail(P, e, "iterate scratch"));
   }
   PCHK(hipMemcpy(P->d_zw, P->zw.data(), 4 * P->nc * sizeof(double), hipMemcpyHostToDevice));
   {
