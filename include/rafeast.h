@@ -74,10 +74,14 @@ enum { RAFEAST_RHS_RESIDUAL = 0,  /* solve against Ritz residuals r_i and use
                                      (zI-A)^{-1} q = (q + (zI-A)^{-1} r)/(z - theta) */
        RAFEAST_RHS_LITERAL = 1 }; /* solve against the Ritz vectors q_i (Algorithm 1) */
 
-/* rafeast_params.engine: COCG engine. */
+/* rafeast_params.engine: COCG engine.  AUTO takes RESIDENT when n fits on
+ * chip (n <= 8192 at FP32_REFINED, n <= 4096 at FP64, row lengths permitting)
+ * and STREAM otherwise.  Both run the same method (COCG with FP64
+ * true-residual refinement) to the same stopping test. */
 enum { RAFEAST_ENGINE_AUTO = 0,
-       RAFEAST_ENGINE_RESIDENT = 1,  /* one workgroup per system, vectors on chip (small n) */
-       RAFEAST_ENGINE_STREAM = 2 };  /* all systems per kernel, vectors in HBM (large n) */
+       RAFEAST_ENGINE_RESIDENT = 1,  /* one workgroup per system, vectors in LDS/registers */
+       RAFEAST_ENGINE_STREAM = 2 };  /* all systems in lock step, vectors in HBM, rows
+                                        reordered by reverse Cuthill-McKee */
 
 /* rafeast_result.flags */
 enum { RAFEAST_PTR_DEVICE = 1 };  /* lambda/resid/X are device pointers */
@@ -176,7 +180,9 @@ rafeast_status rafeast_warmstart(rafeast_plan_t plan, const double* omega, doubl
  * stop test; shifted COCG solves for all (node, column) pairs; combination
  * Q~ = sum_j Re[w_j (z_j I - A)^{-1} Q]; CholQR2.  Writes *res as documented
  * in rafeast_result.  Returns OK, NO_CONVERGENCE, SUBSPACE_TOO_SMALL,
- * EMPTY_WINDOW or BREAKDOWN with results written, or an error. */
+ * EMPTY_WINDOW or BREAKDOWN with results written, or an error.  With the
+ * environment variable RAFEAST_VERBOSE set (not "0"), one progress line per
+ * iteration goes to stderr. */
 rafeast_status rafeast_solve(rafeast_plan_t plan, const double* Q_init, rafeast_result* res);
 
 /* Releases the plan and all its device memory.  NULL is a no-op. */
@@ -193,6 +199,18 @@ const char* rafeast_status_string(rafeast_status s);
  * z and w: nullable host arrays of 2*nc doubles (re, im interleaved). */
 rafeast_status rafeast_plan_info(rafeast_plan_t plan, double* sig_lo, double* sig_hi,
                                  double* anorm_inf, int64_t* nnz, double* z, double* w);
+
+/* The COCG engine the plan resolved (RAFEAST_ENGINE_RESIDENT or _STREAM);
+ * 0 for a NULL plan. */
+int32_t rafeast_plan_engine(rafeast_plan_t plan);
+
+/* Reverse Cuthill-McKee order of the graph of A (host only, needs no
+ * device): per connected component, breadth-first search from a
+ * pseudo-peripheral vertex (George-Liu), neighbours by increasing degree, the
+ * whole sequence reversed.  perm: caller-allocated host [n], perm[new] = old,
+ * 0-based.  The streaming engine renumbers rows with it.  A is validated as
+ * in rafeast_plan (BAD_CSR, NOT_SYMMETRIC, INVALID_ARG). */
+rafeast_status rafeast_rcm_order(const rafeast_csr* A, int32_t* perm);
 
 /* ---------------------------------------------------------------------------
  * Step-level calls on caller-owned device buffers (row-major, see top).  They

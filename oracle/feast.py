@@ -141,12 +141,37 @@ def normalise_signs(X):
 
 # ------------------------------------------------------------------ FEAST ---
 
+# Ritz pairs whose filter gain is below this are spurious (see filter_gain).
+SPURIOUS_GAIN = 0.25
+
+
+def filter_gain(Qt, Q):
+    """Filter gain mu_i of each Ritz vector q_i of Q, a basis of span(Qt).
+
+    Qt = rho(A) Qprev is the filtered block of an orthonormal block Qprev
+    (Section 2.1: the filter approximates the spectral projector).  Writing
+    q_i = Qt y_i, the vector u_i = Qprev y_i satisfies rho(A) u_i = q_i, so
+    mu_i = ||q_i|| / ||y_i|| = ||rho(A) u_i|| / ||u_i||.  For an eigenvector
+    with eigenvalue lam it is |rho(lam)|, at least 1/2 inside the window (the
+    filter is 1/2 at the edges); a mixture of eigenvectors from outside the
+    window, which can put a Ritz value inside it, has the small gain of its
+    parts.  y_i is the least-squares solution of Qt y = q_i.
+    """
+    Y = np.linalg.lstsq(Qt, Q, rcond=None)[0]
+    return np.linalg.norm(Q, axis=0) / np.linalg.norm(Y, axis=0)
+
+
 def feast(A, lmin, lmax, m0, nc, Q0, tol=1e-10, max_iter=20, form="residual",
           solver=None, perturb=None, record=False):
     """FEAST iteration from the start block Q0 (n x m0).
 
     perturb(m, Qt) -> Qt', if given, is applied to the filtered block of
     iteration m before orthonormalisation (perturbation E^(m) of Section 3.2.4).
+
+    The pairs counted (M) and tested for convergence are the Ritz pairs with
+    theta in the closed window whose filter gain (filter_gain) is at least
+    SPURIOUS_GAIN; before the first filter step every gain counts as 1.  The
+    window is reported empty when no Ritz value lies in it from iteration 2 on.
     """
     A = sp.csr_matrix(A, dtype=np.float64)
     s_win = max(abs(lmin), abs(lmax))
@@ -157,16 +182,20 @@ def feast(A, lmin, lmax, m0, nc, Q0, tol=1e-10, max_iter=20, form="residual",
     hist = []
     status = "no_convergence"
     it = 0
+    Qt = None  # the filtered block whose span Q is
     while True:
         theta, Q, R, res = rayleigh_ritz(A, Q, s_win)
-        inside = (theta >= lmin) & (theta <= lmax)
+        mu = filter_gain(Qt, Q) if Qt is not None else np.ones(Q.shape[1])
+        inside = (theta >= lmin) & (theta <= lmax) & (mu >= SPURIOUS_GAIN)
         M = int(inside.sum())
         if record:
-            hist.append(dict(Q=Q.copy(), theta=theta.copy(), res=res.copy(), M=M))
+            hist.append(dict(Q=Q.copy(), theta=theta.copy(), res=res.copy(), M=M, mu=mu.copy()))
         if M > 0 and float(res[inside].max()) <= tol:
             status = "ok"
             break
-        if M == 0 and it >= 2:
+        # empty: no Ritz value in the window at all (early gains can be small
+        # for true window vectors that the previous block held only weakly)
+        if not np.any((theta >= lmin) & (theta <= lmax)) and it >= 2:
             status = "empty_window"
             break
         if it >= max_iter:
@@ -180,7 +209,7 @@ def feast(A, lmin, lmax, m0, nc, Q0, tol=1e-10, max_iter=20, form="residual",
         status = "subspace_too_small"
     X = normalise_signs(Q[:, inside]) if M > 0 else np.zeros((A.shape[0], 0))
     return dict(lam=theta[inside], X=X, res=res[inside], M=M, iters=it,
-                status=status, theta_all=theta, res_all=res, Q=Q, history=hist)
+                status=status, theta_all=theta, res_all=res, mu_all=mu, Q=Q, history=hist)
 
 
 # -------------------------------------------------------------- warmstart ---

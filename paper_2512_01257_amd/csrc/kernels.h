@@ -143,6 +143,82 @@ size_t cocg_resident_lds(int n, bool fp32);
 hipError_t launch_cocg_resident(hipStream_t st, const SellMatrix& A, const CocgLaunch& L,
                                 bool fp32, int num_blocks);
 
+
+// ---- streaming COCG engine (any n) ------------------------------------------
+// All columns c < ncols solve (zc[c] I - A) d_c = b_{c mod k} in lock step;
+// vectors are n x Bp complex blocks, row-major, in the engine's row order
+// (engine row r is caller row perm[r]).  Columns are handled in groups of
+// 64 * stream_cpl(k, ncols, fp32) (CPL complex columns per lane); at most
+// kStreamMaxGroups groups.
+constexpr int kStreamMaxGroups = 128;
+struct StreamGroups {
+  int count;
+  int g[kStreamMaxGroups];    // group of blockIdx.y
+  int par[kStreamMaxGroups];  // which of the two p buffers holds the group's current p
+};
+struct StreamMatrix {
+  int n = 0;
+  const int* rowptr = nullptr;     // CSR in engine row order, columns renumbered
+  const int* col = nullptr;
+  const float* val32 = nullptr;
+  const double* val64 = nullptr;
+  const int* perm = nullptr;       // engine row -> caller row
+};
+struct StreamCols {                // per-column state, Bp entries (complex: 2 Bp)
+  int* state = nullptr;
+  int* it = nullptr;
+  int* nref = nullptr;
+  int* nbd = nullptr;
+  double* rho = nullptr;
+  double* alpha = nullptr;
+  double* beta = nullptr;
+  double* ctol2 = nullptr;
+  double* res = nullptr;
+  double* bn = nullptr;
+  int* lastit = nullptr;           // iteration count at the last check
+  int* span = nullptr;             // iterations between the last two checks (0: none yet)
+  int* span0 = nullptr;            // length of the first check interval after a (re)start
+  int* rstart = nullptr;           // iteration count at the last (re)start
+  double* sprev = nullptr;         // ||s||^2 at the last check (1 at the start)
+};
+struct StreamWork {
+  int Bp = 0;                      // stream_padded_columns(k, ncols, fp32)
+  int num_cu = 0;
+  void* x = nullptr;               // n x Bp complex (engine precision) each
+  void* r = nullptr;
+  void* p0 = nullptr;
+  void* p1 = nullptr;
+  void* w = nullptr;
+  void* xh = nullptr;              // n x Bp complex FP64
+  double* part = nullptr;          // stream_partial_doubles(n, Bp, num_cu)
+  double* zc = nullptr;            // [2 Bp] shift of each column (padding: any finite value)
+  double* scale = nullptr;         // [Bp]
+  int* cnt = nullptr;              // [2 * kStreamMaxGroups]
+  StreamCols cols;
+};
+struct StreamLaunch {
+  const double* B = nullptr;       // n x k RHS (FP64, caller row order), ldb
+  int ldb = 0;
+  int k = 0;
+  int ncols = 0;
+  void* D = nullptr;               // n x ncols complex outputs (caller row order), ldd
+  int ldd = 0;
+  double tol = 1e-6;
+  int maxit = 20000;
+  int max_updates = 64;            // FP64 residual checks that may continue a column
+  int chunk = 8;                   // iterations between host census reads
+  int* iters = nullptr;            // nullable [ncols]
+  double* resid = nullptr;         // nullable [ncols]
+  int* stats = nullptr;            // nullable [2]: refinements, breakdowns (accumulated)
+};
+int stream_cpl(int k, int ncols, bool fp32);
+int stream_padded_columns(int k, int ncols, bool fp32);
+int stream_blocks(int n, int num_cu);
+size_t stream_partial_doubles(int n, int Bp, int num_cu);
+// Runs to completion; synchronises `st` once per census (every `chunk` iterations).
+hipError_t run_stream_cocg(hipStream_t st, const StreamMatrix& A, const StreamWork& W,
+                           const StreamLaunch& L, bool fp32);
+
 }  // namespace rafeast
 
 namespace rafeast {

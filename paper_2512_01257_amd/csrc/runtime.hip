@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -22,6 +23,9 @@ namespace {
 thread_local std::string g_plan_error;
 
 constexpr int kMaxSmallK = 192;
+
+// Ritz pairs with a smaller filter gain are spurious (not counted in M).
+constexpr double kSpuriousGain = 0.25;
 
 }  // namespace
 
@@ -77,8 +81,21 @@ struct rafeast_plan_s {
   int* d_sel = nullptr;      // m0
   void* d_xhi = nullptr;     // FP64 solution scratch of the resident COCG engine
   size_t xhi_slots = 0;
+  // streaming engine: A in reverse Cuthill-McKee order, FP64 and FP32 values
+  int* d_srow = nullptr;
+  int* d_scol = nullptr;
+  float* d_sv32 = nullptr;
+  double* d_sv64 = nullptr;
+  int* d_sperm = nullptr;
+  StreamMatrix smat;
+  StreamWork swork;               // sized for the nc * m0 systems of a solve
+  std::vector<void*> sbufs;       // device buffers behind swork
   int nitems = 0;
   bool have_start = false;
+  // Q = Q~ mtot for the filtered block Q~ of the last iteration (CholQR2's
+  // transforms, k x k row-major, host); valid while have_filter
+  std::vector<double> mtot;
+  bool have_filter = false;
   int ws_used = RAFEAST_WS_NONE;
   std::string err;
   hipEvent_t ev[8] = {};
@@ -88,6 +105,16 @@ struct rafeast_plan_s {
 // helpers
 // ============================================================================
 namespace {
+
+// Progress lines on stderr, one per FEAST iteration, when RAFEAST_VERBOSE is
+// set to a non-empty value other than "0".
+bool verbose_log() {
+  static const bool on = [] {
+    const char* v = std::getenv("RAFEAST_VERBOSE");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
 
 rafeast_status fail(rafeast_plan_s* P, rafeast_status s, const std::string& msg) {
   if (P)
@@ -310,13 +337,156 @@ void free_plan(rafeast_plan_s* P) {
                   P->d_G,      P->d_M,    P->d_S,     P->d_Ssel,  P->d_jw,   P->d_theta,
                   P->d_res,    P->d_qn,   P->d_gamma, P->d_info,  P->d_zw,   P->d_part,
                   P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
-                  P->d_sel, P->d_xhi};
+                  P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm};
   for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (void* p : P->sbufs)
     if (p) (void)hipFree(p);
   for (auto& e : P->ev)
     if (e) (void)hipEventDestroy(e);
   if (P->own_stream && P->st) (void)hipStreamDestroy(P->st);
   delete P;
+}
+
+// Reverse Cuthill-McKee order of the graph of A (diagonal ignored): per
+// connected component, breadth-first search from a pseudo-peripheral vertex
+// (George-Liu: restart from a lowest-degree vertex of the last level while
+// the eccentricity grows), neighbours taken by increasing degree, and the
+// whole sequence reversed.  Returns perm with perm[new] = old.
+std::vector<int> rcm_order(int64_t n, const std::vector<int>& rp, const std::vector<int>& cl) {
+  std::vector<int> deg(n);
+  for (int64_t i = 0; i < n; ++i) {
+    int d = 0;
+    for (int t = rp[i]; t < rp[i + 1]; ++t) d += cl[t] != i;
+    deg[i] = d;
+  }
+  std::vector<int> by_deg(n);
+  for (int64_t i = 0; i < n; ++i) by_deg[i] = (int)i;
+  std::stable_sort(by_deg.begin(), by_deg.end(), [&](int a, int b) { return deg[a] < deg[b]; });
+  std::vector<char> done(n, 0);
+  std::vector<int> stamp(n, -1), level(n, 0), order;
+  order.reserve(n);
+  int stamp_id = 0;
+  std::vector<int> q;
+  q.reserve(n);
+  // BFS over undone vertices from s; returns the eccentricity and a
+  // lowest-degree vertex of the last level.
+  auto bfs_levels = [&](int s, int& far) {
+    ++stamp_id;
+    q.clear();
+    q.push_back(s);
+    stamp[s] = stamp_id;
+    level[s] = 0;
+    int ecc = 0;
+    for (size_t h = 0; h < q.size(); ++h) {
+      const int u = q[h];
+      for (int t = rp[u]; t < rp[u + 1]; ++t) {
+        const int v = cl[t];
+        if (v == u || done[v] || stamp[v] == stamp_id) continue;
+        stamp[v] = stamp_id;
+        level[v] = level[u] + 1;
+        ecc = std::max(ecc, level[v]);
+        q.push_back(v);
+      }
+    }
+    far = s;
+    for (int v : q)
+      if (level[v] == ecc && (far == s || deg[v] < deg[far])) far = v;
+    return ecc;
+  };
+  std::vector<int> nb;
+  for (int s0 : by_deg) {
+    if (done[s0]) continue;
+    int s = s0, far = s0;
+    int ecc = bfs_levels(s, far);
+    for (int rep = 0; rep < 16 && far != s; ++rep) {
+      int far2 = far;
+      const int e2 = bfs_levels(far, far2);
+      if (e2 <= ecc) break;
+      s = far;
+      ecc = e2;
+      far = far2;
+    }
+    // Cuthill-McKee sweep of this component
+    const size_t first = order.size();
+    order.push_back(s);
+    done[s] = 1;
+    for (size_t h = first; h < order.size(); ++h) {
+      const int u = order[h];
+      nb.clear();
+      for (int t = rp[u]; t < rp[u + 1]; ++t) {
+        const int v = cl[t];
+        if (v != u && !done[v]) {
+          done[v] = 1;
+          nb.push_back(v);
+        }
+      }
+      std::sort(nb.begin(), nb.end(),
+                [&](int a, int b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; });
+      order.insert(order.end(), nb.begin(), nb.end());
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+// Device buffers of a streaming-engine workspace for Bp columns.
+rafeast_status alloc_stream_work(rafeast_plan_s* P, int Bp, StreamWork& W,
+                                 std::vector<void*>& bufs) {
+  const int64_t n = P->n;
+  const size_t cs = P->fp32 ? 2 * sizeof(float) : 2 * sizeof(double);
+  auto get = [&](void** ptr, size_t bytes, const char* what) -> rafeast_status {
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+      *ptr = nullptr;
+      return hip_fail(P, e, what);
+    }
+    bufs.push_back(*ptr);
+    return RAFEAST_OK;
+  };
+  W = StreamWork{};
+  W.Bp = Bp;
+  W.num_cu = P->num_cu;
+  const size_t blk = (size_t)n * Bp;
+  RCHK(get(&W.x, blk * cs, "stream x"));
+  RCHK(get(&W.r, blk * cs, "stream r"));
+  RCHK(get(&W.p0, blk * cs, "stream p"));
+  RCHK(get(&W.p1, blk * cs, "stream p'"));
+  RCHK(get(&W.w, blk * cs, "stream w"));
+  RCHK(get(&W.xh, blk * 2 * sizeof(double), "stream x_hi"));
+  RCHK(get((void**)&W.part, stream_partial_doubles((int)n, Bp, P->num_cu) * sizeof(double),
+           "stream partials"));
+  RCHK(get((void**)&W.zc, 2 * (size_t)Bp * sizeof(double), "stream shifts"));
+  RCHK(get((void**)&W.scale, (size_t)Bp * sizeof(double), "stream scale"));
+  RCHK(get((void**)&W.cnt, 2 * kStreamMaxGroups * sizeof(int), "stream census"));
+  RCHK(get((void**)&W.cols.state, (size_t)Bp * sizeof(int), "stream state"));
+  RCHK(get((void**)&W.cols.it, (size_t)Bp * sizeof(int), "stream it"));
+  RCHK(get((void**)&W.cols.nref, (size_t)Bp * sizeof(int), "stream nref"));
+  RCHK(get((void**)&W.cols.nbd, (size_t)Bp * sizeof(int), "stream nbd"));
+  RCHK(get((void**)&W.cols.rho, 2 * (size_t)Bp * sizeof(double), "stream rho"));
+  RCHK(get((void**)&W.cols.alpha, 2 * (size_t)Bp * sizeof(double), "stream alpha"));
+  RCHK(get((void**)&W.cols.beta, 2 * (size_t)Bp * sizeof(double), "stream beta"));
+  RCHK(get((void**)&W.cols.ctol2, (size_t)Bp * sizeof(double), "stream ctol"));
+  RCHK(get((void**)&W.cols.res, (size_t)Bp * sizeof(double), "stream res"));
+  RCHK(get((void**)&W.cols.bn, (size_t)Bp * sizeof(double), "stream bn"));
+  RCHK(get((void**)&W.cols.lastit, (size_t)Bp * sizeof(int), "stream lastit"));
+  RCHK(get((void**)&W.cols.span, (size_t)Bp * sizeof(int), "stream span"));
+  RCHK(get((void**)&W.cols.span0, (size_t)Bp * sizeof(int), "stream span0"));
+  RCHK(get((void**)&W.cols.rstart, (size_t)Bp * sizeof(int), "stream rstart"));
+  RCHK(get((void**)&W.cols.sprev, (size_t)Bp * sizeof(double), "stream sprev"));
+  return RAFEAST_OK;
+}
+
+// Shift of each streaming column: column c = j * k + i takes z_j; padding
+// columns repeat z_0.
+std::vector<double> stream_shifts(int nz, const double* z, int k, int Bp) {
+  std::vector<double> zc(2 * (size_t)Bp);
+  for (int c = 0; c < Bp; ++c) {
+    const int j = c < nz * k ? c / k : 0;
+    zc[2 * c] = z[2 * j];
+    zc[2 * c + 1] = z[2 * j + 1];
+  }
+  return zc;
 }
 
 // ----------------------------------------------------------------------------
@@ -332,9 +502,16 @@ rafeast_status spmm(rafeast_plan_s* P, int k, const double* X, int ldx, double* 
 
 // CholQR2 on Y (n x k, ld) in place through P->d_T; *info as in rafeast_cholqr2.
 rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, int* info,
-                       double* tmp, int ldt) {
+                       double* tmp, int ldt, std::vector<double>* mtot = nullptr) {
   int worst = 0;
   int passes = 2;
+  std::vector<double> hm, prod;
+  if (mtot) {
+    mtot->assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) (*mtot)[(size_t)i * k + i] = 1.0;
+    hm.resize((size_t)k * k);
+    prod.resize((size_t)k * k);
+  }
   for (int pass = 0; pass < passes; ++pass) {
     HIPCHK(P, launch_gram(P->st, n, k, k, Y, ldy, Y, ldy, P->d_G, k, P->d_part));
     HIPCHK(P, launch_chol_inv(P->st, k, n, P->d_G, k, P->d_M, k, P->d_flag));
@@ -347,6 +524,18 @@ rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, 
     }
     if (flag == 1 && pass == 0) passes = 3;
     worst = std::max(worst, flag);
+    if (mtot) {  // mtot <- mtot * M of this pass
+      HIPCHK(P, hipMemcpyAsync(hm.data(), P->d_M, hm.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, P->st));
+      HIPCHK(P, hipStreamSynchronize(P->st));
+      for (int r = 0; r < k; ++r)
+        for (int c = 0; c < k; ++c) {
+          double a = 0.0;
+          for (int t = 0; t < k; ++t) a += (*mtot)[(size_t)r * k + t] * hm[(size_t)t * k + c];
+          prod[(size_t)r * k + c] = a;
+        }
+      mtot->swap(prod);
+    }
     HIPCHK(P, launch_tsmm(P->st, n, k, k, Y, ldy, P->d_M, k, tmp, ldt));
     HIPCHK(P, launch_copy_cols(P->st, n, k, tmp, ldt, Y, ldy));
   }
@@ -357,7 +546,7 @@ rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, 
 // Rayleigh-Ritz on Q (n x m0): theta, rotated Q and W = A Q, residual block R,
 // scaled residual norms; theta and res copied to the host arrays.
 rafeast_status rayleigh_ritz(rafeast_plan_s* P, std::vector<double>& theta,
-                             std::vector<double>& res) {
+                             std::vector<double>& res, std::vector<double>& mu) {
   const int m0 = P->m0, ld = P->ld;
   const int64_t n = P->n;
   RCHK(spmm(P, m0, P->d_Q, ld, P->d_W, ld, 1.0, 0.0));
@@ -376,7 +565,29 @@ rafeast_status rayleigh_ritz(rafeast_plan_s* P, std::vector<double>& theta,
                            P->st));
   HIPCHK(P, hipMemcpyAsync(res.data(), P->d_res, m0 * sizeof(double), hipMemcpyDeviceToHost,
                            P->st));
+  std::vector<double> S;
+  if (P->have_filter) {
+    S.resize((size_t)m0 * m0);
+    HIPCHK(P, hipMemcpyAsync(S.data(), P->d_S, S.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             P->st));
+  }
   HIPCHK(P, hipStreamSynchronize(P->st));
+  // filter gain of each Ritz vector q_i = Q~ y_i, y_i = mtot S e_i, of the
+  // orthonormal block Q_prev that Q~ filtered: mu_i = 1 / ||y_i|| =
+  // ||rho(A) Q_prev y_i|| / ||Q_prev y_i||; 1 before the first filter step
+  mu.assign(m0, 1.0);
+  if (P->have_filter) {
+    const std::vector<double>& Mt = P->mtot;
+    for (int i = 0; i < m0; ++i) {
+      double ss = 0.0;
+      for (int r = 0; r < m0; ++r) {
+        double y = 0.0;
+        for (int t = 0; t < m0; ++t) y += Mt[(size_t)r * m0 + t] * S[(size_t)t * m0 + i];
+        ss += y * y;
+      }
+      mu[i] = ss > 0.0 ? 1.0 / std::sqrt(ss) : 0.0;
+    }
+  }
   return RAFEAST_OK;
 }
 
@@ -404,6 +615,28 @@ rafeast_status run_cocg(rafeast_plan_s* P, int nitems, const int* d_items, const
   L.xhi_slots = P->xhi_slots;
   HIPCHK(P, hipMemsetAsync(P->d_counter, 0, sizeof(int), P->st));
   HIPCHK(P, launch_cocg_resident(P->st, P->sell, L, P->fp32, P->num_cu));
+  return RAFEAST_OK;
+}
+
+// Streaming engine: all nz * k systems of one solve in lock step.  W must be
+// sized for stream_padded_columns(k, nz * k) columns, with W.zc filled by
+// stream_shifts.
+rafeast_status run_stream(rafeast_plan_s* P, const StreamWork& W, int nz, int k, const double* B,
+                          int ldb, void* D, int ldd, double tol, int* d_iters,
+                          double* d_resid = nullptr) {
+  StreamLaunch L;
+  L.B = B;
+  L.ldb = ldb;
+  L.k = k;
+  L.ncols = nz * k;
+  L.D = D;
+  L.ldd = ldd;
+  L.tol = tol;
+  L.maxit = P->prm.max_cocg;
+  L.iters = d_iters;
+  L.resid = d_resid;
+  L.stats = P->d_stats;
+  HIPCHK(P, run_stream_cocg(P->st, P->smat, W, L, P->fp32));
   return RAFEAST_OK;
 }
 
@@ -511,14 +744,21 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
                 "m0 + p = " + std::to_string(w) + " exceeds the small-matrix limit 192");
   const bool fp32 = prm->precision == RAFEAST_FP32_REFINED;
   int engine = prm->engine;
-  if (engine == RAFEAST_ENGINE_AUTO) engine = RAFEAST_ENGINE_RESIDENT;
-  if (engine == RAFEAST_ENGINE_STREAM)
-    return fail(nullptr, RAFEAST_UNSUPPORTED, "streaming COCG engine not available");
-  if (n > cocg_resident_max_n(fp32))
+  if (engine == RAFEAST_ENGINE_RESIDENT && n > cocg_resident_max_n(fp32))
     return fail(nullptr, RAFEAST_UNSUPPORTED,
                 "n too large for the resident COCG engine at this precision");
+  if (engine == RAFEAST_ENGINE_AUTO && n > cocg_resident_max_n(fp32))
+    engine = RAFEAST_ENGINE_STREAM;
   if ((int64_t)prm->nc * prm->m0 > (int64_t)1 << 20)
     return fail(nullptr, RAFEAST_UNSUPPORTED, "nc * m0 too large");
+  {
+    // the streaming engine is the fallback of AUTO, so its limits apply to both
+    const int ncols = prm->nc * prm->m0;
+    const int gw = 64 * stream_cpl(prm->m0, ncols, fp32);
+    if (engine != RAFEAST_ENGINE_RESIDENT && (ncols + gw - 1) / gw > kStreamMaxGroups)
+      return fail(nullptr, RAFEAST_UNSUPPORTED,
+                  "nc * m0 exceeds the streaming engine's column limit");
+  }
 
   int ndev = 0;
   hipError_t he = hipGetDeviceCount(&ndev);
@@ -598,6 +838,7 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
       PCHK(hipMemcpy(P->d_col, cl.data(), nnz * sizeof(int), hipMemcpyHostToDevice));
       PCHK(hipMemcpy(P->d_val, A->values, nnz * sizeof(double), hipMemcpyHostToDevice));
     }
+    if (engine != RAFEAST_ENGINE_STREAM) {
     // SELL-64 of the resident engine: rows sorted by decreasing length (ties
     // by index), slices of 64 slots, widths padded to a multiple of 4
     const int nsl = (int)((n + 63) / 64);
@@ -672,11 +913,63 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
         break;
       }
     }
-    if (rpt == 0) return bail(fail(P, RAFEAST_UNSUPPORTED, "matrix does not fit the resident engine"));
-    PRCHK(dalloc(P, &P->d_wtab, tab.size(), "wave table"));
-    PCHK(hipMemcpy(P->d_wtab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
-    P->sell.wave_slices = P->d_wtab;
-    P->sell.wave_rpt = rpt;
+    if (rpt == 0 && engine == RAFEAST_ENGINE_RESIDENT)
+      return bail(fail(P, RAFEAST_UNSUPPORTED, "matrix does not fit the resident engine"));
+    if (rpt == 0) {
+      engine = RAFEAST_ENGINE_STREAM;  // AUTO: rows too long for the on-chip layout
+    } else {
+      engine = RAFEAST_ENGINE_RESIDENT;
+      PRCHK(dalloc(P, &P->d_wtab, tab.size(), "wave table"));
+      PCHK(hipMemcpy(P->d_wtab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+      P->sell.wave_slices = P->d_wtab;
+      P->sell.wave_rpt = rpt;
+    }
+    }
+    if (engine == RAFEAST_ENGINE_STREAM) {
+      // CSR of the streaming engine in reverse Cuthill-McKee order, so that
+      // the rows a workgroup gathers sit close to its own
+      const std::vector<int> perm = rcm_order(n, rp, cl);
+      std::vector<int> inv(n);
+      for (int64_t r = 0; r < n; ++r) inv[perm[r]] = (int)r;
+      std::vector<int> srp(n + 1, 0), scl(nnz);
+      std::vector<double> sv(nnz);
+      std::vector<float> sv32(nnz);
+      std::vector<std::pair<int, double>> row;
+      for (int64_t r = 0; r < n; ++r) {
+        const int o = perm[r];
+        row.clear();
+        for (int t = rp[o]; t < rp[o + 1]; ++t) row.emplace_back(inv[cl[t]], A->values[t]);
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int, double>& a, const std::pair<int, double>& b) {
+                    return a.first < b.first;
+                  });
+        srp[r + 1] = srp[r] + (int)row.size();
+        for (size_t u = 0; u < row.size(); ++u) {
+          scl[srp[r] + u] = row[u].first;
+          sv[srp[r] + u] = row[u].second;
+          sv32[srp[r] + u] = (float)row[u].second;
+        }
+      }
+      PRCHK(dalloc(P, &P->d_srow, n + 1, "stream rowptr"));
+      PRCHK(dalloc(P, &P->d_scol, nnz, "stream colind"));
+      PRCHK(dalloc(P, &P->d_sv64, nnz, "stream values"));
+      PRCHK(dalloc(P, &P->d_sv32, nnz, "stream values fp32"));
+      PRCHK(dalloc(P, &P->d_sperm, n, "stream perm"));
+      PCHK(hipMemcpy(P->d_srow, srp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+      PCHK(hipMemcpy(P->d_sperm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice));
+      if (nnz) {
+        PCHK(hipMemcpy(P->d_scol, scl.data(), nnz * sizeof(int), hipMemcpyHostToDevice));
+        PCHK(hipMemcpy(P->d_sv64, sv.data(), nnz * sizeof(double), hipMemcpyHostToDevice));
+        PCHK(hipMemcpy(P->d_sv32, sv32.data(), nnz * sizeof(float), hipMemcpyHostToDevice));
+      }
+      P->smat.n = (int)n;
+      P->smat.rowptr = P->d_srow;
+      P->smat.col = P->d_scol;
+      P->smat.val32 = P->d_sv32;
+      P->smat.val64 = P->d_sv64;
+      P->smat.perm = P->d_sperm;
+    }
+    P->engine = engine;
   }
 
   // workspace
@@ -712,10 +1005,15 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
   PRCHK(dalloc(P, &P->d_stats, 2, "stats"));
   PRCHK(dalloc(P, &P->d_flag, 1, "flag"));
   PRCHK(dalloc(P, &P->d_sel, P->m0, "sel"));
-  P->xhi_slots = cocg_resident_xhi_slots((int)n, P->num_cu);
-  {
+  if (P->engine == RAFEAST_ENGINE_RESIDENT) {
+    P->xhi_slots = cocg_resident_xhi_slots((int)n, P->num_cu);
     hipError_t e = hipMalloc(&P->d_xhi, P->xhi_slots * 2 * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(P, e, "solution scratch"));
+  } else {
+    const int Bp = stream_padded_columns(P->m0, P->nc * P->m0, fp32);
+    PRCHK(alloc_stream_work(P, Bp, P->swork, P->sbufs));
+    const std::vector<double> zc = stream_shifts(P->nc, P->zw.data(), P->m0, Bp);
+    PCHK(hipMemcpy(P->swork.zc, zc.data(), zc.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   PCHK(hipMemcpy(P->d_zw, P->zw.data(), 4 * P->nc * sizeof(double), hipMemcpyHostToDevice));
   {
@@ -727,6 +1025,26 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
 #undef PCHK
 #undef PRCHK
   *out = P;
+  return RAFEAST_OK;
+}
+
+int32_t rafeast_plan_engine(rafeast_plan_t P) { return P ? P->engine : 0; }
+
+rafeast_status rafeast_rcm_order(const rafeast_csr* A, int32_t* perm) {
+  if (!A || !perm || !A->rowptr || !A->colind || !A->values)
+    return fail(nullptr, RAFEAST_INVALID_ARG, "null argument");
+  std::string msg;
+  int64_t nnz = 0;
+  double anorm = 0, lo = 0, hi = 0;
+  rafeast_status s = validate_csr(A, nnz, anorm, lo, hi, msg);
+  if (s != RAFEAST_OK) return fail(nullptr, s, msg);
+  const int64_t n = A->n;
+  const int base = A->index_base;
+  std::vector<int> rp(n + 1), cl(nnz);
+  for (int64_t i = 0; i <= n; ++i) rp[i] = A->rowptr[i] - base;
+  for (int64_t t = 0; t < nnz; ++t) cl[t] = A->colind[t] - base;
+  const std::vector<int> ord = rcm_order(n, rp, cl);
+  std::memcpy(perm, ord.data(), n * sizeof(int32_t));
   return RAFEAST_OK;
 }
 
@@ -852,7 +1170,14 @@ rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_res
     if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "random start is rank deficient");
   }
   HIPCHK(P, hipMemsetAsync(P->d_stats, 0, 2 * sizeof(int), P->st));
-  std::vector<double> theta, rs;
+  P->have_filter = false;
+  std::vector<double> theta, rs, mu;
+  // counted pairs: theta in the closed window and filter gain >= 1/4 (an
+  // eigenvector in the window has gain |rho| >= 1/2; a mixture of outside
+  // eigenvectors whose Ritz value falls in the window has a small gain)
+  auto counted = [&](int i) {
+    return theta[i] >= lmin && theta[i] <= lmax && mu[i] >= kSpuriousGain;
+  };
   std::vector<int> iters(P->nitems);
   rafeast_status status = RAFEAST_NO_CONVERGENCE;
   int it = 0, M = 0;
@@ -863,12 +1188,14 @@ rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_res
   const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
   for (;; ++it) {
     HIPCHK(P, hipEventRecord(P->ev[0], P->st));
-    RCHK(rayleigh_ritz(P, theta, rs));
+    RCHK(rayleigh_ritz(P, theta, rs, mu));
     HIPCHK(P, hipEventRecord(P->ev[1], P->st));
     M = 0;
     maxres = 0.0;
+    int in_window = 0;  // Ritz values in the window, spurious or not
+    for (int i = 0; i < m0; ++i) in_window += theta[i] >= lmin && theta[i] <= lmax;
     for (int i = 0; i < m0; ++i)
-      if (theta[i] >= lmin && theta[i] <= lmax) {
+      if (counted(i)) {
         ++M;
         maxres = std::max(maxres, rs[i]);
       }
@@ -876,15 +1203,19 @@ rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_res
       status = RAFEAST_OK;
       break;
     }
-    if (M == 0 && it >= 2) {
+    if (in_window == 0 && it >= 2) {
       status = RAFEAST_EMPTY_WINDOW;
       break;
     }
     if (it >= P->prm.max_iter) break;
     // shifted solves for all (node, column) pairs
     HIPCHK(P, hipEventRecord(P->ev[2], P->st));
-    RCHK(run_cocg(P, P->nitems, P->d_items, P->d_zw, m0, residual_form ? P->d_R : P->d_Q, ld,
-                  P->d_D, nc * m0, P->prm.tol_solve, P->d_iters));
+    if (P->engine == RAFEAST_ENGINE_STREAM)
+      RCHK(run_stream(P, P->swork, nc, m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D, nc * m0,
+                      P->prm.tol_solve, P->d_iters));
+    else
+      RCHK(run_cocg(P, P->nitems, P->d_items, P->d_zw, m0, residual_form ? P->d_R : P->d_Q, ld,
+                    P->d_D, nc * m0, P->prm.tol_solve, P->d_iters));
     HIPCHK(P, hipEventRecord(P->ev[3], P->st));
     HIPCHK(P, hipMemcpyAsync(iters.data(), P->d_iters, P->nitems * sizeof(int),
                              hipMemcpyDeviceToHost, P->st));
@@ -895,7 +1226,8 @@ rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_res
     HIPCHK(P, hipEventRecord(P->ev[4], P->st));
     std::swap(P->d_Q, P->d_Y);
     int ci = 0;
-    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
+    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld, &P->mtot));
+    P->have_filter = ci != 2;
     HIPCHK(P, hipEventRecord(P->ev[5], P->st));
     HIPCHK(P, hipEventSynchronize(P->ev[5]));
     if (ci == 2) breakdown = true;
@@ -903,10 +1235,19 @@ rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_res
     t_ph[RAFEAST_PH_SOLVE] += elapsed(P->ev[2], P->ev[3]);
     t_ph[RAFEAST_PH_COMBINE] += elapsed(P->ev[3], P->ev[4]);
     t_ph[RAFEAST_PH_ORTH] += elapsed(P->ev[4], P->ev[5]);
+    int64_t it_sum = 0;
+    int it_max = 0;
     for (int v : iters) {
-      cocg_sum += v;
-      cocg_max = std::max(cocg_max, v);
+      it_sum += v;
+      it_max = std::max(it_max, v);
     }
+    cocg_sum += it_sum;
+    cocg_max = std::max(cocg_max, it_max);
+    if (verbose_log())
+      std::fprintf(stderr,
+                   "rafeast: iteration %d: M %d, max residual %.3e, COCG %lld (max %d), "
+                   "solve %.1f ms\n",
+                   it + 1, M, maxres, (long long)it_sum, it_max, elapsed(P->ev[2], P->ev[3]));
   }
   HIPCHK(P, hipEventSynchronize(P->ev[1]));
   t_ph[RAFEAST_PH_RR] += elapsed(P->ev[0], P->ev[1]);
@@ -916,7 +1257,7 @@ rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_res
   // outputs: in-window pairs, ascending (theta is sorted)
   std::vector<int> sel;
   for (int i = 0; i < m0; ++i)
-    if (theta[i] >= lmin && theta[i] <= lmax) sel.push_back(i);
+    if (counted(i)) sel.push_back(i);
   std::vector<double> lam(sel.size()), rsel(sel.size());
   for (size_t a = 0; a < sel.size(); ++a) {
     lam[a] = theta[sel[a]];
@@ -1044,7 +1385,31 @@ rafeast_status rafeast_shifted_solve(rafeast_plan_t P, int32_t nz, const double*
   if (e != hipSuccess) {
     s = hip_fail(P, e, "shifted_solve setup");
   } else {
-    s = run_cocg(P, nitems, d_items, d_z, k, B, ldb, X, nz * k, tol, d_it, d_rs);
+    if (P->engine == RAFEAST_ENGINE_STREAM) {
+      // a workspace of this call's width, released below
+      const int gw = 64 * stream_cpl(k, nitems, P->fp32);
+      const int Bp = stream_padded_columns(k, nitems, P->fp32);
+      std::vector<void*> bufs;
+      StreamWork W;
+      if (Bp / gw > kStreamMaxGroups)
+        s = fail(P, RAFEAST_UNSUPPORTED, "nz * k exceeds the streaming engine's column limit");
+      else
+        s = alloc_stream_work(P, Bp, W, bufs);
+      if (s == RAFEAST_OK) {
+        const std::vector<double> zc = stream_shifts(nz, z, k, Bp);
+        e = hipMemcpyAsync(W.zc, zc.data(), zc.size() * sizeof(double), hipMemcpyHostToDevice,
+                           P->st);
+        if (e != hipSuccess) s = hip_fail(P, e, "shifted_solve shifts");
+      }
+      if (s == RAFEAST_OK) s = run_stream(P, W, nz, k, B, ldb, X, nz * k, tol, d_it, d_rs);
+      if (s == RAFEAST_OK) {
+        e = hipStreamSynchronize(P->st);
+        if (e != hipSuccess) s = hip_fail(P, e, "shifted_solve");
+      }
+      for (void* b : bufs) (void)hipFree(b);
+    } else {
+      s = run_cocg(P, nitems, d_items, d_z, k, B, ldb, X, nz * k, tol, d_it, d_rs);
+    }
     if (s == RAFEAST_OK && iters) {
       e = hipMemcpyAsync(iters, d_it, nitems * sizeof(int), hipMemcpyDeviceToHost, P->st);
       if (e != hipSuccess) s = hip_fail(P, e, "copy iterations");

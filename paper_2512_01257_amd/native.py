@@ -95,6 +95,10 @@ def lib():
     L.rafeast_status_string.restype = C.c_char_p
     L.rafeast_plan_info.argtypes = [P, dp, dp, dp, C.POINTER(C.c_int64), dp, dp]
     L.rafeast_plan_info.restype = C.c_int
+    L.rafeast_plan_engine.argtypes = [P]
+    L.rafeast_plan_engine.restype = C.c_int32
+    L.rafeast_rcm_order.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32)]
+    L.rafeast_rcm_order.restype = C.c_int
     L.rafeast_spmm.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, C.c_double, C.c_double]
     L.rafeast_spmm.restype = C.c_int
     L.rafeast_gram.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int32, P, C.c_int32,
@@ -145,6 +149,22 @@ def _tptr(t, dtype=None):
     if dtype is not None and t.dtype != dtype:
         raise ValueError(f"expected {dtype}, got {t.dtype}")
     return C.c_void_p(t.data_ptr())
+
+
+def rcm_order(csr):
+    """Reverse Cuthill-McKee permutation (perm[new] = old) the streaming engine uses."""
+    L = lib()
+    rowptr = np.ascontiguousarray(csr.rowptr, dtype=np.int32)
+    colind = np.ascontiguousarray(csr.colind, dtype=np.int32)
+    values = np.ascontiguousarray(csr.values, dtype=np.float64)
+    A = Csr(int(csr.n), rowptr.ctypes.data_as(C.POINTER(C.c_int32)),
+            colind.ctypes.data_as(C.POINTER(C.c_int32)),
+            values.ctypes.data_as(C.POINTER(C.c_double)), 0)
+    perm = np.zeros(int(csr.n), dtype=np.int32)
+    st = L.rafeast_rcm_order(C.byref(A), perm.ctypes.data_as(C.POINTER(C.c_int32)))
+    if st != 0:
+        raise RafeastError(st, L.rafeast_last_error(None).decode())
+    return perm
 
 
 def default_params() -> Params:
@@ -212,6 +232,12 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def engine(self):
+        """COCG engine the plan resolved: "resident" or "stream"."""
+        e = lib().rafeast_plan_engine(self._h)
+        return {v: k for k, v in ENGINE.items()}[e]
 
     # ----------------------------------------------------------------- calls
     def info(self):

@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: CPU test taking more than ~20 s")
+    config.addinivalue_line("markers", "slow: test taking more than ~20 s on the CPU or minutes on the GPU")
 
 
 @pytest.fixture(scope="session")

@@ -10,6 +10,7 @@ import pytest
 from oracle import feast as F
 from oracle.subspace import sin_theta
 from tests.closed_forms import grid_eigs, window_basis
+from tests.feast_checks import check_against as _check_against, gap_out as _gap_out
 from workloads import gaussian, grid_laplacian, knn_laplacian, random_symmetric
 
 pytestmark = pytest.mark.gpu
@@ -18,32 +19,11 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 CFG1_WIN = (0.0, 0.20200934091026512)
 
 
-def _gap_out(all_eigs, lmin, lmax):
-    inside = all_eigs[(all_eigs >= lmin) & (all_eigs <= lmax)]
-    outside = all_eigs[(all_eigs < lmin) | (all_eigs > lmax)]
-    return np.min(np.abs(outside[:, None] - inside[None, :]))
-
-
-def _check_against(out, A, lam_ref, V_ref, lmin, lmax, tol_eig, gap):
-    s_win = max(abs(lmin), abs(lmax))
-    assert out["M"] == len(lam_ref)
-    assert np.abs(out["lam"] - lam_ref).max() <= 1e-10 * s_win
-    X = out["X"]
-    R = A @ X - X * out["lam"][None, :]
-    res = np.linalg.norm(R, axis=0) / s_win
-    assert res.max() <= tol_eig * 1.0001
-    np.testing.assert_allclose(out["resid"], res, rtol=1e-3, atol=1e-15)
-    assert np.abs(X.T @ X - np.eye(X.shape[1])).max() < 1e-12
-    st = sin_theta(X, V_ref).max()
-    assert st <= max(1e-8, 2 * np.linalg.norm(R) / gap), st
-    # sign convention: largest-magnitude entry positive
-    idx = np.argmax(np.abs(X), axis=0)
-    assert np.all(X[idx, np.arange(X.shape[1])] > 0)
-
-
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("mode", ["plain16", "ra4"])
-def test_grid2d_40x40(gpu_lib, precision, mode):
+@pytest.mark.parametrize("precision,mode,engine",
+                         [("fp32", "plain16", "auto"), ("fp64", "plain16", "auto"),
+                          ("fp32", "ra4", "auto"), ("fp64", "ra4", "auto"),
+                          ("fp32", "ra4", "stream"), ("fp64", "ra4", "stream")])
+def test_grid2d_40x40(gpu_lib, precision, mode, engine):
     dims, shift = (40, 40), 0.01
     csr = grid_laplacian(dims, shift)
     A = csr.to_scipy()
@@ -54,7 +34,8 @@ def test_grid2d_40x40(gpu_lib, precision, mode):
     gap = _gap_out(allv, lmin, lmax)
     nc = 16 if mode == "plain16" else 4
     with gpu_lib.Plan(csr, lmin, lmax, m0, nc=nc, q=2, p=10, precision=precision,
-                      ws_op="none" if mode == "plain16" else "auto") as plan:
+                      ws_op="none" if mode == "plain16" else "auto", engine=engine) as plan:
+        assert plan.engine == ("resident" if engine == "auto" else engine)
         om = gaussian(csr.n, plan.w, 0)
         ws = plan.warmstart(omega=om)
         out = plan.solve()
@@ -202,15 +183,16 @@ def _knn8000():
     return csr, win
 
 
-@pytest.mark.parametrize("nc,ws_op", [(4, "auto"), (16, "none")])
-def test_knn8000_parity(gpu_lib, nc, ws_op):
+@pytest.mark.parametrize("nc,ws_op,engine",
+                         [(4, "auto", "auto"), (16, "none", "auto"), (4, "auto", "stream")])
+def test_knn8000_parity(gpu_lib, nc, ws_op, engine):
     csr, win = _knn8000()
     A = csr.to_scipy()
     lmin, lmax = win["lmin"], win["lmax"]
     ev = np.array(win["eigenvalues"])
     m0, p = 64, 20
     with gpu_lib.Plan(csr, lmin, lmax, m0, nc=nc, q=2, p=p, tol_solve=1e-6, ws_op=ws_op,
-                      tol_eig=1e-12) as plan:
+                      tol_eig=1e-12, engine=engine) as plan:
         om = gaussian(csr.n, m0 + p, 0)
         plan.warmstart(omega=om)
         out = plan.solve()
@@ -227,3 +209,27 @@ def test_knn8000_parity(gpu_lib, nc, ws_op):
     R = A @ X - X * out["lam"][None, :]
     gap = ev[50] - ev[49]
     assert sin_theta(X, ref["X"]).max() <= max(1e-8, 2 * np.linalg.norm(R) / gap)
+
+
+def test_spurious_ritz_value_excluded(gpu_lib):
+    # diagonal A, window [-1, 1], outside pairs +-1.3 and +-1.8 of equal filter
+    # value: with m0 = 8 the subspace keeps one mixture of the +-1.8 pair whose
+    # Ritz value (seed 0) lies in the window; the filter-gain test drops it
+    import scipy.sparse as sp
+
+    from workloads import csr_from_scipy
+
+    inside = np.array([-0.7, -0.3, 0.1, 0.5, 0.8])
+    lam = np.concatenate([inside, [-1.3, 1.3, -1.8, 1.8], np.linspace(3.0, 20.0, 191)])
+    A = sp.diags(lam).tocsr()
+    csr = csr_from_scipy(A)
+    Q0 = np.random.default_rng(0).standard_normal((A.shape[0], 8))
+    ref = F.feast(A, -1.0, 1.0, 8, 4, Q0, tol=1e-12, max_iter=25)
+    assert ref["status"] == "ok" and ref["M"] == 5
+    for precision in ("fp64", "fp32"):
+        with gpu_lib.Plan(csr, -1.0, 1.0, 8, nc=4, q=1, p=4, precision=precision, tol_eig=1e-12,
+                          tol_solve=1e-8, max_iter=25) as plan:
+            out = plan.solve(Q_init=Q0)
+        assert out["status"] == "OK" and out["M"] == 5, (precision, out["status"], out["M"])
+        np.testing.assert_allclose(out["lam"], inside, atol=1e-12)
+        assert abs(out["iters"] - ref["iters"]) <= 1

@@ -136,8 +136,9 @@ def test_gaussian_matches_oracle_philox(small_plan, torch_dev, seed):
         np.testing.assert_allclose(O.cpu().numpy(), ref, rtol=1e-14, atol=1e-14)
 
 
+@pytest.mark.parametrize("engine", ["resident", "stream"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("fp32", 1e-10)])
-def test_shifted_solve_cocg(gpu_lib, torch_dev, precision, tol):
+def test_shifted_solve_cocg(gpu_lib, torch_dev, precision, tol, engine):
     torch = torch_dev
     csr = grid_laplacian((40, 40), 0.01)
     A = csr.to_scipy()
@@ -147,7 +148,8 @@ def test_shifted_solve_cocg(gpu_lib, torch_dev, precision, tol):
     rng = np.random.default_rng(5)
     k = 5
     B = rng.standard_normal((csr.n, k)) * np.array([1, 1e-8, 1e3, 1, 0])[None, :]
-    with _plan(gpu_lib, csr, precision=precision, m0=8) as plan:
+    with _plan(gpu_lib, csr, precision=precision, m0=8, engine=engine) as plan:
+        assert plan.engine == engine
         ct = torch.complex64 if precision == "fp32" else torch.complex128
         X = torch.zeros((csr.n, len(z) * k), dtype=ct, device="cuda")
         its, rs = plan.shifted_solve(z, torch.from_numpy(B).cuda(), X, tol)

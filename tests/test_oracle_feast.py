@@ -226,3 +226,53 @@ def test_default_oversampling_remark1():
     assert F.default_oversampling(50) == 10
     assert F.default_oversampling(64) == 20
     assert F.default_oversampling(128) == 20
+
+
+# --- spurious Ritz values (filter gain) -------------------------------------
+
+def _spurious_case():
+    """Diagonal A with window [-1, 1] and outside pairs +-1.3, +-1.8 that the
+    symmetric half-circle filter cannot tell apart; with m0 = 8 the subspace
+    holds the 5 window vectors, the +-1.3 pair and one fixed mixture of the
+    +-1.8 pair, whose Ritz value can fall inside the window."""
+    inside = [-0.7, -0.3, 0.1, 0.5, 0.8]
+    lam = np.array(inside + [-1.3, 1.3, -1.8, 1.8] + list(np.linspace(3.0, 20.0, 191)))
+    return sp.diags(lam).tocsr(), np.array(inside), lam
+
+
+def test_filter_gain_closed_form():
+    lam = np.array([0.2, 0.9, 1.4, 2.5])
+    z, w = half_circle(-1.0, 1.0, 4)
+    rho = filter_value(lam, z, w)
+    E = np.eye(4)
+    # eigenvectors: the gain is |rho(lambda)|
+    np.testing.assert_allclose(F.filter_gain(E * rho[None, :], E), np.abs(rho), rtol=1e-14)
+    # an equal mixture of e_0 and e_3: 1 / sqrt((1/rho_0^2 + 1/rho_3^2) / 2)
+    q = (E[:, [0]] + E[:, [3]]) / np.sqrt(2.0)
+    Qt = E[:, [0, 3]] * rho[[0, 3]][None, :]
+    g = F.filter_gain(Qt, q)[0]
+    assert abs(g - 1.0 / np.sqrt(0.5 / rho[0] ** 2 + 0.5 / rho[3] ** 2)) <= 1e-14 * g
+
+
+def test_spurious_ritz_value_is_excluded(monkeypatch):
+    A, inside, lam = _spurious_case()
+    n = A.shape[0]
+    z, w = half_circle(-1.0, 1.0, 4)
+    Q0 = np.random.default_rng(0).standard_normal((n, 8))
+    # counting every in-window Ritz value: the mixture of the +-1.8 pair stays
+    # in the window (its Ritz value does not move) and blocks convergence
+    monkeypatch.setattr(F, "SPURIOUS_GAIN", 0.0)
+    bad = F.feast(A, -1.0, 1.0, 8, 4, Q0, tol=1e-12, max_iter=25)
+    assert bad["status"] == "no_convergence" and bad["M"] == 6
+    spur = [i for i, t in enumerate(bad["theta_all"])
+            if -1 <= t <= 1 and np.min(np.abs(t - inside)) > 1e-6]
+    assert len(spur) == 1
+    g = abs(filter_value(np.array([1.8]), z, w)[0])
+    assert abs(bad["mu_all"][spur[0]] - g) <= 1e-8 * g
+    monkeypatch.undo()
+    # with the gain test: the five window eigenvalues, converged
+    out = F.feast(A, -1.0, 1.0, 8, 4, Q0, tol=1e-12, max_iter=25)
+    assert out["status"] == "ok" and out["M"] == 5
+    np.testing.assert_allclose(out["lam"], inside, atol=1e-12)
+    sel = (out["theta_all"] >= -1) & (out["theta_all"] <= 1) & (out["mu_all"] >= F.SPURIOUS_GAIN)
+    np.testing.assert_allclose(out["mu_all"][sel], np.abs(filter_value(inside, z, w)), rtol=1e-6)
