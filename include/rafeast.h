@@ -91,6 +91,7 @@ enum { RAFEAST_PH_RR = 0, RAFEAST_PH_SOLVE = 1, RAFEAST_PH_COMBINE = 2, RAFEAST_
        RAFEAST_PH_TOTAL = 4, RAFEAST_NPHASE = 5 };
 
 typedef struct rafeast_plan_s* rafeast_plan_t;
+typedef struct rafeast_batch_s* rafeast_batch_t;
 
 /* Symmetric matrix in CSR, host memory.  The full symmetric pattern is
  * required (a triangle-only input fails the symmetry check).  Within a row,
@@ -260,6 +261,51 @@ rafeast_status rafeast_shifted_solve(rafeast_plan_t plan, int32_t nz, const doub
  * even c takes sqrt(-2 ln u1) cos(2 pi u2), odd c the sin. */
 rafeast_status rafeast_gaussian(rafeast_plan_t plan, int32_t w, uint64_t seed, double* Omega,
                                 int32_t ld);
+
+/* ---------------------------------------------------------------------------
+ * Batching form: many independent problems (matrix, window, parameters) run
+ * their FEAST iterations in lock step.  In each iteration the shifted
+ * systems of every member that fits on chip (the resident engine) are solved
+ * in one persistent launch, replayed from a captured HIP graph: its work
+ * items are (member, node, column) triples, longest first across members.
+ * Members too large for the resident engine use the streaming engine after
+ * that launch.  The Rayleigh-Ritz, combination and CholQR2 steps run per
+ * member.  Each member computes exactly what rafeast_solve computes for it.
+ * ------------------------------------------------------------------------- */
+
+/* Plans count >= 1 problems: A[g] with prm[g] (host arrays of count).  All
+ * members must share precision, tol_solve and max_cocg (INVALID_ARG
+ * otherwise); prm[0].hip_stream (or a stream the batch creates) is used for
+ * all.  Errors as rafeast_plan, for the first member
+ * that fails (the text names it). */
+rafeast_status rafeast_plan_batch(int32_t count, const rafeast_csr* A, const rafeast_params* prm,
+                                  rafeast_batch_t* out);
+
+/* The plan of member g (0 <= g < count; NULL otherwise), owned by the batch:
+ * use it for rafeast_warmstart, rafeast_plan_info or rafeast_plan_engine;
+ * do not destroy it or call rafeast_solve on it while the batch is in use. */
+rafeast_plan_t rafeast_batch_plan(rafeast_batch_t batch, int32_t g);
+
+/* Phase 2 for all members.  Q_init: nullable host array of count nullable
+ * start blocks (as rafeast_solve).  res: host array of count results, each
+ * set up as for rafeast_solve.  status: nullable host [count], each member's
+ * rafeast_solve status.  t_ms: nullable host [RAFEAST_NPHASE], the batch's
+ * device time per phase (the solve phase is the shared launch plus
+ * streaming-engine solves).  Returns OK when every member returned OK, else
+ * the first non-OK member status (all members' results are written);
+ * failures of the device or arguments return at once. */
+rafeast_status rafeast_batch_solve(rafeast_batch_t batch, const double* const* Q_init,
+                                   rafeast_result* res, rafeast_status* status, double* t_ms);
+
+/* Members that ran on the resident engine in the shared launch. */
+int32_t rafeast_batch_resident_count(rafeast_batch_t batch);
+
+/* Releases the batch and its member plans.  NULL is a no-op. */
+void rafeast_batch_destroy(rafeast_batch_t batch);
+
+/* Text of the last error on the batch (NULL: the last failed
+ * rafeast_plan_batch). */
+const char* rafeast_batch_last_error(rafeast_batch_t batch);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,10 @@
 // reductions per iteration are workgroup reductions: no grid-wide
 // synchronisation, and systems with different iteration counts retire
 // independently.  Workgroups take systems from an atomic work counter in the
-// order given (longest first).
+// order given (longest first).  A work item names a graph, a shift and a
+// right-hand-side column, so one launch can serve the systems of several
+// matrices (the batching form); a workgroup reloads the graph's descriptor
+// only when its next item belongs to another graph.
 //
 // Per system: b is scaled to unit norm.  Mixed-precision iterative
 // refinement: each cycle runs COCG in T (float or double; per-thread sums in
@@ -126,43 +129,115 @@ __device__ __forceinline__ E load_entry(const E* __restrict__ base, unsigned idx
                                      idx * (unsigned)sizeof(E));
 }
 
-template <typename T, int RPT>
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) ResGraph ConstGraph;
+__device__ __forceinline__ ConstGraph* const_graph(const ResGraph* graphs, int g) {
+  return reinterpret_cast<ConstGraph*>((size_t)graphs) + g;
+}
+#else
+__device__ __forceinline__ const ResGraph* const_graph(const ResGraph* graphs, int g) {
+  return graphs + g;  // device-only function; the host pass never calls it
+}
+#endif
+
+// MULTI false: every item belongs to the graph whose fields are the scalar
+// kernel arguments (scalar loads from the argument segment).  MULTI true:
+// item (g, j, i) reads graphs[g] at its start; the scalar graph arguments
+// are unused.
+template <typename T, int RPT, bool MULTI>
 __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
-    int nslices, const int* __restrict__ sbase, const int* __restrict__ perm,
-    const typename EntryOf<T>::type* __restrict__ ent, const SellEntry64* __restrict__ ent64,
-    int nitems, const int* __restrict__ items, const double* __restrict__ zs,
-    const double* __restrict__ Bm, int ldb, int kcols, cpx<T>* __restrict__ D, int ldd,
-    double tol, int maxit, int max_refine, int* __restrict__ counter, int* __restrict__ iters,
-    int* __restrict__ stats, double* __restrict__ resid_out, cpx<double>* __restrict__ xhi_all,
-    int zero_base, const int* __restrict__ wave_slices) {
+    int a_nslices, const int* __restrict__ a_sbase, const int* __restrict__ a_perm,
+    const void* __restrict__ a_ent, const SellEntry64* __restrict__ a_ent64, int nitems,
+    const int* __restrict__ items, const double* __restrict__ a_zs,
+    const double* __restrict__ a_B, int a_ldb, int a_kcols, void* __restrict__ a_D, int a_ldd,
+    double tol, int maxit, int max_refine, int* __restrict__ counter, int* __restrict__ a_iters,
+    int* __restrict__ a_stats, double* __restrict__ a_resid, cpx<double>* __restrict__ xhi_all,
+    int a_zero_base, const int* __restrict__ a_wave_slices, const ResGraph* __restrict__ graphs,
+    int max_npad) {
   // Dynamic LDS only (so p starts at address 0 and a gather address is the
-  // entry's stored byte offset): p | r | reduction slots | work item.
+  // entry's stored byte offset): p | r (sized for the graph of the current
+  // item) ... reduction slots | work item (after room for the largest graph).
   extern __shared__ unsigned char smem_raw[];
-  const int npad = nslices * 64;
   cpx<T>* P = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* R = P + npad;
-  double(*red)[kResWaves][4] =
-      reinterpret_cast<double(*)[kResWaves][4]>(smem_raw + (size_t)npad * 2 * sizeof(cpx<T>));
+  double(*red)[kResWaves][4] = reinterpret_cast<double(*)[kResWaves][4]>(
+      smem_raw + (size_t)max_npad * 2 * sizeof(cpx<T>));
   int& s_item = *reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(red) +
                                         2 * kResWaves * 4 * sizeof(double));
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double tol2 = tol * tol;
-  // this wave's slices (-1: none), widest first; fixed for the whole kernel
-  int slc[RPT];
+  cpx<double>* __restrict__ XH = xhi_all + (size_t)blockIdx.x * max_npad;
+
+  // The graph of the current item.  A descriptor from the array is read
+  // through the constant address space: scalar, invariant loads the compiler
+  // may repeat instead of keeping every field live in registers.  With a
+  // single graph, everything is read once, before the work loop.
+  int nslices = 0, zero_base = 0, ldb = 0, kcols = 0, ldd = 0;
+  const int* __restrict__ sbase = nullptr;
+  const int* __restrict__ perm = nullptr;
+  const typename EntryOf<T>::type* __restrict__ ent = nullptr;
+  const SellEntry64* __restrict__ ent64 = nullptr;
+  const double* __restrict__ Bm = nullptr;
+  cpx<T>* __restrict__ D = nullptr;
+  const double* __restrict__ zs = nullptr;
+  int* __restrict__ iters = nullptr;
+  double* __restrict__ resid_out = nullptr;
+  int* __restrict__ stats = nullptr;
+  cpx<T>* R = P;
+  int slc[RPT];  // this wave's slices (-1: none), widest first
+  auto load_graph = [&](const auto& G) {
+    nslices = G.nslices;
+    zero_base = G.zero_base;
+    ldb = G.ldb;
+    kcols = G.kcols;
+    ldd = G.ldd;
+    sbase = G.sbase;
+    perm = G.perm;
+    ent = reinterpret_cast<const typename EntryOf<T>::type*>(G.ent);
+    ent64 = G.ent64;
+    Bm = G.B;
+    D = reinterpret_cast<cpx<T>*>(G.D);
+    zs = G.zs;
+    iters = G.iters;
+    resid_out = G.resid;
+    stats = G.stats;
+    R = P + nslices * 64;
 #pragma unroll
-  for (int t = 0; t < RPT; ++t) slc[t] = wave_slices[wv * RPT + t];
-  cpx<double>* __restrict__ XH = xhi_all + (size_t)blockIdx.x * npad;
+    for (int t = 0; t < RPT; ++t) slc[t] = G.wave_slices[wv * RPT + t];
+  };
+  if constexpr (!MULTI) {
+    ResGraph g0;
+    g0.nslices = a_nslices;
+    g0.zero_base = a_zero_base;
+    g0.ldb = a_ldb;
+    g0.kcols = a_kcols;
+    g0.ldd = a_ldd;
+    g0.sbase = a_sbase;
+    g0.perm = a_perm;
+    g0.ent = a_ent;
+    g0.ent64 = a_ent64;
+    g0.wave_slices = a_wave_slices;
+    g0.B = a_B;
+    g0.D = a_D;
+    g0.zs = a_zs;
+    g0.iters = a_iters;
+    g0.resid = a_resid;
+    g0.stats = a_stats;
+    load_graph(g0);
+  }
 
   cpx<T> w[RPT], xr[RPT];
 
   for (;;) {
     if (tid == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
     if (item >= nitems) break;
-    const int j = items[2 * item], ci = items[2 * item + 1];
+    const int g = __builtin_amdgcn_readfirstlane(items[3 * item]);
+    const int j = __builtin_amdgcn_readfirstlane(items[3 * item + 1]);
+    const int ci = __builtin_amdgcn_readfirstlane(items[3 * item + 2]);
+    if constexpr (MULTI) load_graph(*const_graph(graphs, g));
     const double zr = zs[2 * j], zi = zs[2 * j + 1];
     const int ocol = j * kcols + ci;
 
@@ -483,47 +558,77 @@ size_t cocg_resident_lds(int n, bool fp32) {
          2 * kResWaves * 4 * sizeof(double) + 16;
 }
 
-template <typename T, int RPT>
-static hipError_t launch_res(hipStream_t st, const SellMatrix& A, const CocgLaunch& L,
-                             const typename EntryOf<T>::type* ent, int blocks) {
+template <typename T, int RPT, bool MULTI>
+static hipError_t launch_res(hipStream_t st, const ResGraph& g0, const ResGraph* graphs, int max_n,
+                             const CocgLaunch& L, int blocks) {
+  auto kern = k_cocg_resident<T, RPT, MULTI>;
   // the gathers address LDS absolutely: the kernel must own no static LDS
   hipFuncAttributes fa;
-  hipError_t fe = hipFuncGetAttributes(&fa, (const void*)k_cocg_resident<T, RPT>);
+  hipError_t fe = hipFuncGetAttributes(&fa, (const void*)kern);
   if (fe != hipSuccess) return fe;
   if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
-  const size_t lds = cocg_resident_lds(A.n, sizeof(T) == 4);
-  hipError_t e = hipFuncSetAttribute((const void*)k_cocg_resident<T, RPT>,
+  const size_t lds = cocg_resident_lds(max_n, sizeof(T) == 4);
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cocg_resident<T, RPT>), dim3(blocks), dim3(kResThreads), lds, st,
-                     A.nslices, A.sbase, A.perm, ent, A.e64, L.nitems, L.items, L.zs, L.B, L.ldb,
-                     L.k, (cpx<T>*)L.D, L.ldd, L.tol, L.maxit, L.max_refine, L.counter, L.iters,
-                     L.stats, L.resid, (cpx<double>*)L.xhi, A.zero_base, A.wave_slices);
+  const int max_npad = (max_n + 63) / 64 * 64;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kResThreads), lds, st, g0.nslices, g0.sbase,
+                     g0.perm, g0.ent, g0.ent64, L.nitems, L.items, g0.zs, g0.B, g0.ldb, g0.kcols,
+                     g0.D, g0.ldd, L.tol, L.maxit, L.max_refine, L.counter, g0.iters, g0.stats,
+                     g0.resid, (cpx<double>*)L.xhi, g0.zero_base, g0.wave_slices, graphs,
+                     max_npad);
   return hipGetLastError();
 }
 
-hipError_t launch_cocg_resident(hipStream_t st, const SellMatrix& A, const CocgLaunch& L,
-                                bool fp32, int num_blocks) {
-  if (A.n > cocg_resident_max_n(fp32)) return hipErrorInvalidValue;
-  // 32-bit indexing of the RHS and output blocks
-  if ((int64_t)A.n * L.ldb >= (int64_t(1) << 31) || (int64_t)A.n * L.ldd >= (int64_t(1) << 31))
+template <typename T, int RPT, bool MULTI>
+static hipError_t prepare_res(int max_n) {
+  const size_t lds = cocg_resident_lds(max_n, sizeof(T) == 4);
+  return hipFuncSetAttribute((const void*)k_cocg_resident<T, RPT, MULTI>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t prepare_cocg_resident(int max_n, int rpt, bool fp32) {
+  if (max_n < 1 || max_n > cocg_resident_max_n(fp32)) return hipErrorInvalidValue;
+  if (fp32) {
+    if (rpt == 1) return prepare_res<float, 1, true>(max_n);
+    if (rpt == 2) return prepare_res<float, 2, true>(max_n);
+    if (rpt == 4) return prepare_res<float, 4, true>(max_n);
+    if (rpt == 8) return prepare_res<float, 8, true>(max_n);
     return hipErrorInvalidValue;
+  }
+  if (rpt == 1) return prepare_res<double, 1, true>(max_n);
+  if (rpt == 2) return prepare_res<double, 2, true>(max_n);
+  if (rpt == 4) return prepare_res<double, 4, true>(max_n);
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int RPT>
+static hipError_t launch_res2(hipStream_t st, const ResGraph* g0, const ResGraph* graphs,
+                              int max_n, const CocgLaunch& L, int blocks) {
+  if (g0) return launch_res<T, RPT, false>(st, *g0, nullptr, max_n, L, blocks);
+  return launch_res<T, RPT, true>(st, ResGraph{}, graphs, max_n, L, blocks);
+}
+
+hipError_t launch_cocg_resident(hipStream_t st, const ResGraph* g0, const ResGraph* graphs,
+                                int max_n, int rpt, const CocgLaunch& L, bool fp32,
+                                int num_blocks) {
+  if (max_n < 1 || max_n > cocg_resident_max_n(fp32)) return hipErrorInvalidValue;
   if (L.nitems <= 0) return hipSuccess;
-  const int need = A.wave_rpt;  // slots per wave of the slice table
-  if (A.wave_slices == nullptr || !(need == 1 || need == 2 || need == 4 || need == 8))
-    return hipErrorInvalidValue;
+  if ((g0 == nullptr) == (graphs == nullptr)) return hipErrorInvalidValue;
+  if (!(rpt == 1 || rpt == 2 || rpt == 4 || rpt == 8)) return hipErrorInvalidValue;
   int blocks = num_blocks < L.nitems ? num_blocks : L.nitems;
   if (blocks < 1) blocks = 1;
-  if (L.xhi == nullptr || (size_t)blocks * A.nslices * 64 > L.xhi_slots) return hipErrorInvalidValue;
+  const size_t max_npad = (size_t)(max_n + 63) / 64 * 64;
+  if (L.xhi == nullptr || (size_t)blocks * max_npad > L.xhi_slots) return hipErrorInvalidValue;
   if (fp32) {
-    if (need == 1) return launch_res<float, 1>(st, A, L, A.e32, blocks);
-    if (need == 2) return launch_res<float, 2>(st, A, L, A.e32, blocks);
-    if (need == 4) return launch_res<float, 4>(st, A, L, A.e32, blocks);
-    return launch_res<float, 8>(st, A, L, A.e32, blocks);
+    if (rpt == 1) return launch_res2<float, 1>(st, g0, graphs, max_n, L, blocks);
+    if (rpt == 2) return launch_res2<float, 2>(st, g0, graphs, max_n, L, blocks);
+    if (rpt == 4) return launch_res2<float, 4>(st, g0, graphs, max_n, L, blocks);
+    return launch_res2<float, 8>(st, g0, graphs, max_n, L, blocks);
   }
-  if (need == 1) return launch_res<double, 1>(st, A, L, A.e64, blocks);
-  if (need == 2) return launch_res<double, 2>(st, A, L, A.e64, blocks);
-  if (need == 4) return launch_res<double, 4>(st, A, L, A.e64, blocks);
+  if (rpt == 1) return launch_res2<double, 1>(st, g0, graphs, max_n, L, blocks);
+  if (rpt == 2) return launch_res2<double, 2>(st, g0, graphs, max_n, L, blocks);
+  if (rpt == 4) return launch_res2<double, 4>(st, g0, graphs, max_n, L, blocks);
   return hipErrorInvalidValue;
 }
 

@@ -437,6 +437,18 @@ hipError_t launch_copy_cols(hipStream_t st, int64_t n, int k, const double* src,
   return hipGetLastError();
 }
 
+// p[0..n) = v.  A kernel, not a memset node, so it can sit in a captured graph.
+__global__ void k_fill_int(int* __restrict__ p, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_int(hipStream_t st, int* p, int v, int n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
 __global__ void k_row2col(int64_t n, int k, const double* __restrict__ src, int lds,
                           double* __restrict__ dst) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

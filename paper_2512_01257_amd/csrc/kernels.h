@@ -59,6 +59,8 @@ hipError_t launch_export_vectors(hipStream_t st, int64_t n, int cnt, const int* 
                                  const double* src, int lds, double* dst, double* part);
 hipError_t launch_copy_cols(hipStream_t st, int64_t n, int k, const double* src, int lds,
                             double* dst, int ldd);
+// p[0..n) = v by a kernel (usable inside a captured graph, unlike a memset).
+hipError_t launch_fill_int(hipStream_t st, int* p, int v, int n);
 
 // ---- small dense (one workgroup) ------------------------------------------------
 // M such that Y M has orthonormal columns for G = Y^T Y (k x k): column
@@ -109,24 +111,38 @@ struct SellMatrix {
   int wave_rpt = 0;                     // slots per wave (1, 2, 4 or 8)
 };
 
+// One matrix (graph) of a resident launch, with the right-hand sides and
+// outputs of its systems.  An item (g, j, i) solves (z_j I - A_g) d = B_g[:, i]
+// into column j * kcols + i of D_g.
+struct ResGraph {
+  int nslices = 0;
+  int zero_base = 0;
+  int ldb = 0;
+  int kcols = 0;                        // RHS columns of this graph
+  int ldd = 0;
+  int pad_ = 0;
+  const int* sbase = nullptr;           // SellMatrix fields of A_g
+  const int* perm = nullptr;
+  const void* ent = nullptr;            // SellEntry32 (FP32 engine) or SellEntry64
+  const SellEntry64* ent64 = nullptr;
+  const int* wave_slices = nullptr;     // table built for the launch's slots per wave
+  const double* B = nullptr;            // n_g x kcols RHS (FP64), ldb
+  void* D = nullptr;                    // n_g x (nz kcols) complex outputs, ldd
+  const double* zs = nullptr;           // shifts (re, im)
+  int* iters = nullptr;                 // [nz kcols] iterations per system
+  double* resid = nullptr;              // nullable [nz kcols] final relative true residual
+  int* stats = nullptr;                 // [2]: refinements, breakdowns (accumulated)
+};
+
 struct CocgLaunch {
   int nitems = 0;
-  const int* items = nullptr;   // [2*nitems] (shift j, column i), longest first
-  const double* zs = nullptr;   // [2*nz] shifts (re, im)
-  const double* B = nullptr;    // n x k RHS (FP64), ldb
-  int ldb = 0;
-  int k = 0;                    // RHS columns; output column of item = j*k + i
-  void* D = nullptr;            // n x (nz*k) complex outputs, ldd complex entries
-  int ldd = 0;
+  const int* items = nullptr;   // [3*nitems] (graph g, shift j, column i), longest first
   double tol = 1e-6;
   int maxit = 20000;
   int max_refine = 4;
   int* counter = nullptr;       // zeroed work counter
-  int* iters = nullptr;         // [nz*k] iterations per system
-  int* stats = nullptr;         // [2]: refinements, breakdowns (accumulated)
-  double* resid = nullptr;      // nullable [nz*k]: final relative true residual
   void* xhi = nullptr;          // FP64 complex solution scratch, xhi_slots entries
-  size_t xhi_slots = 0;         // >= blocks * nslices * 64
+  size_t xhi_slots = 0;         // >= blocks * (max_n rounded up to 64)
 };
 
 // FP64 scratch entries (complex) the resident engine needs for `blocks` workgroups.
@@ -140,8 +156,16 @@ int cocg_resident_waves();
 std::vector<int> cocg_resident_wave_table(const std::vector<int>& widths, int rpt);
 // Dynamic LDS bytes the resident engine needs for n.
 size_t cocg_resident_lds(int n, bool fp32);
-hipError_t launch_cocg_resident(hipStream_t st, const SellMatrix& A, const CocgLaunch& L,
-                                bool fp32, int num_blocks);
+// Sets the kernel attributes a resident launch for max_n and rpt needs (the
+// launch sets them too; call this before capturing one into a graph).
+hipError_t prepare_cocg_resident(int max_n, int rpt, bool fp32);
+// One persistent launch over all items of L.  Either g0 (host pointer; all
+// items name graph 0, passed by value) or graphs (device array of the graphs
+// the items name) is given.  max_n: the largest n among them; rpt: the slots
+// per wave every graph's wave table was built for.
+hipError_t launch_cocg_resident(hipStream_t st, const ResGraph* g0, const ResGraph* graphs,
+                                int max_n, int rpt, const CocgLaunch& L, bool fp32,
+                                int num_blocks);
 
 
 // ---- streaming COCG engine (any n) ------------------------------------------

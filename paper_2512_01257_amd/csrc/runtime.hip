@@ -81,6 +81,7 @@ struct rafeast_plan_s {
   int* d_sel = nullptr;      // m0
   void* d_xhi = nullptr;     // FP64 solution scratch of the resident COCG engine
   size_t xhi_slots = 0;
+  std::vector<int> sell_widths; // slice widths, for wave tables of other slot counts
   // streaming engine: A in reverse Cuthill-McKee order, FP64 and FP32 values
   int* d_srow = nullptr;
   int* d_scol = nullptr;
@@ -99,6 +100,31 @@ struct rafeast_plan_s {
   int ws_used = RAFEAST_WS_NONE;
   std::string err;
   hipEvent_t ev[8] = {};
+};
+
+// A batch: member plans sharing one stream, and the state of the shared
+// resident launch.
+struct rafeast_batch_s {
+  std::vector<rafeast_plan_s*> plans;
+  std::vector<int> res_idx;          // member -> slot in the descriptor array (-1: streaming)
+  std::vector<int*> wtab;            // member -> wave table for the common slot count
+  std::vector<int*> own_wtab;        // tables the batch allocated
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  bool fp32 = true;
+  int rpt = 0, max_n = 0, num_cu = 0, nres = 0;
+  ResGraph* d_graphs = nullptr;
+  std::vector<ResGraph> h_graphs;
+  int* d_items = nullptr;
+  std::vector<int> h_items;
+  int* d_counter = nullptr;
+  void* d_xhi = nullptr;
+  size_t xhi_slots = 0;
+  hipGraph_t graph = nullptr;        // captured counter reset + resident launch
+  hipGraphExec_t gexec = nullptr;
+  int graph_nitems = -1;             // the item count the capture was made for
+  hipEvent_t ev[2] = {};
+  std::string err;
 };
 
 // ============================================================================
@@ -591,30 +617,52 @@ rafeast_status rayleigh_ritz(rafeast_plan_s* P, std::vector<double>& theta,
   return RAFEAST_OK;
 }
 
-// COCG over items (j, i) of the given shift table; outputs into D.
+// The resident-launch descriptor of the plan's matrix with the given RHS,
+// outputs and shift table.
+ResGraph resident_graph(const rafeast_plan_s* P, const double* d_zs, int k, const double* B,
+                        int ldb, void* D, int ldd, int* d_iters, double* d_resid,
+                        const int* wave_slices) {
+  ResGraph gd;
+  gd.nslices = P->sell.nslices;
+  gd.zero_base = P->sell.zero_base;
+  gd.ldb = ldb;
+  gd.kcols = k;
+  gd.ldd = ldd;
+  gd.sbase = P->sell.sbase;
+  gd.perm = P->sell.perm;
+  gd.ent = P->fp32 ? (const void*)P->sell.e32 : (const void*)P->sell.e64;
+  gd.ent64 = P->sell.e64;
+  gd.wave_slices = wave_slices;
+  gd.B = B;
+  gd.D = D;
+  gd.zs = d_zs;
+  gd.iters = d_iters;
+  gd.resid = d_resid;
+  gd.stats = P->d_stats;
+  return gd;
+}
+
+// COCG over items (0, j, i) of the given shift table; outputs into D.
 rafeast_status run_cocg(rafeast_plan_s* P, int nitems, const int* d_items, const double* d_zs,
                         int k, const double* B, int ldb, void* D, int ldd, double tol,
                         int* d_iters, double* d_resid = nullptr) {
+  // 32-bit indexing of the RHS and output blocks inside the kernel
+  if (P->n * (int64_t)ldb >= (int64_t(1) << 31) || P->n * (int64_t)ldd >= (int64_t(1) << 31))
+    return fail(P, RAFEAST_UNSUPPORTED, "blocks too large for the resident engine");
+  const ResGraph gd =
+      resident_graph(P, d_zs, k, B, ldb, D, ldd, d_iters, d_resid, P->sell.wave_slices);
   CocgLaunch L;
   L.nitems = nitems;
   L.items = d_items;
-  L.zs = d_zs;
-  L.B = B;
-  L.ldb = ldb;
-  L.k = k;
-  L.D = D;
-  L.ldd = ldd;
   L.tol = tol;
   L.maxit = P->prm.max_cocg;
   L.max_refine = 4;
   L.counter = P->d_counter;
-  L.iters = d_iters;
-  L.stats = P->d_stats;
-  L.resid = d_resid;
   L.xhi = P->d_xhi;
   L.xhi_slots = P->xhi_slots;
   HIPCHK(P, hipMemsetAsync(P->d_counter, 0, sizeof(int), P->st));
-  HIPCHK(P, launch_cocg_resident(P->st, P->sell, L, P->fp32, P->num_cu));
+  HIPCHK(P, launch_cocg_resident(P->st, &gd, nullptr, (int)P->n, P->sell.wave_rpt, L, P->fp32,
+                                 P->num_cu));
   return RAFEAST_OK;
 }
 
@@ -642,15 +690,16 @@ rafeast_status run_stream(rafeast_plan_s* P, const StreamWork& W, int nz, int k,
 
 // Orders (shift, column) pairs longest-first: the smaller Im z, the more COCG
 // iterations a system needs.
-std::vector<int> make_items(int nz, const double* zs, int k) {
+std::vector<int> make_items(int nz, const double* zs, int k, int g = 0) {
   std::vector<int> js(nz);
   for (int j = 0; j < nz; ++j) js[j] = j;
   std::stable_sort(js.begin(), js.end(),
                    [&](int a, int b) { return std::fabs(zs[2 * a + 1]) < std::fabs(zs[2 * b + 1]); });
   std::vector<int> items;
-  items.reserve(2 * nz * k);
+  items.reserve(3 * (size_t)nz * k);
   for (int j : js)
     for (int i = 0; i < k; ++i) {
+      items.push_back(g);
       items.push_back(j);
       items.push_back(i);
     }
@@ -669,6 +718,189 @@ int resolve_ws_op(const rafeast_plan_s* P) {
   if (P->prm.lmin <= P->sig_lo) return RAFEAST_WS_FLIP;
   if (P->prm.lmax >= P->sig_hi) return RAFEAST_WS_LITERAL;
   return RAFEAST_WS_FOLD;
+}
+
+// ----------------------------------------------------------------------------
+// Phase 2 in steps (one plan, or several in lock step for the batching form)
+// ----------------------------------------------------------------------------
+struct SolveRun {
+  std::vector<double> theta, rs, mu;
+  std::vector<int> iters;
+  rafeast_status status = RAFEAST_NO_CONVERGENCE;
+  int it = 0, M = 0;
+  double maxres = 0.0;
+  int64_t cocg_sum = 0;
+  int cocg_max = 0;
+  bool breakdown = false, done = false;
+  double t_ph[RAFEAST_NPHASE] = {0, 0, 0, 0, 0};
+};
+
+// Counted pairs: theta in the closed window and filter gain >= 1/4 (an
+// eigenvector in the window has gain |rho| >= 1/2; a mixture of outside
+// eigenvectors whose Ritz value falls in the window has a small gain).
+bool counted(const rafeast_plan_s* P, const SolveRun& S, int i) {
+  return S.theta[i] >= P->prm.lmin && S.theta[i] <= P->prm.lmax && S.mu[i] >= kSpuriousGain;
+}
+
+// Start block: Q_init, else the last warm start, else the orthonormalised
+// device sketch.
+rafeast_status solve_begin(rafeast_plan_s* P, const double* Q_init, SolveRun& S) {
+  P->err.clear();
+  const int64_t n = P->n;
+  const int m0 = P->m0, ld = P->ld;
+  HIPCHK(P, hipEventRecord(P->ev[6], P->st));
+  if (Q_init) {
+    HIPCHK(P, hipMemcpyAsync(P->d_T, Q_init, (size_t)n * m0 * sizeof(double),
+                             hipMemcpyHostToDevice, P->st));
+    HIPCHK(P, launch_colmajor_to_rowmajor(P->st, n, m0, P->d_T, P->d_Q, ld));
+    int ci = 0;
+    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
+    if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "Q_init is rank deficient");
+  } else if (!P->have_start) {
+    HIPCHK(P, launch_gaussian(P->st, n, m0, P->prm.seed, P->d_Q, ld));
+    int ci = 0;
+    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
+    if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "random start is rank deficient");
+  }
+  HIPCHK(P, hipMemsetAsync(P->d_stats, 0, 2 * sizeof(int), P->st));
+  P->have_filter = false;
+  S = SolveRun();
+  S.iters.assign(P->nitems, 0);
+  return RAFEAST_OK;
+}
+
+// Rayleigh-Ritz and the stopping tests; S.done when the iteration ends here.
+rafeast_status solve_test(rafeast_plan_s* P, SolveRun& S) {
+  const int m0 = P->m0;
+  HIPCHK(P, hipEventRecord(P->ev[0], P->st));
+  RCHK(rayleigh_ritz(P, S.theta, S.rs, S.mu));
+  HIPCHK(P, hipEventRecord(P->ev[1], P->st));
+  HIPCHK(P, hipEventSynchronize(P->ev[1]));
+  S.t_ph[RAFEAST_PH_RR] += elapsed(P->ev[0], P->ev[1]);
+  S.M = 0;
+  S.maxres = 0.0;
+  int in_window = 0;  // Ritz values in the window, spurious or not
+  for (int i = 0; i < m0; ++i) in_window += S.theta[i] >= P->prm.lmin && S.theta[i] <= P->prm.lmax;
+  for (int i = 0; i < m0; ++i)
+    if (counted(P, S, i)) {
+      ++S.M;
+      S.maxres = std::max(S.maxres, S.rs[i]);
+    }
+  if (S.M > 0 && S.maxres <= P->prm.tol_eig) {
+    S.status = RAFEAST_OK;
+    S.done = true;
+  } else if (in_window == 0 && S.it >= 2) {
+    S.status = RAFEAST_EMPTY_WINDOW;
+    S.done = true;
+  } else if (S.it >= P->prm.max_iter) {
+    S.done = true;
+  }
+  return RAFEAST_OK;
+}
+
+// The shifted solves of one plan, for all (node, column) pairs.
+rafeast_status solve_shifted_systems(rafeast_plan_s* P) {
+  const int m0 = P->m0, nc = P->nc, ld = P->ld;
+  const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
+  if (P->engine == RAFEAST_ENGINE_STREAM)
+    return run_stream(P, P->swork, nc, m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D, nc * m0,
+                      P->prm.tol_solve, P->d_iters);
+  return run_cocg(P, P->nitems, P->d_items, P->d_zw, m0, residual_form ? P->d_R : P->d_Q, ld,
+                  P->d_D, nc * m0, P->prm.tol_solve, P->d_iters);
+}
+
+// After the solves (between events ev[2] and ev[3]): combination
+// Q~ = sum_j Re[w_j (z_j I - A)^{-1} Q], CholQR2, timings, counters.
+rafeast_status solve_combine(rafeast_plan_s* P, SolveRun& S) {
+  const int64_t n = P->n;
+  const int m0 = P->m0, nc = P->nc, ld = P->ld;
+  const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
+  HIPCHK(P, hipMemcpyAsync(S.iters.data(), P->d_iters, P->nitems * sizeof(int),
+                           hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, launch_gamma(P->st, nc, m0, P->d_zw, P->d_theta, P->d_gamma));
+  HIPCHK(P, launch_combine(P->st, n, nc, m0, P->d_gamma, P->d_zw, residual_form, P->d_Q, ld,
+                           P->d_D, nc * m0, P->fp32, P->d_Y, ld));
+  HIPCHK(P, hipEventRecord(P->ev[4], P->st));
+  std::swap(P->d_Q, P->d_Y);
+  int ci = 0;
+  RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld, &P->mtot));
+  P->have_filter = ci != 2;
+  HIPCHK(P, hipEventRecord(P->ev[5], P->st));
+  HIPCHK(P, hipEventSynchronize(P->ev[5]));
+  if (ci == 2) S.breakdown = true;
+  S.t_ph[RAFEAST_PH_SOLVE] += elapsed(P->ev[2], P->ev[3]);
+  S.t_ph[RAFEAST_PH_COMBINE] += elapsed(P->ev[3], P->ev[4]);
+  S.t_ph[RAFEAST_PH_ORTH] += elapsed(P->ev[4], P->ev[5]);
+  int64_t it_sum = 0;
+  int it_max = 0;
+  for (int v : S.iters) {
+    it_sum += v;
+    it_max = std::max(it_max, v);
+  }
+  S.cocg_sum += it_sum;
+  S.cocg_max = std::max(S.cocg_max, it_max);
+  if (verbose_log())
+    std::fprintf(stderr,
+                 "rafeast: iteration %d: M %d, max residual %.3e, COCG %lld (max %d), "
+                 "solve %.1f ms\n",
+                 S.it + 1, S.M, S.maxres, (long long)it_sum, it_max, elapsed(P->ev[2], P->ev[3]));
+  ++S.it;
+  return RAFEAST_OK;
+}
+
+// Status and outputs of a finished iteration.
+rafeast_status solve_finish(rafeast_plan_s* P, SolveRun& S, rafeast_result* res) {
+  const int64_t n = P->n;
+  const int m0 = P->m0, ld = P->ld;
+  rafeast_status status = S.status;
+  if (status == RAFEAST_OK && S.M >= m0) status = RAFEAST_SUBSPACE_TOO_SMALL;
+  if (S.breakdown && status != RAFEAST_OK) status = RAFEAST_BREAKDOWN;
+  // outputs: counted pairs, ascending (theta is sorted)
+  std::vector<int> sel;
+  for (int i = 0; i < m0; ++i)
+    if (counted(P, S, i)) sel.push_back(i);
+  std::vector<double> lam(sel.size()), rsel(sel.size());
+  for (size_t a = 0; a < sel.size(); ++a) {
+    lam[a] = S.theta[sel[a]];
+    rsel[a] = S.rs[sel[a]];
+  }
+  const bool dev_out = (res->flags & RAFEAST_PTR_DEVICE) != 0;
+  if (!sel.empty()) {
+    if (dev_out) {
+      HIPCHK(P, hipMemcpyAsync(res->lambda, lam.data(), lam.size() * sizeof(double),
+                               hipMemcpyHostToDevice, P->st));
+      HIPCHK(P, hipMemcpyAsync(res->resid, rsel.data(), rsel.size() * sizeof(double),
+                               hipMemcpyHostToDevice, P->st));
+    } else {
+      std::memcpy(res->lambda, lam.data(), lam.size() * sizeof(double));
+      std::memcpy(res->resid, rsel.data(), rsel.size() * sizeof(double));
+    }
+  }
+  if (res->X && !sel.empty()) {
+    HIPCHK(P, hipMemcpyAsync(P->d_sel, sel.data(), sel.size() * sizeof(int), hipMemcpyHostToDevice,
+                             P->st));
+    double* dst = dev_out ? res->X : P->d_T;
+    HIPCHK(P, launch_export_vectors(P->st, n, (int)sel.size(), P->d_sel, P->d_Q, ld, dst, nullptr));
+    if (!dev_out)
+      HIPCHK(P, hipMemcpyAsync(res->X, P->d_T, (size_t)n * sel.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, P->st));
+  }
+  int stats[2] = {0, 0};
+  HIPCHK(P, hipMemcpyAsync(stats, P->d_stats, 2 * sizeof(int), hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipEventRecord(P->ev[7], P->st));
+  HIPCHK(P, hipEventSynchronize(P->ev[7]));
+  S.t_ph[RAFEAST_PH_TOTAL] = elapsed(P->ev[6], P->ev[7]);
+  P->have_start = false;  // the next solve without Q_init starts afresh
+  res->M = S.M;
+  res->iters = S.it;
+  res->cocg_iters = S.cocg_sum;
+  res->cocg_max = S.cocg_max;
+  res->refinements = stats[0];
+  res->max_resid = S.maxres;
+  for (int i = 0; i < RAFEAST_NPHASE; ++i) res->t_ms[i] = S.t_ph[i];
+  if (stats[1] > 0 && status != RAFEAST_OK)
+    P->err = std::to_string(stats[1]) + " COCG systems broke down";
+  return status;
 }
 
 }  // namespace
@@ -903,6 +1135,7 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
     // slice-to-wave table for the smallest slot count per wave that fits
     std::vector<int> widths(nsl);
     for (int s2 = 0; s2 < nsl; ++s2) widths[s2] = (sb[s2 + 1] - sb[s2]) / 64;
+    P->sell_widths = widths;
     std::vector<int> tab;
     int rpt = 0;
     for (int cand : {1, 2, 4, 8}) {
@@ -999,7 +1232,7 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
     if (e != hipSuccess) return bail(hip_fail(P, e, "solve block"));
   }
   P->nitems = P->nc * P->m0;
-  PRCHK(dalloc(P, &P->d_items, 2 * (size_t)P->nitems, "items"));
+  PRCHK(dalloc(P, &P->d_items, 3 * (size_t)P->nitems, "items"));
   PRCHK(dalloc(P, &P->d_counter, 1, "counter"));
   PRCHK(dalloc(P, &P->d_iters, (size_t)P->nitems, "iters"));
   PRCHK(dalloc(P, &P->d_stats, 2, "stats"));
@@ -1150,156 +1383,17 @@ rafeast_status rafeast_warmstart(rafeast_plan_t P, const double* omega, double* 
 
 rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_result* res) {
   if (!P || !res || !res->lambda || !res->resid) return RAFEAST_INVALID_ARG;
-  P->err.clear();
-  const int64_t n = P->n;
-  const int m0 = P->m0, ld = P->ld, nc = P->nc;
-  const double lmin = P->prm.lmin, lmax = P->prm.lmax;
-  double t_ph[RAFEAST_NPHASE] = {0, 0, 0, 0, 0};
-  HIPCHK(P, hipEventRecord(P->ev[6], P->st));
-  if (Q_init) {
-    HIPCHK(P, hipMemcpyAsync(P->d_T, Q_init, (size_t)n * m0 * sizeof(double),
-                             hipMemcpyHostToDevice, P->st));
-    HIPCHK(P, launch_colmajor_to_rowmajor(P->st, n, m0, P->d_T, P->d_Q, ld));
-    int ci = 0;
-    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
-    if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "Q_init is rank deficient");
-  } else if (!P->have_start) {
-    HIPCHK(P, launch_gaussian(P->st, n, m0, P->prm.seed, P->d_Q, ld));
-    int ci = 0;
-    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld));
-    if (ci == 2) return fail(P, RAFEAST_BREAKDOWN, "random start is rank deficient");
-  }
-  HIPCHK(P, hipMemsetAsync(P->d_stats, 0, 2 * sizeof(int), P->st));
-  P->have_filter = false;
-  std::vector<double> theta, rs, mu;
-  // counted pairs: theta in the closed window and filter gain >= 1/4 (an
-  // eigenvector in the window has gain |rho| >= 1/2; a mixture of outside
-  // eigenvectors whose Ritz value falls in the window has a small gain)
-  auto counted = [&](int i) {
-    return theta[i] >= lmin && theta[i] <= lmax && mu[i] >= kSpuriousGain;
-  };
-  std::vector<int> iters(P->nitems);
-  rafeast_status status = RAFEAST_NO_CONVERGENCE;
-  int it = 0, M = 0;
-  double maxres = 0.0;
-  int64_t cocg_sum = 0;
-  int cocg_max = 0;
-  bool breakdown = false;
-  const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
-  for (;; ++it) {
-    HIPCHK(P, hipEventRecord(P->ev[0], P->st));
-    RCHK(rayleigh_ritz(P, theta, rs, mu));
-    HIPCHK(P, hipEventRecord(P->ev[1], P->st));
-    M = 0;
-    maxres = 0.0;
-    int in_window = 0;  // Ritz values in the window, spurious or not
-    for (int i = 0; i < m0; ++i) in_window += theta[i] >= lmin && theta[i] <= lmax;
-    for (int i = 0; i < m0; ++i)
-      if (counted(i)) {
-        ++M;
-        maxres = std::max(maxres, rs[i]);
-      }
-    if (M > 0 && maxres <= P->prm.tol_eig) {
-      status = RAFEAST_OK;
-      break;
-    }
-    if (in_window == 0 && it >= 2) {
-      status = RAFEAST_EMPTY_WINDOW;
-      break;
-    }
-    if (it >= P->prm.max_iter) break;
-    // shifted solves for all (node, column) pairs
+  SolveRun S;
+  RCHK(solve_begin(P, Q_init, S));
+  for (;;) {
+    RCHK(solve_test(P, S));
+    if (S.done) break;
     HIPCHK(P, hipEventRecord(P->ev[2], P->st));
-    if (P->engine == RAFEAST_ENGINE_STREAM)
-      RCHK(run_stream(P, P->swork, nc, m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D, nc * m0,
-                      P->prm.tol_solve, P->d_iters));
-    else
-      RCHK(run_cocg(P, P->nitems, P->d_items, P->d_zw, m0, residual_form ? P->d_R : P->d_Q, ld,
-                    P->d_D, nc * m0, P->prm.tol_solve, P->d_iters));
+    RCHK(solve_shifted_systems(P));
     HIPCHK(P, hipEventRecord(P->ev[3], P->st));
-    HIPCHK(P, hipMemcpyAsync(iters.data(), P->d_iters, P->nitems * sizeof(int),
-                             hipMemcpyDeviceToHost, P->st));
-    // combination Q~ = sum_j Re[w_j (z_j I - A)^{-1} Q]
-    HIPCHK(P, launch_gamma(P->st, nc, m0, P->d_zw, P->d_theta, P->d_gamma));
-    HIPCHK(P, launch_combine(P->st, n, nc, m0, P->d_gamma, P->d_zw, residual_form, P->d_Q, ld,
-                             P->d_D, nc * m0, P->fp32, P->d_Y, ld));
-    HIPCHK(P, hipEventRecord(P->ev[4], P->st));
-    std::swap(P->d_Q, P->d_Y);
-    int ci = 0;
-    RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld, &P->mtot));
-    P->have_filter = ci != 2;
-    HIPCHK(P, hipEventRecord(P->ev[5], P->st));
-    HIPCHK(P, hipEventSynchronize(P->ev[5]));
-    if (ci == 2) breakdown = true;
-    t_ph[RAFEAST_PH_RR] += elapsed(P->ev[0], P->ev[1]);
-    t_ph[RAFEAST_PH_SOLVE] += elapsed(P->ev[2], P->ev[3]);
-    t_ph[RAFEAST_PH_COMBINE] += elapsed(P->ev[3], P->ev[4]);
-    t_ph[RAFEAST_PH_ORTH] += elapsed(P->ev[4], P->ev[5]);
-    int64_t it_sum = 0;
-    int it_max = 0;
-    for (int v : iters) {
-      it_sum += v;
-      it_max = std::max(it_max, v);
-    }
-    cocg_sum += it_sum;
-    cocg_max = std::max(cocg_max, it_max);
-    if (verbose_log())
-      std::fprintf(stderr,
-                   "rafeast: iteration %d: M %d, max residual %.3e, COCG %lld (max %d), "
-                   "solve %.1f ms\n",
-                   it + 1, M, maxres, (long long)it_sum, it_max, elapsed(P->ev[2], P->ev[3]));
+    RCHK(solve_combine(P, S));
   }
-  HIPCHK(P, hipEventSynchronize(P->ev[1]));
-  t_ph[RAFEAST_PH_RR] += elapsed(P->ev[0], P->ev[1]);
-  if (status == RAFEAST_OK && M >= m0) status = RAFEAST_SUBSPACE_TOO_SMALL;
-  if (breakdown && status != RAFEAST_OK) status = RAFEAST_BREAKDOWN;
-
-  // outputs: in-window pairs, ascending (theta is sorted)
-  std::vector<int> sel;
-  for (int i = 0; i < m0; ++i)
-    if (counted(i)) sel.push_back(i);
-  std::vector<double> lam(sel.size()), rsel(sel.size());
-  for (size_t a = 0; a < sel.size(); ++a) {
-    lam[a] = theta[sel[a]];
-    rsel[a] = rs[sel[a]];
-  }
-  const bool dev_out = (res->flags & RAFEAST_PTR_DEVICE) != 0;
-  if (!sel.empty()) {
-    if (dev_out) {
-      HIPCHK(P, hipMemcpyAsync(res->lambda, lam.data(), lam.size() * sizeof(double),
-                               hipMemcpyHostToDevice, P->st));
-      HIPCHK(P, hipMemcpyAsync(res->resid, rsel.data(), rsel.size() * sizeof(double),
-                               hipMemcpyHostToDevice, P->st));
-    } else {
-      std::memcpy(res->lambda, lam.data(), lam.size() * sizeof(double));
-      std::memcpy(res->resid, rsel.data(), rsel.size() * sizeof(double));
-    }
-  }
-  if (res->X && !sel.empty()) {
-    HIPCHK(P, hipMemcpyAsync(P->d_sel, sel.data(), sel.size() * sizeof(int), hipMemcpyHostToDevice,
-                             P->st));
-    double* dst = dev_out ? res->X : P->d_T;
-    HIPCHK(P, launch_export_vectors(P->st, n, (int)sel.size(), P->d_sel, P->d_Q, ld, dst, nullptr));
-    if (!dev_out)
-      HIPCHK(P, hipMemcpyAsync(res->X, P->d_T, (size_t)n * sel.size() * sizeof(double),
-                               hipMemcpyDeviceToHost, P->st));
-  }
-  int stats[2] = {0, 0};
-  HIPCHK(P, hipMemcpyAsync(stats, P->d_stats, 2 * sizeof(int), hipMemcpyDeviceToHost, P->st));
-  HIPCHK(P, hipEventRecord(P->ev[7], P->st));
-  HIPCHK(P, hipEventSynchronize(P->ev[7]));
-  t_ph[RAFEAST_PH_TOTAL] = elapsed(P->ev[6], P->ev[7]);
-  P->have_start = false;  // the next solve without Q_init starts afresh
-  res->M = M;
-  res->iters = it;
-  res->cocg_iters = cocg_sum;
-  res->cocg_max = cocg_max;
-  res->refinements = stats[0];
-  res->max_resid = maxres;
-  for (int i = 0; i < RAFEAST_NPHASE; ++i) res->t_ms[i] = t_ph[i];
-  if (stats[1] > 0 && status != RAFEAST_OK)
-    P->err = std::to_string(stats[1]) + " COCG systems broke down";
-  return status;
+  return solve_finish(P, S, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -1436,6 +1530,296 @@ rafeast_status rafeast_gaussian(rafeast_plan_t P, int32_t w, uint64_t seed, doub
   HIPCHK(P, launch_gaussian(P->st, P->n, w, seed, Omega, ld));
   HIPCHK(P, hipStreamSynchronize(P->st));
   return RAFEAST_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batching form
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_batch_error;
+
+rafeast_status batch_fail(rafeast_batch_s* B, rafeast_status st, const std::string& msg) {
+  if (B)
+    B->err = msg;
+  else
+    g_batch_error = msg;
+  return st;
+}
+
+void free_batch(rafeast_batch_s* B) {
+  if (!B) return;
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  for (int* t : B->own_wtab) (void)hipFree(t);
+  void* ptrs[] = {B->d_graphs, B->d_items, B->d_counter, B->d_xhi};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (auto& e : B->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (rafeast_plan_s* P : B->plans) free_plan(P);
+  if (B->own_stream && B->st) (void)hipStreamDestroy(B->st);
+  delete B;
+}
+
+#define BCHK(B, expr)                                                          \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess)                                                      \
+      return batch_fail((B), _e == hipErrorOutOfMemory ? RAFEAST_OOM : RAFEAST_DEVICE, \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));    \
+  } while (0)
+
+// One shared resident launch for the active resident members: descriptors
+// and (member, node, column) items, longest first across members (the cost
+// of a system is taken as nnz * sqrt(spectral width / |Im z|), the COCG
+// iteration count growing as the shift nears the spectrum).  The counter
+// reset and the launch are captured once per item count and replayed.
+rafeast_status batch_resident_solves(rafeast_batch_s* B, const std::vector<char>& active) {
+  struct Key {
+    double cost;
+    int k, j, i;
+  };
+  std::vector<Key> keys;
+  for (size_t g = 0; g < B->plans.size(); ++g) {
+    const int k = B->res_idx[g];
+    if (k < 0 || !active[g]) continue;
+    rafeast_plan_s* P = B->plans[g];
+    const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
+    B->h_graphs[k] = resident_graph(P, P->d_zw, P->m0, residual_form ? P->d_R : P->d_Q, P->ld,
+                                    P->d_D, P->nc * P->m0, P->d_iters, nullptr, B->wtab[g]);
+    const double width = std::max(P->sig_hi - P->sig_lo, 1e-300);
+    for (int j = 0; j < P->nc; ++j) {
+      const double im = std::max(std::fabs(P->zw[2 * j + 1]), 1e-300);
+      const double cost = (double)P->nnz * std::sqrt(width / im);
+      for (int i = 0; i < P->m0; ++i) keys.push_back(Key{cost, k, j, i});
+    }
+  }
+  if (keys.empty()) return RAFEAST_OK;
+  std::stable_sort(keys.begin(), keys.end(),
+                   [](const Key& a, const Key& b) { return a.cost > b.cost; });
+  const int nitems = (int)keys.size();
+  B->h_items.resize(3 * (size_t)nitems);
+  for (int t = 0; t < nitems; ++t) {
+    B->h_items[3 * t] = keys[t].k;
+    B->h_items[3 * t + 1] = keys[t].j;
+    B->h_items[3 * t + 2] = keys[t].i;
+  }
+  BCHK(B, hipMemcpyAsync(B->d_graphs, B->h_graphs.data(), B->nres * sizeof(ResGraph),
+                         hipMemcpyHostToDevice, B->st));
+  BCHK(B, hipMemcpyAsync(B->d_items, B->h_items.data(), B->h_items.size() * sizeof(int),
+                         hipMemcpyHostToDevice, B->st));
+  if (B->graph_nitems != nitems) {
+    if (B->gexec) BCHK(B, hipGraphExecDestroy(B->gexec));
+    if (B->graph) BCHK(B, hipGraphDestroy(B->graph));
+    B->gexec = nullptr;
+    B->graph = nullptr;
+    const rafeast_plan_s* P0 = B->plans[0];
+    CocgLaunch L;
+    L.nitems = nitems;
+    L.items = B->d_items;
+    L.tol = P0->prm.tol_solve;
+    L.maxit = P0->prm.max_cocg;
+    L.max_refine = 4;
+    L.counter = B->d_counter;
+    L.xhi = B->d_xhi;
+    L.xhi_slots = B->xhi_slots;
+    BCHK(B, prepare_cocg_resident(B->max_n, B->rpt, B->fp32));
+    BCHK(B, hipStreamBeginCapture(B->st, hipStreamCaptureModeRelaxed));
+    hipError_t e = launch_fill_int(B->st, B->d_counter, 0, 1);
+    if (e == hipSuccess)
+      e = launch_cocg_resident(B->st, nullptr, B->d_graphs, B->max_n, B->rpt, L, B->fp32,
+                               B->num_cu);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(B->st, &g);
+    BCHK(B, e);
+    BCHK(B, e2);
+    B->graph = g;
+    BCHK(B, hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+    B->graph_nitems = nitems;
+  }
+  BCHK(B, hipGraphLaunch(B->gexec, B->st));
+  return RAFEAST_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rafeast_status rafeast_plan_batch(int32_t count, const rafeast_csr* A, const rafeast_params* prm,
+                                  rafeast_batch_t* out) {
+  if (!out) return batch_fail(nullptr, RAFEAST_INVALID_ARG, "null output");
+  *out = nullptr;
+  if (count < 1 || !A || !prm) return batch_fail(nullptr, RAFEAST_INVALID_ARG, "need count >= 1 and arrays");
+  for (int g = 1; g < count; ++g)
+    if (prm[g].precision != prm[0].precision || prm[g].tol_solve != prm[0].tol_solve ||
+        prm[g].max_cocg != prm[0].max_cocg)
+      return batch_fail(nullptr, RAFEAST_INVALID_ARG,
+                        "batch members must share precision, tol_solve and max_cocg");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return batch_fail(nullptr, RAFEAST_DEVICE, "no HIP device available");
+  rafeast_batch_s* B = new rafeast_batch_s();
+  B->fp32 = prm[0].precision == RAFEAST_FP32_REFINED;
+  auto bail = [&](rafeast_status st) {
+    g_batch_error = B->err;
+    free_batch(B);
+    return st;
+  };
+#define BPCHK(expr)                                                   \
+  do {                                                                \
+    hipError_t _e = (expr);                                           \
+    if (_e != hipSuccess)                                             \
+      return bail(batch_fail(B, _e == hipErrorOutOfMemory ? RAFEAST_OOM : RAFEAST_DEVICE, \
+                             std::string(#expr) + ": " + hipGetErrorString(_e)));         \
+  } while (0)
+  if (prm[0].hip_stream) {
+    B->st = (hipStream_t)prm[0].hip_stream;
+  } else {
+    BPCHK(hipStreamCreateWithFlags(&B->st, hipStreamNonBlocking));
+    B->own_stream = true;
+  }
+  for (auto& e : B->ev) BPCHK(hipEventCreate(&e));
+  for (int g = 0; g < count; ++g) {
+    rafeast_params q = prm[g];
+    q.hip_stream = B->st;
+    rafeast_plan_t P = nullptr;
+    const rafeast_status st = rafeast_plan(&A[g], &q, &P);
+    if (st != RAFEAST_OK) {
+      B->err = "member " + std::to_string(g) + ": " + rafeast_last_error(nullptr);
+      return bail(st);
+    }
+    B->plans.push_back(P);
+  }
+  // resident members share one launch: a common slot count per wave and
+  // LDS sized for the largest of them
+  B->res_idx.assign(count, -1);
+  B->wtab.assign(count, nullptr);
+  for (int g = 0; g < count; ++g) {
+    rafeast_plan_s* P = B->plans[g];
+    if (P->engine != RAFEAST_ENGINE_RESIDENT) continue;
+    B->res_idx[g] = B->nres++;
+    B->rpt = std::max(B->rpt, P->sell.wave_rpt);
+    B->max_n = std::max<int>(B->max_n, (int)P->n);
+  }
+  B->num_cu = B->plans[0]->num_cu;
+  if (B->nres > 0) {
+    for (int g = 0; g < count; ++g) {
+      rafeast_plan_s* P = B->plans[g];
+      if (B->res_idx[g] < 0) continue;
+      if (P->sell.wave_rpt == B->rpt) {
+        B->wtab[g] = const_cast<int*>(P->sell.wave_slices);
+        continue;
+      }
+      // more slots per wave than the member needs always fit
+      const std::vector<int> tab = cocg_resident_wave_table(P->sell_widths, B->rpt);
+      if (tab.empty())
+        return bail(batch_fail(B, RAFEAST_UNSUPPORTED, "wave table of member " + std::to_string(g)));
+      int* d = nullptr;
+      BPCHK(hipMalloc(&d, tab.size() * sizeof(int)));
+      B->own_wtab.push_back(d);
+      BPCHK(hipMemcpy(d, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+      B->wtab[g] = d;
+    }
+    size_t items = 0;
+    for (int g = 0; g < count; ++g)
+      if (B->res_idx[g] >= 0) items += 3 * (size_t)B->plans[g]->nitems;
+    B->h_graphs.resize(B->nres);
+    BPCHK(hipMalloc(&B->d_graphs, B->nres * sizeof(ResGraph)));
+    BPCHK(hipMalloc(&B->d_items, items * sizeof(int)));
+    BPCHK(hipMalloc(&B->d_counter, sizeof(int)));
+    B->xhi_slots = (size_t)B->num_cu * ((size_t)(B->max_n + 63) / 64 * 64);
+    BPCHK(hipMalloc(&B->d_xhi, B->xhi_slots * 2 * sizeof(double)));
+  }
+#undef BPCHK
+  *out = B;
+  return RAFEAST_OK;
+}
+
+rafeast_plan_t rafeast_batch_plan(rafeast_batch_t B, int32_t g) {
+  if (!B || g < 0 || g >= (int32_t)B->plans.size()) return nullptr;
+  return B->plans[g];
+}
+
+int32_t rafeast_batch_resident_count(rafeast_batch_t B) { return B ? B->nres : 0; }
+
+rafeast_status rafeast_batch_solve(rafeast_batch_t B, const double* const* Q_init,
+                                   rafeast_result* res, rafeast_status* status, double* t_ms) {
+  if (!B || !res) return RAFEAST_INVALID_ARG;
+  const int count = (int)B->plans.size();
+  for (int g = 0; g < count; ++g)
+    if (!res[g].lambda || !res[g].resid) return batch_fail(B, RAFEAST_INVALID_ARG, "result arrays");
+  B->err.clear();
+  double tb[RAFEAST_NPHASE] = {0, 0, 0, 0, 0};
+  auto member_fail = [&](int g, rafeast_status st) {
+    return batch_fail(B, st, "member " + std::to_string(g) + ": " + B->plans[g]->err);
+  };
+  BCHK(B, hipEventRecord(B->ev[0], B->st));
+  std::vector<SolveRun> S(count);
+  for (int g = 0; g < count; ++g) {
+    const rafeast_status st = solve_begin(B->plans[g], Q_init ? Q_init[g] : nullptr, S[g]);
+    if (st != RAFEAST_OK) return member_fail(g, st);
+  }
+  std::vector<char> active(count, 1);
+  for (;;) {
+    int nact = 0;
+    for (int g = 0; g < count; ++g) {
+      if (!active[g]) continue;
+      const rafeast_status st = solve_test(B->plans[g], S[g]);
+      if (st != RAFEAST_OK) return member_fail(g, st);
+      if (S[g].done)
+        active[g] = 0;
+      else
+        ++nact;
+    }
+    if (nact == 0) break;
+    // every active member's solves: the shared resident launch, then the
+    // streaming members
+    for (int g = 0; g < count; ++g)
+      if (active[g]) BCHK(B, hipEventRecord(B->plans[g]->ev[2], B->st));
+    RCHK(batch_resident_solves(B, active));
+    for (int g = 0; g < count; ++g) {
+      if (!active[g] || B->res_idx[g] >= 0) continue;
+      const rafeast_status st = solve_shifted_systems(B->plans[g]);
+      if (st != RAFEAST_OK) return member_fail(g, st);
+    }
+    for (int g = 0; g < count; ++g)
+      if (active[g]) BCHK(B, hipEventRecord(B->plans[g]->ev[3], B->st));
+    bool timed = false;
+    for (int g = 0; g < count; ++g) {
+      if (!active[g]) continue;
+      const rafeast_status st = solve_combine(B->plans[g], S[g]);
+      if (st != RAFEAST_OK) return member_fail(g, st);
+      if (!timed) {  // the solve phase is shared: count it once
+        tb[RAFEAST_PH_SOLVE] += elapsed(B->plans[g]->ev[2], B->plans[g]->ev[3]);
+        timed = true;
+      }
+    }
+  }
+  rafeast_status first = RAFEAST_OK;
+  for (int g = 0; g < count; ++g) {
+    const rafeast_status st = solve_finish(B->plans[g], S[g], &res[g]);
+    if (st != RAFEAST_OK && st != RAFEAST_NO_CONVERGENCE && st != RAFEAST_SUBSPACE_TOO_SMALL &&
+        st != RAFEAST_EMPTY_WINDOW && st != RAFEAST_BREAKDOWN)
+      return member_fail(g, st);
+    if (status) status[g] = st;
+    if (st != RAFEAST_OK && first == RAFEAST_OK) first = st;
+    tb[RAFEAST_PH_RR] += S[g].t_ph[RAFEAST_PH_RR];
+    tb[RAFEAST_PH_COMBINE] += S[g].t_ph[RAFEAST_PH_COMBINE];
+    tb[RAFEAST_PH_ORTH] += S[g].t_ph[RAFEAST_PH_ORTH];
+  }
+  BCHK(B, hipEventRecord(B->ev[1], B->st));
+  BCHK(B, hipEventSynchronize(B->ev[1]));
+  tb[RAFEAST_PH_TOTAL] = elapsed(B->ev[0], B->ev[1]);
+  if (t_ms)
+    for (int i = 0; i < RAFEAST_NPHASE; ++i) t_ms[i] = tb[i];
+  return first;
+}
+
+void rafeast_batch_destroy(rafeast_batch_t B) { free_batch(B); }
+
+const char* rafeast_batch_last_error(rafeast_batch_t B) {
+  return B ? B->err.c_str() : g_batch_error.c_str();
 }
 
 }  // extern "C"

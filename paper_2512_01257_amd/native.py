@@ -99,6 +99,19 @@ def lib():
     L.rafeast_plan_engine.restype = C.c_int32
     L.rafeast_rcm_order.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32)]
     L.rafeast_rcm_order.restype = C.c_int
+    L.rafeast_plan_batch.argtypes = [C.c_int32, C.POINTER(Csr), C.POINTER(Params), C.POINTER(P)]
+    L.rafeast_plan_batch.restype = C.c_int
+    L.rafeast_batch_plan.argtypes = [P, C.c_int32]
+    L.rafeast_batch_plan.restype = P
+    L.rafeast_batch_solve.argtypes = [P, C.POINTER(dp), C.POINTER(Result), C.POINTER(C.c_int),
+                                      dp]
+    L.rafeast_batch_solve.restype = C.c_int
+    L.rafeast_batch_resident_count.argtypes = [P]
+    L.rafeast_batch_resident_count.restype = C.c_int32
+    L.rafeast_batch_destroy.argtypes = [P]
+    L.rafeast_batch_destroy.restype = None
+    L.rafeast_batch_last_error.argtypes = [P]
+    L.rafeast_batch_last_error.restype = C.c_char_p
     L.rafeast_spmm.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, C.c_double, C.c_double]
     L.rafeast_spmm.restype = C.c_int
     L.rafeast_gram.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int32, P, C.c_int32,
@@ -167,6 +180,30 @@ def rcm_order(csr):
     return perm
 
 
+def _csr_struct(csr):
+    rowptr = np.ascontiguousarray(csr.rowptr, dtype=np.int32)
+    colind = np.ascontiguousarray(csr.colind, dtype=np.int32)
+    values = np.ascontiguousarray(csr.values, dtype=np.float64)
+    A = Csr(int(csr.n), rowptr.ctypes.data_as(C.POINTER(C.c_int32)),
+            colind.ctypes.data_as(C.POINTER(C.c_int32)),
+            values.ctypes.data_as(C.POINTER(C.c_double)), 0)
+    return A, (rowptr, colind, values)
+
+
+def _params(lmin, lmax, m0, nc, q, p, tol_eig, tol_solve, max_iter, max_cocg, precision,
+            ws_op, rhs_form, engine, seed, stream):
+    prm = default_params()
+    prm.lmin, prm.lmax, prm.m0, prm.nc, prm.q, prm.p = lmin, lmax, m0, nc, q, p
+    prm.tol_eig, prm.tol_solve, prm.max_iter, prm.max_cocg = tol_eig, tol_solve, max_iter, max_cocg
+    prm.precision = PRECISION[precision]
+    prm.ws_op = WS_OP[ws_op]
+    prm.rhs_form = RHS_FORM[rhs_form]
+    prm.engine = ENGINE[engine]
+    prm.seed = seed
+    prm.hip_stream = stream
+    return prm
+
+
 def default_params() -> Params:
     p = Params()
     lib().rafeast_params_default(C.byref(p))
@@ -180,27 +217,19 @@ class Plan:
                  max_iter=20, max_cocg=20000, precision="fp32", ws_op="auto",
                  rhs_form="residual", engine="auto", seed=0, stream=None):
         L = lib()
-        rowptr = np.ascontiguousarray(csr.rowptr, dtype=np.int32)
-        colind = np.ascontiguousarray(csr.colind, dtype=np.int32)
-        values = np.ascontiguousarray(csr.values, dtype=np.float64)
-        A = Csr(int(csr.n), rowptr.ctypes.data_as(C.POINTER(C.c_int32)),
-                colind.ctypes.data_as(C.POINTER(C.c_int32)),
-                values.ctypes.data_as(C.POINTER(C.c_double)), 0)
-        prm = default_params()
-        prm.lmin, prm.lmax, prm.m0, prm.nc, prm.q, prm.p = lmin, lmax, m0, nc, q, p
-        prm.tol_eig, prm.tol_solve, prm.max_iter, prm.max_cocg = tol_eig, tol_solve, max_iter, max_cocg
-        prm.precision = PRECISION[precision]
-        prm.ws_op = WS_OP[ws_op]
-        prm.rhs_form = RHS_FORM[rhs_form]
-        prm.engine = ENGINE[engine]
-        prm.seed = seed
-        prm.hip_stream = stream
+        A, keep = _csr_struct(csr)
+        prm = _params(lmin, lmax, m0, nc, q, p, tol_eig, tol_solve, max_iter, max_cocg,
+                      precision, ws_op, rhs_form, engine, seed, stream)
         h = C.c_void_p()
         st = L.rafeast_plan(C.byref(A), C.byref(prm), C.byref(h))
         if st != 0:
             raise RafeastError(st, L.rafeast_last_error(None).decode())
+        self._setup(h, int(csr.n), m0, nc, lmin, lmax, precision, p, owned=True)
+
+    def _setup(self, h, n, m0, nc, lmin, lmax, precision, p, owned):
         self._h = h
-        self.n = int(csr.n)
+        self._owned = owned
+        self.n = n
         self.m0 = m0
         self.nc = nc
         self.lmin, self.lmax = lmin, lmax
@@ -210,7 +239,8 @@ class Plan:
     # ------------------------------------------------------------------ life
     def close(self):
         if getattr(self, "_h", None):
-            lib().rafeast_destroy(self._h)
+            if self._owned:
+                lib().rafeast_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -359,3 +389,106 @@ class Plan:
 
         self._check(lib().rafeast_gaussian(self._h, Omega.shape[1], seed,
                                            _tptr(Omega, torch.float64), Omega.stride(0)))
+
+
+_PLAN_DEFAULTS = dict(nc=8, q=2, p=-1, tol_eig=1e-10, tol_solve=1e-6, max_iter=20,
+                      max_cocg=20000, precision="fp32", ws_op="auto", rhs_form="residual",
+                      engine="auto", seed=0)
+
+
+class Batch:
+    """The batching form (rafeast_plan_batch): problems is a list of dicts with
+    csr, lmin, lmax, m0 and any Plan keyword; common keywords apply to all."""
+
+    def __init__(self, problems, stream=None, **common):
+        L = lib()
+        count = len(problems)
+        As = (Csr * count)()
+        prms = (Params * count)()
+        self._keep = []
+        self._spec = []
+        for g, pr in enumerate(problems):
+            kw = dict(_PLAN_DEFAULTS)
+            kw.update(common)
+            kw.update({k: v for k, v in pr.items() if k not in ("csr", "lmin", "lmax", "m0")})
+            A, keep = _csr_struct(pr["csr"])
+            self._keep.append(keep)
+            As[g] = A
+            prms[g] = _params(pr["lmin"], pr["lmax"], pr["m0"], kw["nc"], kw["q"], kw["p"],
+                              kw["tol_eig"], kw["tol_solve"], kw["max_iter"], kw["max_cocg"],
+                              kw["precision"], kw["ws_op"], kw["rhs_form"], kw["engine"],
+                              kw["seed"], stream)
+            self._spec.append((int(pr["csr"].n), pr["m0"], kw["nc"], pr["lmin"], pr["lmax"],
+                               kw["precision"], kw["p"]))
+        h = C.c_void_p()
+        st = L.rafeast_plan_batch(count, As, prms, C.byref(h))
+        if st != 0:
+            raise RafeastError(st, L.rafeast_batch_last_error(None).decode())
+        self._h = h
+        self.members = []
+        for g in range(count):
+            n, m0, nc, lmin, lmax, prec, p = self._spec[g]
+            m = Plan.__new__(Plan)
+            m._setup(C.c_void_p(L.rafeast_batch_plan(h, g)), n, m0, nc, lmin, lmax, prec, p,
+                     owned=False)
+            self.members.append(m)
+
+    @property
+    def resident_count(self):
+        return lib().rafeast_batch_resident_count(self._h)
+
+    def solve(self, Q_init=None, want_vectors=True):
+        """Lock-step Phase 2 of all members: (result dicts, batch t_ms, batch status)."""
+        count = len(self.members)
+        outs, keep = [], []
+        res = (Result * count)()
+        for g, m in enumerate(self.members):
+            lam = np.zeros(m.m0)
+            rs = np.zeros(m.m0)
+            X = np.zeros((m.n, m.m0), order="F") if want_vectors else None
+            res[g].flags = 0
+            res[g].lam = lam.ctypes.data
+            res[g].resid = rs.ctypes.data
+            res[g].X = X.ctypes.data if X is not None else None
+            outs.append((lam, rs, X))
+        qi = None
+        if Q_init is not None:
+            qi = (C.POINTER(C.c_double) * count)()
+            for g, q in enumerate(Q_init):
+                if q is not None:
+                    a = np.asfortranarray(q, dtype=np.float64)
+                    keep.append(a)
+                    qi[g] = _dptr(a)
+        tb = np.zeros(NPHASE)
+        sts = (C.c_int * count)()
+        st = lib().rafeast_batch_solve(self._h, qi, res, sts, _dptr(tb))
+        if st not in RESULT_STATUSES:
+            raise RafeastError(st, lib().rafeast_batch_last_error(self._h).decode())
+        results = []
+        for g, (lam, rs, X) in enumerate(outs):
+            r = res[g]
+            M = r.M
+            results.append(dict(status=STATUS[sts[g]], lam=lam[:M].copy(), resid=rs[:M].copy(),
+                                X=X[:, :M].copy() if X is not None else None, M=M,
+                                iters=r.iters, cocg_iters=r.cocg_iters, cocg_max=r.cocg_max,
+                                refinements=r.refinements, max_resid=r.max_resid))
+        return results, {k: float(tb[i]) for i, k in enumerate(PHASES)}, STATUS[st]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for m in self.members:
+                m._h = None
+            lib().rafeast_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

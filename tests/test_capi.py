@@ -140,3 +140,25 @@ def test_valid_input_without_device(native):
     assert L.rafeast_plan(C.byref(A), C.byref(prm), C.byref(h)) == 5
     assert h.value is None
     assert b"device" in L.rafeast_last_error(None)
+
+
+def test_batch_argument_errors(native):
+    L = native.lib()
+    assert L.rafeast_batch_plan(None, 0) is None
+    assert L.rafeast_batch_resident_count(None) == 0
+    L.rafeast_batch_destroy(None)  # no-op
+    csr = grid_laplacian((6, 6), 0.01)
+    A, keep = native._csr_struct(csr)
+    As = (native.Csr * 2)(A, A)
+    p0 = native._params(0.0, 0.5, 8, 4, 1, -1, 1e-10, 1e-6, 20, 20000, "fp32", "auto",
+                        "residual", "auto", 0, None)
+    p1 = native._params(0.0, 0.5, 8, 4, 1, -1, 1e-10, 1e-6, 20, 20000, "fp64", "auto",
+                        "residual", "auto", 0, None)
+    h = C.c_void_p()
+    # members must share the precision (checked before any device call)
+    assert L.rafeast_plan_batch(2, As, (native.Params * 2)(p0, p1), C.byref(h)) == 1
+    assert h.value is None
+    assert b"precision" in L.rafeast_batch_last_error(None)
+    assert L.rafeast_plan_batch(0, As, (native.Params * 2)(p0, p0), C.byref(h)) == 1
+    if not _has_gpu():
+        assert L.rafeast_plan_batch(2, As, (native.Params * 2)(p0, p0), C.byref(h)) == 5
