@@ -89,6 +89,115 @@ def cpu_baseline(csr, win, runs):
                        f"p=20, FP64, sparse-LU shifted solves), {t:.1f} s total")
 
 
+def main_batch(args):
+    """The batching workload: 32 unweighted kNN Laplacians (2D/3D, k in
+    {8, 12, 16}, n log-uniform in [2000, 60000]), each with its own window
+    of 10-40 smallest eigenvalues and m0 = ceil(1.5 count), N_c = 4, q = 2.
+    One step: warm start and lock-step Phase 2 of all 32 (rafeast_batch_solve);
+    compared with the 32 problems solved one after another (rafeast_solve)."""
+    import numpy as np
+    import torch
+
+    from paper_2512_01257_amd import native
+    from workloads import knn_laplacian
+
+    with open(os.path.join(ROOT, "tests", "golden", "windows.json")) as f:
+        wins = json.load(f)["batch32"]
+    probs = []
+    for wn in wins:
+        csr = knn_laplacian(wn["n"], wn["dim"], wn["k"], seed=wn["seed"], weighted=False)
+        if csr.nnz != wn["nnz"]:
+            raise RuntimeError("workload generator does not reproduce the stored window fixture")
+        probs.append(dict(csr=csr, lmin=wn["lmin"], lmax=wn["lmax"], m0=wn["m0"]))
+    kw = dict(nc=4, q=2, tol_eig=1e-10, tol_solve=1e-6, precision="fp32", seed=0)
+
+    def check(outs):
+        err = 0.0
+        for wn, o in zip(wins, outs):
+            if o["status"] != "OK" or o["M"] != wn["count"]:
+                raise RuntimeError(f"member did not converge: {o['status']} M={o['M']}")
+            ev = np.array(wn["eigenvalues"][: wn["count"]])
+            err = max(err, float(np.abs(o["lam"] - ev).max()) / max(abs(wn["lmin"]), wn["lmax"]))
+        if err > 1e-10:
+            raise RuntimeError(f"eigenvalue error {err:.3e} (relative to s_win) above 1e-10")
+        return err
+
+    t0 = time.perf_counter()
+    B = native.Batch(probs, **kw)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+
+    def batch_step():
+        for m in B.members:
+            m.warmstart()
+        return B.solve(want_vectors=False)
+
+    for _ in range(args.warmup):
+        batch_step()
+    log(f"timing {args.steps} batch step(s), {len(probs)} problems, "
+        f"{B.resident_count} in the shared resident launch")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = []
+    for _ in range(args.steps):
+        steps.append(batch_step())
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    err = check(steps[-1][0])
+    M_step = sum(o["M"] for o in steps[-1][0])
+    value = M_step * args.steps / secs
+    t_ms = {k: round(sum(s[1][k] for s in steps) / args.steps, 2) for k in steps[0][1]}
+    B.close()
+
+    # the same problems one after another
+    seq = None
+    if args.plain_steps != 0:
+        plans = [native.Plan(p["csr"], p["lmin"], p["lmax"], p["m0"], **kw) for p in probs]
+        for pl in plans:  # warm up
+            pl.warmstart()
+            pl.solve(want_vectors=False)
+        log("timing the problems one after another")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = []
+        for pl in plans:
+            pl.warmstart()
+            outs.append(pl.solve(want_vectors=False))
+        torch.cuda.synchronize()
+        s1 = time.perf_counter() - t0
+        check(outs)
+        seq = {"value": round(sum(o["M"] for o in outs) / s1, 3), "unit": "eigenpairs/s",
+               "ms": round(s1 * 1e3, 2)}
+        for pl in plans:
+            pl.close()
+    line = {
+        "metric": "eigenpairs/s at rel. residual 1e-10, batch of 32 graph Laplacians",
+        "value": round(value, 3),
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(secs / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch of 32 unweighted kNN Laplacians (2D/3D points, k in {8,12,16}, "
+                        "n log-uniform in [2000, 60000]), windows of 10-40 smallest "
+                        "eigenvalues, m0 = ceil(1.5 count), N_c=4, q=2, COCG tol 1e-6",
+            "problems": len(probs), "resident_members": int(sum(p["csr"].n <= 8192 for p in probs)),
+            "eigenpairs_per_step": M_step, "n_total": int(sum(p["csr"].n for p in probs)),
+        },
+        "batch_phase_ms_per_step": t_ms,
+        "one_after_another": seq,
+        "speedup_vs_one_after_another": None if seq is None else round(value / seq["value"], 3),
+        "plan_ms": round(plan_ms, 2),
+        "max_eig_error_vs_reference": err,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,12 +209,17 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (a dispatch of known traffic "
                          "for scaling memory counters)")
+    ap.add_argument("--workload", choices=("knn8000", "batch32"), default="knn8000",
+                    help="knn8000: the headline workload (default); batch32: the batching "
+                         "form over 32 graphs")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
               f"WORLD_SIZE {world}); the multi-GPU path is not part of it.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch32":
+        return main_batch(args)
 
     import numpy as np
     import torch

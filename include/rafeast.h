@@ -307,6 +307,63 @@ void rafeast_batch_destroy(rafeast_batch_t batch);
  * rafeast_plan_batch). */
 const char* rafeast_batch_last_error(rafeast_batch_t batch);
 
+/* ---------------------------------------------------------------------------
+ * Learned polynomial preconditioner for the shifted solves (an addition to
+ * the paper's method, which solves (z_j I - A) d = r unpreconditioned;
+ * Section 2.1).  p(A) = sum_{k<8} c_k T_k(A^), A^ = a A + b I mapping the
+ * plan's Gershgorin interval [lo, hi] onto [-1, 1] (a = 2/(hi - lo),
+ * b = -(hi + lo)/(hi - lo)), T_k the Chebyshev polynomials, c_k complex.
+ * The coefficients come from a network 4 -> 64 -> 64 -> 64 -> 16 (exact
+ * GELU on the hidden layers) of the features (Re z^, Im z^, theta^_lo,
+ * theta^_hi): the shift and the smallest and largest current Ritz values,
+ * mapped like A.  Outputs are (Re c_0, Im c_0, ..., Re c_7, Im c_7).
+ * Parameters: rafeast_pc_param_count() floats, per layer W (out x in,
+ * row-major) then b; used in BF16 (round to nearest even) with FP32 sums,
+ * trained in FP32.  All arrays below are device pointers unless marked host.
+ * ------------------------------------------------------------------------- */
+
+/* Number of network parameters (9680). */
+int32_t rafeast_pc_param_count(void);
+
+/* Training samples from k real residual vectors R (n x k FP64, row-major,
+ * ldr) at nz shifts z (host, 2*nz): sample s = j*k + i has features X[s][4],
+ * G[s] (8 x 8 complex, re/im interleaved, row-major), h[s] (8 complex) and
+ * rr[s] with v_l = (z_j I - A) T_l(A^) R[:, i], G_lm = v_l^H v_m,
+ * h_l = v_l^H R[:, i], rr = ||R[:, i]||^2.  The loss of coefficients c is
+ * ||(zI - A) p(A) r - r||^2 / ||r||^2 = (c^H G c - 2 Re(c^H h) + rr) / rr. */
+rafeast_status rafeast_pc_samples(rafeast_plan_t plan, int32_t nz, const double* z, int32_t k,
+                                  const double* R, int32_t ldr, double theta_lo, double theta_hi,
+                                  double* X, double* G, double* h, double* rr);
+
+/* Network outputs Y[s][16] (FP32) of features X[s][4] for s < ns; W: FP32
+ * parameters (used in BF16). */
+rafeast_status rafeast_pc_forward(rafeast_plan_t plan, int32_t ns, const double* X, const float* W,
+                                  float* Y);
+
+/* Gradient grad[rafeast_pc_param_count()] (FP32) of the mean loss over the
+ * ns samples at parameters W; loss: nullable host, the mean loss. */
+rafeast_status rafeast_pc_gradient(rafeast_plan_t plan, int32_t ns, const double* X,
+                                   const double* G, const double* h, const double* rr,
+                                   const float* W, float* grad, double* loss);
+
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on W in place for
+ * `steps` minibatches of `batch` samples; order: host [steps * batch]
+ * sample indices (< ns).  loss: nullable host [steps], each minibatch's mean
+ * loss before its step. */
+rafeast_status rafeast_pc_train(rafeast_plan_t plan, int32_t ns, const double* X, const double* G,
+                                const double* h, const double* rr, float* W, int32_t steps,
+                                int32_t batch, const int32_t* order, float lr, double* loss);
+
+/* COCG in FP64 for (z_j I - A) X_{j,c} = B_c (nz shifts, k right-hand
+ * sides, B n x k FP64 row-major, ldb), preconditioned by p(A) with coef
+ * (host [nz][8] complex, re/im interleaved; NULL: no preconditioner), all
+ * systems in lock step, to true residual ||b - (zI - A) x|| <= tol ||b||
+ * or max_cocg iterations.  X: n x (nz*k) complex FP64, column j*k + c.
+ * iters, resid: nullable host [nz*k]. */
+rafeast_status rafeast_pc_solve(rafeast_plan_t plan, int32_t nz, const double* z, int32_t k,
+                                const double* B, int32_t ldb, const double* coef, void* X,
+                                double tol, int32_t* iters, double* resid);
+
 #ifdef __cplusplus
 }
 #endif

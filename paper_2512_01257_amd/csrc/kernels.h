@@ -8,6 +8,8 @@
 
 #include <vector>
 
+#include "device.h"  // cpx<T>
+
 namespace rafeast {
 
 // ---- sparse x dense (FP64, real) ------------------------------------------
@@ -249,4 +251,74 @@ namespace rafeast {
 // dst (column-major n x k) <- src (row-major, lds).
 hipError_t launch_rowmajor_to_colmajor(hipStream_t st, int64_t n, int k, const double* src,
                                        int lds, double* dst);
+}  // namespace rafeast
+
+namespace rafeast {
+// ---- learned polynomial preconditioner ---------------------------------------
+// T: 9 blocks T_0..T_8 (n x kc row-major, block stride n * kc) of T_k(A^) R;
+// part: nchunks * kc * 136 doubles.  Per sample s = j * kc + i: X[s][4],
+// G[s][8][8] and h[s][8] complex (re, im), rr[s].
+hipError_t launch_pc_gram_assemble(hipStream_t st, int64_t n, int kc, const double* T, int nz,
+                                   const double* zs, double a, double b, double th_lo,
+                                   double th_hi, double* part, int nchunks, double* X, double* G,
+                                   double* h, double* rr);
+int mlp_param_count();
+int mlp_backward_waves(int nb);
+// wb <- BF16 values (held in FP32) of the FP32 parameters w
+hipError_t launch_mlp_bf16(hipStream_t st, const float* w, float* wb);
+// Y[s][16] = network(X[s]) for s < ns, with BF16 parameters wb
+hipError_t launch_mlp_forward(hipStream_t st, int ns, const double* X, const float* wb, float* Y);
+// grad = gradient of the mean loss over samples idx[0..nb); part holds
+// mlp_backward_waves(nb) * mlp_param_count() floats, lpart as many doubles;
+// loss (nullable) the mean loss
+hipError_t launch_mlp_grad(hipStream_t st, int nb, const int* idx, const double* X,
+                           const double* G, const double* h, const double* rr, const float* wb,
+                           float* part, double* lpart, float* grad, double* loss);
+hipError_t launch_adam(hipStream_t st, float* w, float* m, float* v, const float* g, float lr,
+                       int step, float* wb);
+
+struct PcCols {  // per column, Bc entries (complex: 2 Bc)
+  int* active = nullptr;
+  int* it = nullptr;
+  int* pending = nullptr;
+  double* bn2 = nullptr;
+  double* res = nullptr;
+  double* rho = nullptr;
+  double* rhon = nullptr;
+  double* alpha = nullptr;
+  double* beta = nullptr;
+};
+struct PcSolve {
+  int64_t n = 0;
+  const int* rowptr = nullptr;     // CSR, FP64 values
+  const int* col = nullptr;
+  const double* val = nullptr;
+  double a = 1, b = 0;             // A^ = a A + b I
+  int Bc = 0;                      // columns (systems)
+  const double* zc = nullptr;      // [2 Bc] shift of each column
+  const double* coef = nullptr;    // nullable [8][Bc] complex Chebyshev coefficients
+  const double* B = nullptr;       // n x kb RHS (FP64), column c takes B[:, c % kb]
+  int ldb = 0, kb = 0;
+  cpx<double>* x = nullptr;        // n x Bc complex FP64 blocks
+  cpx<double>* r = nullptr;
+  cpx<double>* u = nullptr;
+  cpx<double>* p0 = nullptr;
+  cpx<double>* p1 = nullptr;
+  cpx<double>* w = nullptr;
+  cpx<double>* t0 = nullptr;       // Clenshaw work blocks (unused without coef)
+  cpx<double>* t1 = nullptr;
+  cpx<double>* t2 = nullptr;
+  double* part = nullptr;          // pc_blocks(n, num_cu) * Bc * 3 doubles
+  int* counts = nullptr;           // [2]
+  PcCols cols;
+  double tol = 1e-10;
+  int maxit = 20000;
+  int num_cu = 256;
+};
+int pc_blocks(int64_t n, int num_cu);
+// Preconditioned COCG (coef) or plain COCG (coef null) in FP64 on all Bc
+// columns in lock step, to true residual ||b - (zI - A) x|| <= tol ||b||.
+// Synchronises st once or twice per iteration.
+hipError_t run_pc_cocg(hipStream_t st, const PcSolve& S);
+
 }  // namespace rafeast

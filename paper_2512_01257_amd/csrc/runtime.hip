@@ -1823,3 +1823,217 @@ const char* rafeast_batch_last_error(rafeast_batch_t B) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned polynomial preconditioner
+// ---------------------------------------------------------------------------
+namespace {
+struct DevBuf {  // device allocations released together
+  std::vector<void*> ptrs;
+  ~DevBuf() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  template <typename T>
+  hipError_t get(T** p, size_t count) {
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, (count ? count : 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(q);
+    *p = (T*)q;
+    return e;
+  }
+};
+
+void spectral_map(const rafeast_plan_s* P, double& a, double& b) {
+  a = 2.0 / (P->sig_hi - P->sig_lo);
+  b = -(P->sig_hi + P->sig_lo) / (P->sig_hi - P->sig_lo);
+}
+}  // namespace
+
+extern "C" {
+
+int32_t rafeast_pc_param_count(void) { return mlp_param_count(); }
+
+rafeast_status rafeast_pc_samples(rafeast_plan_t P, int32_t nz, const double* z, int32_t k,
+                                  const double* R, int32_t ldr, double theta_lo, double theta_hi,
+                                  double* X, double* G, double* h, double* rr) {
+  if (!P || !z || !R || !X || !G || !h || !rr || nz < 1 || k < 1 || ldr < k)
+    return RAFEAST_INVALID_ARG;
+  P->err.clear();
+  const int64_t n = P->n;
+  double a, b;
+  spectral_map(P, a, b);
+  DevBuf buf;
+  double *T = nullptr, *part = nullptr, *dz = nullptr;
+  const size_t bs = (size_t)n * k;
+  const int nchunks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 2047) / 2048));
+  HIPCHK(P, buf.get(&T, 9 * bs));
+  HIPCHK(P, buf.get(&part, (size_t)nchunks * k * 136));
+  HIPCHK(P, buf.get(&dz, 2 * (size_t)nz));
+  HIPCHK(P, hipMemcpyAsync(dz, z, 2 * nz * sizeof(double), hipMemcpyHostToDevice, P->st));
+  HIPCHK(P, launch_copy_cols(P->st, n, k, R, ldr, T, k));
+  // T_1 = A^ T_0, T_{k+1} = 2 A^ T_k - T_{k-1}
+  RCHK(spmm(P, k, T, k, T + bs, k, a, b));
+  for (int t = 1; t < 8; ++t)
+    RCHK(spmm(P, k, T + t * bs, k, T + (t + 1) * bs, k, 2.0 * a, 2.0 * b, T + (t - 1) * bs, k,
+              -1.0));
+  HIPCHK(P, launch_pc_gram_assemble(P->st, n, k, T, nz, dz, a, b, theta_lo, theta_hi, part,
+                                    nchunks, X, G, h, rr));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_pc_forward(rafeast_plan_t P, int32_t ns, const double* X, const float* W,
+                                  float* Y) {
+  if (!P || !X || !W || !Y || ns < 1) return RAFEAST_INVALID_ARG;
+  DevBuf buf;
+  float* wb = nullptr;
+  HIPCHK(P, buf.get(&wb, mlp_param_count()));
+  HIPCHK(P, launch_mlp_bf16(P->st, W, wb));
+  HIPCHK(P, launch_mlp_forward(P->st, ns, X, wb, Y));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_pc_gradient(rafeast_plan_t P, int32_t ns, const double* X, const double* G,
+                                   const double* h, const double* rr, const float* W, float* grad,
+                                   double* loss) {
+  if (!P || !X || !G || !h || !rr || !W || !grad || ns < 1) return RAFEAST_INVALID_ARG;
+  DevBuf buf;
+  float *wb = nullptr, *part = nullptr;
+  double *lpart = nullptr, *dl = nullptr;
+  int* idx = nullptr;
+  const int npar = mlp_param_count(), waves = mlp_backward_waves(ns);
+  HIPCHK(P, buf.get(&wb, npar));
+  HIPCHK(P, buf.get(&part, (size_t)waves * npar));
+  HIPCHK(P, buf.get(&lpart, waves));
+  HIPCHK(P, buf.get(&dl, 1));
+  HIPCHK(P, buf.get(&idx, ns));
+  std::vector<int> order(ns);
+  for (int i = 0; i < ns; ++i) order[i] = i;
+  HIPCHK(P, hipMemcpyAsync(idx, order.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->st));
+  HIPCHK(P, launch_mlp_bf16(P->st, W, wb));
+  HIPCHK(P, launch_mlp_grad(P->st, ns, idx, X, G, h, rr, wb, part, lpart, grad, dl));
+  double hl = 0.0;
+  HIPCHK(P, hipMemcpyAsync(&hl, dl, sizeof(double), hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  if (loss) *loss = hl;
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_pc_train(rafeast_plan_t P, int32_t ns, const double* X, const double* G,
+                                const double* h, const double* rr, float* W, int32_t steps,
+                                int32_t batch, const int32_t* order, float lr, double* loss) {
+  if (!P || !X || !G || !h || !rr || !W || !order || ns < 1 || steps < 1 || batch < 1 ||
+      !(lr > 0.0f))
+    return RAFEAST_INVALID_ARG;
+  for (int64_t t = 0; t < (int64_t)steps * batch; ++t)
+    if (order[t] < 0 || order[t] >= ns) return fail(P, RAFEAST_INVALID_ARG, "order out of range");
+  DevBuf buf;
+  float *wb = nullptr, *part = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+  double *lpart = nullptr, *dl = nullptr;
+  int* idx = nullptr;
+  const int npar = mlp_param_count(), waves = mlp_backward_waves(batch);
+  HIPCHK(P, buf.get(&wb, npar));
+  HIPCHK(P, buf.get(&part, (size_t)waves * npar));
+  HIPCHK(P, buf.get(&m, npar));
+  HIPCHK(P, buf.get(&v, npar));
+  HIPCHK(P, buf.get(&g, npar));
+  HIPCHK(P, buf.get(&lpart, waves));
+  HIPCHK(P, buf.get(&dl, steps));
+  HIPCHK(P, buf.get(&idx, (size_t)steps * batch));
+  HIPCHK(P, hipMemcpyAsync(idx, order, (size_t)steps * batch * sizeof(int),
+                           hipMemcpyHostToDevice, P->st));
+  HIPCHK(P, hipMemsetAsync(m, 0, npar * sizeof(float), P->st));
+  HIPCHK(P, hipMemsetAsync(v, 0, npar * sizeof(float), P->st));
+  HIPCHK(P, launch_mlp_bf16(P->st, W, wb));
+  for (int t = 0; t < steps; ++t) {
+    HIPCHK(P, launch_mlp_grad(P->st, batch, idx + (size_t)t * batch, X, G, h, rr, wb, part, lpart,
+                              g, dl + t));
+    HIPCHK(P, launch_adam(P->st, W, m, v, g, lr, t + 1, wb));
+  }
+  if (loss)
+    HIPCHK(P, hipMemcpyAsync(loss, dl, steps * sizeof(double), hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_pc_solve(rafeast_plan_t P, int32_t nz, const double* z, int32_t k,
+                                const double* B, int32_t ldb, const double* coef, void* Xout,
+                                double tol, int32_t* iters, double* resid) {
+  if (!P || !z || !B || !Xout || nz < 1 || k < 1 || ldb < k || !(tol > 0.0) || !(tol < 1.0))
+    return RAFEAST_INVALID_ARG;
+  P->err.clear();
+  const int64_t n = P->n;
+  const int Bc = nz * k;
+  DevBuf buf;
+  PcSolve S;
+  S.n = n;
+  S.rowptr = P->d_rowptr;
+  S.col = P->d_col;
+  S.val = P->d_val;
+  spectral_map(P, S.a, S.b);
+  S.Bc = Bc;
+  S.B = B;
+  S.ldb = ldb;
+  S.kb = k;
+  S.tol = tol;
+  S.maxit = P->prm.max_cocg;
+  S.num_cu = P->num_cu;
+  const size_t blk = (size_t)n * Bc;
+  S.x = (cpx<double>*)Xout;
+  HIPCHK(P, buf.get(&S.r, blk));
+  HIPCHK(P, buf.get(&S.p0, blk));
+  HIPCHK(P, buf.get(&S.p1, blk));
+  HIPCHK(P, buf.get(&S.w, blk));
+  if (coef) {
+    HIPCHK(P, buf.get(&S.u, blk));
+    HIPCHK(P, buf.get(&S.t0, blk));
+    HIPCHK(P, buf.get(&S.t1, blk));
+    HIPCHK(P, buf.get(&S.t2, blk));
+  }
+  double *zc = nullptr, *cf = nullptr;
+  HIPCHK(P, buf.get(&S.part, (size_t)pc_blocks(n, P->num_cu) * Bc * 3));
+  HIPCHK(P, buf.get(&S.counts, 2));
+  HIPCHK(P, buf.get(&zc, 2 * (size_t)Bc));
+  HIPCHK(P, buf.get(&S.cols.active, Bc));
+  HIPCHK(P, buf.get(&S.cols.it, Bc));
+  HIPCHK(P, buf.get(&S.cols.pending, Bc));
+  HIPCHK(P, buf.get(&S.cols.bn2, Bc));
+  HIPCHK(P, buf.get(&S.cols.res, Bc));
+  HIPCHK(P, buf.get(&S.cols.rho, 2 * (size_t)Bc));
+  HIPCHK(P, buf.get(&S.cols.rhon, 2 * (size_t)Bc));
+  HIPCHK(P, buf.get(&S.cols.alpha, 2 * (size_t)Bc));
+  HIPCHK(P, buf.get(&S.cols.beta, 2 * (size_t)Bc));
+  std::vector<double> hz(2 * (size_t)Bc), hc;
+  for (int c = 0; c < Bc; ++c) {
+    hz[2 * c] = z[2 * (c / k)];
+    hz[2 * c + 1] = z[2 * (c / k) + 1];
+  }
+  HIPCHK(P, hipMemcpyAsync(zc, hz.data(), hz.size() * sizeof(double), hipMemcpyHostToDevice,
+                           P->st));
+  S.zc = zc;
+  if (coef) {  // [8][Bc] complex from the per-shift [nz][8] complex
+    hc.resize(16 * (size_t)Bc);
+    for (int t = 0; t < 8; ++t)
+      for (int c = 0; c < Bc; ++c) {
+        hc[(size_t)t * 2 * Bc + 2 * c] = coef[(c / k) * 16 + 2 * t];
+        hc[(size_t)t * 2 * Bc + 2 * c + 1] = coef[(c / k) * 16 + 2 * t + 1];
+      }
+    HIPCHK(P, buf.get(&cf, hc.size()));
+    HIPCHK(P, hipMemcpyAsync(cf, hc.data(), hc.size() * sizeof(double), hipMemcpyHostToDevice,
+                             P->st));
+    S.coef = cf;
+  }
+  HIPCHK(P, run_pc_cocg(P->st, S));
+  std::vector<int> hit(Bc);
+  std::vector<double> hres(Bc);
+  HIPCHK(P, hipMemcpyAsync(hit.data(), S.cols.it, Bc * sizeof(int), hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipMemcpyAsync(hres.data(), S.cols.res, Bc * sizeof(double), hipMemcpyDeviceToHost,
+                           P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  if (iters) std::memcpy(iters, hit.data(), Bc * sizeof(int));
+  if (resid) std::memcpy(resid, hres.data(), Bc * sizeof(double));
+  return RAFEAST_OK;
+}
+
+}  // extern "C"

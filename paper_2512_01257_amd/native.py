@@ -99,6 +99,21 @@ def lib():
     L.rafeast_plan_engine.restype = C.c_int32
     L.rafeast_rcm_order.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32)]
     L.rafeast_rcm_order.restype = C.c_int
+    L.rafeast_pc_param_count.argtypes = []
+    L.rafeast_pc_param_count.restype = C.c_int32
+    L.rafeast_pc_samples.argtypes = [P, C.c_int32, dp, C.c_int32, P, C.c_int32, C.c_double,
+                                     C.c_double, P, P, P, P]
+    L.rafeast_pc_samples.restype = C.c_int
+    L.rafeast_pc_forward.argtypes = [P, C.c_int32, P, P, P]
+    L.rafeast_pc_forward.restype = C.c_int
+    L.rafeast_pc_gradient.argtypes = [P, C.c_int32, P, P, P, P, P, P, dp]
+    L.rafeast_pc_gradient.restype = C.c_int
+    L.rafeast_pc_train.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_int32, C.c_int32,
+                                   C.POINTER(C.c_int32), C.c_float, dp]
+    L.rafeast_pc_train.restype = C.c_int
+    L.rafeast_pc_solve.argtypes = [P, C.c_int32, dp, C.c_int32, P, C.c_int32, dp, P, C.c_double,
+                                   C.POINTER(C.c_int32), dp]
+    L.rafeast_pc_solve.restype = C.c_int
     L.rafeast_plan_batch.argtypes = [C.c_int32, C.POINTER(Csr), C.POINTER(Params), C.POINTER(P)]
     L.rafeast_plan_batch.restype = C.c_int
     L.rafeast_batch_plan.argtypes = [P, C.c_int32]
@@ -268,6 +283,77 @@ class Plan:
         """COCG engine the plan resolved: "resident" or "stream"."""
         e = lib().rafeast_plan_engine(self._h)
         return {v: k for k, v in ENGINE.items()}[e]
+
+    # ------------------------------------------- learned preconditioner
+    def pc_samples(self, z, R, theta_lo, theta_hi):
+        """(X, G, h, rr) device tensors for real residuals R (device n x k FP64)."""
+        import torch
+
+        z = np.asarray(z, dtype=np.complex128)
+        zz = np.empty(2 * len(z))
+        zz[0::2], zz[1::2] = z.real, z.imag
+        k = R.shape[1]
+        ns = len(z) * k
+        X = torch.empty((ns, 4), dtype=torch.float64, device="cuda")
+        G = torch.empty((ns, 8, 8, 2), dtype=torch.float64, device="cuda")
+        h = torch.empty((ns, 8, 2), dtype=torch.float64, device="cuda")
+        rr = torch.empty(ns, dtype=torch.float64, device="cuda")
+        self._check(lib().rafeast_pc_samples(self._h, len(z), _dptr(zz), k,
+                                             _tptr(R, torch.float64), k, theta_lo, theta_hi,
+                                             _tptr(X), _tptr(G), _tptr(h), _tptr(rr)))
+        return X, G, h, rr
+
+    def pc_forward(self, X, W):
+        import torch
+
+        Y = torch.empty((X.shape[0], 16), dtype=torch.float32, device="cuda")
+        self._check(lib().rafeast_pc_forward(self._h, X.shape[0], _tptr(X, torch.float64),
+                                             _tptr(W, torch.float32), _tptr(Y)))
+        return Y
+
+    def pc_gradient(self, X, G, h, rr, W):
+        import torch
+
+        g = torch.empty(lib().rafeast_pc_param_count(), dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        self._check(lib().rafeast_pc_gradient(self._h, X.shape[0], _tptr(X), _tptr(G), _tptr(h),
+                                              _tptr(rr), _tptr(W, torch.float32), _tptr(g),
+                                              C.byref(loss)))
+        return g, loss.value
+
+    def pc_train(self, X, G, h, rr, W, order, batch, lr):
+        """Adam on W (device FP32, in place); order: host int32 [steps * batch]."""
+        import torch
+
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        steps = len(order) // batch
+        loss = np.zeros(steps)
+        self._check(lib().rafeast_pc_train(self._h, X.shape[0], _tptr(X), _tptr(G), _tptr(h),
+                                           _tptr(rr), _tptr(W, torch.float32), steps, batch,
+                                           order.ctypes.data_as(C.POINTER(C.c_int32)), lr,
+                                           _dptr(loss)))
+        return loss
+
+    def pc_solve(self, z, B, X, tol, coef=None):
+        """Preconditioned (coef: [nz][8] complex) or plain FP64 COCG; X device
+        complex128 n x (nz*k).  Returns (iters, resid)."""
+        import torch
+
+        z = np.asarray(z, dtype=np.complex128)
+        zz = np.empty(2 * len(z))
+        zz[0::2], zz[1::2] = z.real, z.imag
+        k = B.shape[1]
+        cf = None
+        if coef is not None:
+            c = np.asarray(coef, dtype=np.complex128).reshape(len(z), 8)
+            cf = np.empty(16 * len(z))
+            cf[0::2], cf[1::2] = c.real.ravel(), c.imag.ravel()
+        its = np.zeros(len(z) * k, dtype=np.int32)
+        rs = np.zeros(len(z) * k)
+        self._check(lib().rafeast_pc_solve(self._h, len(z), _dptr(zz), k, _tptr(B, torch.float64),
+                                           k, _dptr(cf), _tptr(X, torch.complex128), tol,
+                                           its.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(rs)))
+        return its, rs
 
     # ----------------------------------------------------------------- calls
     def info(self):
