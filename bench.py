@@ -198,6 +198,111 @@ def main_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def main_learned(args):
+    """The learned-preconditioner workload: 16-NN graph Laplacian of 10^6
+    uniform points in the unit cube (Gaussian weights, + 1e-3 I), the N_c = 4
+    shifts of the window of its 100 smallest eigenvalues, 64 right-hand sides.
+    The coefficient network is trained on samples from a 20000-point graph of
+    the same family; COCG preconditioned by the network's polynomials is
+    timed against the same COCG without it, both to true residual 1e-10."""
+    import numpy as np
+    import torch
+
+    from paper_2512_01257_amd import native
+    from workloads import knn_laplacian
+    from workloads.learned import flatten, init_weights, minibatch_order, residual_samples
+
+    with open(os.path.join(ROOT, "tests", "golden", "windows.json")) as f:
+        fx = json.load(f)["learned"]
+
+    def features(plan, z, th_lo, th_hi):
+        inf = plan.info()
+        a = 2.0 / (inf["sig_hi"] - inf["sig_lo"])
+        b = -(inf["sig_hi"] + inf["sig_lo"]) / (inf["sig_hi"] - inf["sig_lo"])
+        return np.array([[a * zj.real + b, a * zj.imag, a * th_lo + b, a * th_hi + b] for zj in z])
+
+    # training data: shifts of windows [0, s u] (s = 1, 1/2, ..., 1/32) on the small graph
+    tr = fx["train"]
+    csr_t = knn_laplacian(tr["n"], 3, 16, seed=tr["seed"], weighted=True, shift=1e-3)
+    t0 = time.perf_counter()
+    with native.Plan(csr_t, 0.0, tr["u"], 8, nc=4, q=1, p=4, precision="fp64") as pt:
+        Xs, Gs, hs, rrs = [], [], [], []
+        R = torch.from_numpy(np.ascontiguousarray(residual_samples(tr["n"], 64, 17))).cuda()
+        for e in range(6):
+            u = tr["u"] / 2.0 ** e
+            with native.Plan(csr_t, 0.0, u, 8, nc=4, q=1, p=4, precision="fp64") as pw:
+                z = pw.info()["z"]
+            X, G, h, rr = pt.pc_samples(z, R, 1e-3, u)
+            Xs.append(X), Gs.append(G), hs.append(h), rrs.append(rr)
+        X, G, h, rr = (torch.cat(t) for t in (Xs, Gs, hs, rrs))
+        ns = X.shape[0]
+        W = torch.from_numpy(flatten(init_weights(1))).cuda()
+        _, loss0 = pt.pc_gradient(X, G, h, rr, W)
+        order = minibatch_order(ns, 200, 2)
+        pt.pc_train(X, G, h, rr, W, order, batch=64, lr=2e-3)
+        _, loss1 = pt.pc_gradient(X, G, h, rr, W)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"trained on {ns} samples: mean loss {loss0:.4f} -> {loss1:.4f} ({train_s:.1f} s)")
+
+    # the large graph
+    te = fx["test"]
+    t0 = time.perf_counter()
+    csr = knn_laplacian(te["n"], 3, 16, seed=te["seed"], weighted=True, shift=1e-3)
+    log(f"graph n={csr.n} nnz={csr.nnz} built in {time.perf_counter() - t0:.1f} s")
+    nrhs = 64
+    with native.Plan(csr, 0.0, te["u"], 8, nc=4, q=1, p=4, precision="fp64",
+                     max_cocg=20000) as plan:
+        z = plan.info()["z"]
+        Xf = torch.from_numpy(features(plan, z, 1e-3, te["u"])).cuda()
+        Y = plan.pc_forward(Xf, W).cpu().numpy().astype(np.float64)
+        coef = Y[:, 0::2] + 1j * Y[:, 1::2]
+        B = torch.from_numpy(np.ascontiguousarray(residual_samples(csr.n, nrhs, 23))).cuda()
+        out = {}
+        for name, cf in (("plain", None), ("learned", coef)):
+            Xs = torch.zeros((csr.n, len(z) * nrhs), dtype=torch.complex128, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its, rs = plan.pc_solve(z, B, Xs, 1e-10, coef=cf)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            if rs.max() > 1e-10:
+                raise RuntimeError(f"{name}: residual {rs.max():.3e} above 1e-10")
+            out[name] = dict(seconds=round(secs, 3), iters_max=int(its.max()),
+                             iters_mean=round(float(its.mean()), 1),
+                             spmm_per_iter=1 if cf is None else 8,
+                             max_resid=float(rs.max()))
+            log(f"{name}: {secs:.2f} s, iterations max {its.max()} mean {its.mean():.1f}")
+            del Xs
+    speed = out["plain"]["seconds"] / out["learned"]["seconds"]
+    line = {
+        "metric": "COCG time to true residual 1e-10, learned polynomial preconditioner vs none",
+        "value": round(speed, 3),
+        "unit": "x (plain time / preconditioned time)",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(out["learned"]["seconds"] * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": "16-NN graph Laplacian of 1e6 uniform points in [0,1]^3, Gaussian "
+                        "weights, +1e-3 I; N_c=4 shifts of the window [0, u] holding about "
+                        "its 100 smallest eigenvalues; 64 random right-hand sides; FP64 COCG",
+            "n": csr.n, "nnz": csr.nnz, "u": te["u"], "u_method": te["method"],
+            "train": {"n": tr["n"], "samples": int(ns), "steps": len(order) // 64,
+                      "loss_before": loss0, "loss_after": loss1, "seconds": round(train_s, 2)},
+        },
+        "plain": out["plain"],
+        "learned": out["learned"],
+        "iteration_ratio": round(out["plain"]["iters_max"] / out["learned"]["iters_max"], 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,9 +314,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (a dispatch of known traffic "
                          "for scaling memory counters)")
-    ap.add_argument("--workload", choices=("knn8000", "batch32"), default="knn8000",
+    ap.add_argument("--workload", choices=("knn8000", "batch32", "learned"), default="knn8000",
                     help="knn8000: the headline workload (default); batch32: the batching "
-                         "form over 32 graphs")
+                         "form over 32 graphs; learned: the learned preconditioner at n=1e6")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -220,6 +325,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch32":
         return main_batch(args)
+    if args.workload == "learned":
+        return main_learned(args)
 
     import numpy as np
     import torch

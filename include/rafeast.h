@@ -290,8 +290,9 @@ rafeast_plan_t rafeast_batch_plan(rafeast_batch_t batch, int32_t g);
  * start blocks (as rafeast_solve).  res: host array of count results, each
  * set up as for rafeast_solve.  status: nullable host [count], each member's
  * rafeast_solve status.  t_ms: nullable host [RAFEAST_NPHASE], the batch's
- * device time per phase (the solve phase is the shared launch plus
- * streaming-engine solves).  Returns OK when every member returned OK, else
+ * device time per phase: RR summed over members, SOLVE the shared launch
+ * plus the streaming-engine solves, COMBINE the members' combination and
+ * CholQR2 together (ORTH is 0), TOTAL.  Returns OK when every member returned OK, else
  * the first non-OK member status (all members' results are written);
  * failures of the device or arguments return at once. */
 rafeast_status rafeast_batch_solve(rafeast_batch_t batch, const double* const* Q_init,

@@ -17,6 +17,7 @@
 // layer inputs are rounded to BF16, sums accumulate in FP32.  One wave per
 // sample, one lane per neuron.  Loss per sample:
 // (c^H G c - 2 Re(c^H h) + rr) / rr, averaged over the minibatch.
+#include <cstdio>
 #include <utility>
 
 #include "device.h"
@@ -748,6 +749,9 @@ hipError_t run_pc_cocg(hipStream_t st, const PcSolve& S) {
       live = host_counts[1];
       if (live == 0) break;
     }
+    if (S.progress && (it + 1) % 500 == 0)
+      std::fprintf(stderr, "rafeast: preconditioned COCG iteration %d, %d systems left\n", it + 1,
+                   live);
     if (pre) {
       PCE(apply_m());
       PCE(fin(4, 2));

@@ -314,6 +314,7 @@ struct PcSolve {
   double tol = 1e-10;
   int maxit = 20000;
   int num_cu = 256;
+  bool progress = false;           // a line on stderr every 500 iterations
 };
 int pc_blocks(int64_t n, int num_cu);
 // Preconditioned COCG (coef) or plain COCG (coef null) in FP64 on all Bc

@@ -123,7 +123,7 @@ struct rafeast_batch_s {
   hipGraph_t graph = nullptr;        // captured counter reset + resident launch
   hipGraphExec_t gexec = nullptr;
   int graph_nitems = -1;             // the item count the capture was made for
-  hipEvent_t ev[2] = {};
+  hipEvent_t ev[6] = {};              // total, solve phase, combine phase
   std::string err;
 };
 
@@ -1774,7 +1774,8 @@ rafeast_status rafeast_batch_solve(rafeast_batch_t B, const double* const* Q_ini
     }
     if (nact == 0) break;
     // every active member's solves: the shared resident launch, then the
-    // streaming members
+    // streaming members (a member's own solve time is this whole phase)
+    BCHK(B, hipEventRecord(B->ev[2], B->st));
     for (int g = 0; g < count; ++g)
       if (active[g]) BCHK(B, hipEventRecord(B->plans[g]->ev[2], B->st));
     RCHK(batch_resident_solves(B, active));
@@ -1783,18 +1784,17 @@ rafeast_status rafeast_batch_solve(rafeast_batch_t B, const double* const* Q_ini
       const rafeast_status st = solve_shifted_systems(B->plans[g]);
       if (st != RAFEAST_OK) return member_fail(g, st);
     }
-    for (int g = 0; g < count; ++g)
-      if (active[g]) BCHK(B, hipEventRecord(B->plans[g]->ev[3], B->st));
-    bool timed = false;
+    BCHK(B, hipEventRecord(B->ev[3], B->st));
     for (int g = 0; g < count; ++g) {
       if (!active[g]) continue;
+      BCHK(B, hipEventRecord(B->plans[g]->ev[3], B->st));
       const rafeast_status st = solve_combine(B->plans[g], S[g]);
       if (st != RAFEAST_OK) return member_fail(g, st);
-      if (!timed) {  // the solve phase is shared: count it once
-        tb[RAFEAST_PH_SOLVE] += elapsed(B->plans[g]->ev[2], B->plans[g]->ev[3]);
-        timed = true;
-      }
     }
+    BCHK(B, hipEventRecord(B->ev[4], B->st));
+    BCHK(B, hipEventSynchronize(B->ev[4]));
+    tb[RAFEAST_PH_SOLVE] += elapsed(B->ev[2], B->ev[3]);
+    tb[RAFEAST_PH_COMBINE] += elapsed(B->ev[3], B->ev[4]);  // combination and CholQR2
   }
   rafeast_status first = RAFEAST_OK;
   for (int g = 0; g < count; ++g) {
@@ -1805,8 +1805,6 @@ rafeast_status rafeast_batch_solve(rafeast_batch_t B, const double* const* Q_ini
     if (status) status[g] = st;
     if (st != RAFEAST_OK && first == RAFEAST_OK) first = st;
     tb[RAFEAST_PH_RR] += S[g].t_ph[RAFEAST_PH_RR];
-    tb[RAFEAST_PH_COMBINE] += S[g].t_ph[RAFEAST_PH_COMBINE];
-    tb[RAFEAST_PH_ORTH] += S[g].t_ph[RAFEAST_PH_ORTH];
   }
   BCHK(B, hipEventRecord(B->ev[1], B->st));
   BCHK(B, hipEventSynchronize(B->ev[1]));
@@ -1979,6 +1977,7 @@ rafeast_status rafeast_pc_solve(rafeast_plan_t P, int32_t nz, const double* z, i
   S.tol = tol;
   S.maxit = P->prm.max_cocg;
   S.num_cu = P->num_cu;
+  S.progress = verbose_log();
   const size_t blk = (size_t)n * Bc;
   S.x = (cpx<double>*)Xout;
   HIPCHK(P, buf.get(&S.r, blk));

@@ -1,12 +1,15 @@
 """Writes windows.json: search intervals cut at mid-gaps of reference spectra.
 
 Calls only oracle/ (spectra) and workloads/ (the seeded matrices).  Run from
-the repository root:  python tests/golden/make_windows.py
+the repository root:  python tests/golden/make_windows.py [entry ...]
+(entries: knn8000, batch32, learned; default all; others are kept).
 """
 
 import json
 import os
 import sys
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -16,32 +19,69 @@ from workloads import knn_laplacian  # noqa: E402
 from workloads.graphs import batch_graph_specs  # noqa: E402
 
 
-def main():
-    out = {}
+def knn8000():
     # kNN Laplacian, n = 8000, 2D points (stream 1), k = 10, Gaussian weights,
     # + 1e-3 I; window holding the 50 smallest eigenvalues.
     A = knn_laplacian(8000, 2, 10, seed=1, weighted=True, shift=1e-3).to_scipy()
     ev = bottom_eigvalsh(A, 60)
-    out["knn8000"] = dict(
+    return dict(
         recipe="knn_laplacian(8000, dim=2, k=10, seed=1, weighted=True, shift=1e-3)",
         count=50, lmin=0.0, lmax=float(0.5 * (ev[49] + ev[50])),
         eigenvalues=[float(v) for v in ev[:52]], nnz=int(A.nnz))
+
+
+def batch32():
     # 32 unweighted kNN Laplacians (no shift) of the batching workload: member
     # g keeps its `count` smallest eigenvalues in [-0.1 u, u], u at the mid-gap
-    out["batch32"] = []
+    out = []
     for s in batch_graph_specs():
         A = knn_laplacian(s["n"], s["dim"], s["k"], seed=s["seed"], weighted=False).to_scipy()
         c = s["count"]
         ev = bottom_eigvalsh(A, c + 2)
         u = float(0.5 * (ev[c - 1] + ev[c]))
-        out["batch32"].append(dict(
+        out.append(dict(
             recipe=f"knn_laplacian({s['n']}, dim={s['dim']}, k={s['k']}, seed={s['seed']}, "
                    "weighted=False)",
             n=s["n"], dim=s["dim"], k=s["k"], seed=s["seed"], count=c, lmin=-0.1 * u, lmax=u,
             m0=int(-(-3 * c // 2)), eigenvalues=[float(v) for v in ev], nnz=int(A.nnz)))
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "windows.json"), "w") as f:
+    return out
+
+
+def learned():
+    # 3D 16-NN Laplacians, Gaussian weights, + 1e-3 I (points stream 5): the
+    # window edge u = mid-gap of eigenvalues 100 and 101 at n = 1e4, 2e4, 5e4;
+    # at n = 1e6 (too large for shift-invert here) u follows the power law
+    # u ~ C n^-p fitted to those three (the kNN Laplacian with sigma = median
+    # neighbour distance scales its low spectrum like n^(-2/3)).
+    ns, us = [10000, 20000, 50000], []
+    for n in ns:
+        ev = bottom_eigvalsh(knn_laplacian(n, 3, 16, seed=5, weighted=True, shift=1e-3).to_scipy(),
+                             102)
+        us.append(float(0.5 * (ev[99] + ev[100])))
+    slope, icpt = np.polyfit(np.log(ns), np.log(us), 1)
+    u6 = float(np.exp(icpt + slope * np.log(1e6)))
+    return dict(
+        recipe="knn_laplacian(n, dim=3, k=16, seed=5, weighted=True, shift=1e-3)",
+        measured=dict(n=ns, u=us), fit_exponent=float(slope),
+        train=dict(n=20000, seed=5, u=us[1]),
+        test=dict(n=1000000, seed=5, u=u6,
+                  method="power law fitted to the mid-gap lambda_100/101 at n=1e4, 2e4, 5e4"))
+
+
+ENTRIES = dict(knn8000=knn8000, batch32=batch32, learned=learned)
+
+
+def main(names):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "windows.json")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            out = json.load(f)
+    for name in names or list(ENTRIES):
+        out[name] = ENTRIES[name]()
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])
