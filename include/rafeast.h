@@ -269,14 +269,17 @@ rafeast_status rafeast_gaussian(rafeast_plan_t plan, int32_t w, uint64_t seed, d
  * in one persistent launch, replayed from a captured HIP graph: its work
  * items are (member, node, column) triples, longest first across members.
  * Members too large for the resident engine use the streaming engine after
- * that launch.  The Rayleigh-Ritz, combination and CholQR2 steps run per
- * member.  Each member computes exactly what rafeast_solve computes for it.
+ * that launch, concurrently with each other.  The Rayleigh-Ritz,
+ * combination and CholQR2 steps run per member.  Each member computes
+ * exactly what rafeast_solve computes for it.
  * ------------------------------------------------------------------------- */
 
 /* Plans count >= 1 problems: A[g] with prm[g] (host arrays of count).  All
  * members must share precision, tol_solve and max_cocg (INVALID_ARG
- * otherwise); prm[0].hip_stream (or a stream the batch creates) is used for
- * all.  Errors as rafeast_plan, for the first member
+ * otherwise).  prm[0].hip_stream (or a stream the batch creates) carries the
+ * shared launch; every member gets a stream of its own (owned by the batch;
+ * the members' hip_stream fields are ignored), and streaming-engine members
+ * solve concurrently from host worker threads.  Errors as rafeast_plan, for the first member
  * that fails (the text names it). */
 rafeast_status rafeast_plan_batch(int32_t count, const rafeast_csr* A, const rafeast_params* prm,
                                   rafeast_batch_t* out);

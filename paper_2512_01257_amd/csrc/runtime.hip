@@ -6,11 +6,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/rafeast.h"
@@ -26,6 +28,9 @@ constexpr int kMaxSmallK = 192;
 
 // Ritz pairs with a smaller filter gain are spurious (not counted in M).
 constexpr double kSpuriousGain = 0.25;
+
+// Host workers driving streaming-engine members of a batch concurrently.
+constexpr size_t kBatchWorkers = 8;
 
 }  // namespace
 
@@ -124,6 +129,8 @@ struct rafeast_batch_s {
   hipGraphExec_t gexec = nullptr;
   int graph_nitems = -1;             // the item count the capture was made for
   hipEvent_t ev[6] = {};              // total, solve phase, combine phase
+  std::vector<hipStream_t> mst;       // member streams (owned)
+  std::vector<hipEvent_t> mev;        // member events (owned)
   std::string err;
 };
 
@@ -1559,6 +1566,10 @@ void free_batch(rafeast_batch_s* B) {
   for (auto& e : B->ev)
     if (e) (void)hipEventDestroy(e);
   for (rafeast_plan_s* P : B->plans) free_plan(P);
+  for (hipEvent_t e : B->mev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t q : B->mst)
+    if (q) (void)hipStreamDestroy(q);
   if (B->own_stream && B->st) (void)hipStreamDestroy(B->st);
   delete B;
 }
@@ -1680,9 +1691,15 @@ rafeast_status rafeast_plan_batch(int32_t count, const rafeast_csr* A, const raf
     B->own_stream = true;
   }
   for (auto& e : B->ev) BPCHK(hipEventCreate(&e));
+  B->mst.assign(count, nullptr);
+  B->mev.assign(count, nullptr);
+  for (int g = 0; g < count; ++g) {
+    BPCHK(hipStreamCreateWithFlags(&B->mst[g], hipStreamNonBlocking));
+    BPCHK(hipEventCreateWithFlags(&B->mev[g], hipEventDisableTiming));
+  }
   for (int g = 0; g < count; ++g) {
     rafeast_params q = prm[g];
-    q.hip_stream = B->st;
+    q.hip_stream = B->mst[g];
     rafeast_plan_t P = nullptr;
     const rafeast_status st = rafeast_plan(&A[g], &q, &P);
     if (st != RAFEAST_OK) {
@@ -1755,6 +1772,8 @@ rafeast_status rafeast_batch_solve(rafeast_batch_t B, const double* const* Q_ini
     return batch_fail(B, st, "member " + std::to_string(g) + ": " + B->plans[g]->err);
   };
   BCHK(B, hipEventRecord(B->ev[0], B->st));
+  for (int g = 0; g < count; ++g)  // members start after the batch's start mark
+    BCHK(B, hipStreamWaitEvent(B->plans[g]->st, B->ev[0], 0));
   std::vector<SolveRun> S(count);
   for (int g = 0; g < count; ++g) {
     const rafeast_status st = solve_begin(B->plans[g], Q_init ? Q_init[g] : nullptr, S[g]);
@@ -1773,23 +1792,55 @@ rafeast_status rafeast_batch_solve(rafeast_batch_t B, const double* const* Q_ini
         ++nact;
     }
     if (nact == 0) break;
-    // every active member's solves: the shared resident launch, then the
-    // streaming members (a member's own solve time is this whole phase)
+    // every active member's solves: the shared resident launch on the batch
+    // stream, and the streaming members concurrently, each on its own
+    // stream from a host worker (their kernels are small, so several in
+    // flight fill the device).  A member's own solve time is this phase.
     BCHK(B, hipEventRecord(B->ev[2], B->st));
-    for (int g = 0; g < count; ++g)
-      if (active[g]) BCHK(B, hipEventRecord(B->plans[g]->ev[2], B->st));
-    RCHK(batch_resident_solves(B, active));
     for (int g = 0; g < count; ++g) {
-      if (!active[g] || B->res_idx[g] >= 0) continue;
-      const rafeast_status st = solve_shifted_systems(B->plans[g]);
-      if (st != RAFEAST_OK) return member_fail(g, st);
+      if (!active[g]) continue;
+      rafeast_plan_s* P = B->plans[g];
+      BCHK(B, hipEventRecord(B->mev[g], P->st));     // its right-hand sides are ready
+      BCHK(B, hipStreamWaitEvent(B->st, B->mev[g], 0));
+      BCHK(B, hipEventRecord(P->ev[2], P->st));
+    }
+    RCHK(batch_resident_solves(B, active));
+    std::vector<int> todo;
+    for (int g = 0; g < count; ++g)
+      if (active[g] && B->res_idx[g] < 0) todo.push_back(g);
+    std::vector<rafeast_status> sst(count, RAFEAST_OK);
+    {
+      std::atomic<size_t> next{0};
+      auto worker = [&]() {
+        for (size_t t = next++; t < todo.size(); t = next++)
+          sst[todo[t]] = solve_shifted_systems(B->plans[todo[t]]);
+      };
+      const size_t nthr = std::min<size_t>(todo.size(), kBatchWorkers);
+      std::vector<std::thread> pool;
+      for (size_t t = 1; t < nthr; ++t) pool.emplace_back(worker);
+      if (nthr > 0) worker();
+      for (auto& th : pool) th.join();
+    }
+    for (int g : todo)
+      if (sst[g] != RAFEAST_OK) return member_fail(g, sst[g]);
+    BCHK(B, hipEventRecord(B->ev[5], B->st));  // the shared launch is done
+    for (int g = 0; g < count; ++g) {
+      if (!active[g]) continue;
+      rafeast_plan_s* P = B->plans[g];
+      if (B->res_idx[g] >= 0) BCHK(B, hipStreamWaitEvent(P->st, B->ev[5], 0));
+      BCHK(B, hipEventRecord(B->mev[g], P->st));
+      BCHK(B, hipStreamWaitEvent(B->st, B->mev[g], 0));
     }
     BCHK(B, hipEventRecord(B->ev[3], B->st));
     for (int g = 0; g < count; ++g) {
       if (!active[g]) continue;
-      BCHK(B, hipEventRecord(B->plans[g]->ev[3], B->st));
-      const rafeast_status st = solve_combine(B->plans[g], S[g]);
+      rafeast_plan_s* P = B->plans[g];
+      BCHK(B, hipStreamWaitEvent(P->st, B->ev[3], 0));
+      BCHK(B, hipEventRecord(P->ev[3], P->st));
+      const rafeast_status st = solve_combine(P, S[g]);
       if (st != RAFEAST_OK) return member_fail(g, st);
+      BCHK(B, hipEventRecord(B->mev[g], P->st));
+      BCHK(B, hipStreamWaitEvent(B->st, B->mev[g], 0));
     }
     BCHK(B, hipEventRecord(B->ev[4], B->st));
     BCHK(B, hipEventSynchronize(B->ev[4]));
@@ -1799,6 +1850,8 @@ rafeast_status rafeast_batch_solve(rafeast_batch_t B, const double* const* Q_ini
   rafeast_status first = RAFEAST_OK;
   for (int g = 0; g < count; ++g) {
     const rafeast_status st = solve_finish(B->plans[g], S[g], &res[g]);
+    BCHK(B, hipEventRecord(B->mev[g], B->plans[g]->st));
+    BCHK(B, hipStreamWaitEvent(B->st, B->mev[g], 0));
     if (st != RAFEAST_OK && st != RAFEAST_NO_CONVERGENCE && st != RAFEAST_SUBSPACE_TOO_SMALL &&
         st != RAFEAST_EMPTY_WINDOW && st != RAFEAST_BREAKDOWN)
       return member_fail(g, st);
