@@ -9,7 +9,7 @@ power iterations with CholQR2, Rayleigh-Ritz truncation) and Phase 2 (FEAST
 iterations with COCG shifted solves) until every in-window Ritz pair has
 residual <= 1e-10; results stay in device memory.  RA-FEAST runs with
 N_c = 4, q = 2, p = 20, complex-FP32 COCG (tolerance 1e-6) with FP64
-refinement; plain FEAST (N_c = 16, random start) runs beside it on the same
+reliable updates; plain FEAST (N_c = 16, random start) runs beside it on the same
 matrix and kernels.
 
 Prints one JSON line.  --gpus N with N > 1 is refused (single-GPU build).
@@ -479,7 +479,7 @@ def main():
         "config": {
             "workload": "knn-laplacian n=8000 (2D points, k=10, Gaussian weights, +1e-3 I), "
                         "50 smallest eigenvalues, m0=64; RA-FEAST N_c=4 q=2 p=20 vs plain "
-                        "FEAST N_c=16; COCG tol 1e-6 (complex FP32 + FP64 refinement)",
+                        "FEAST N_c=16; COCG tol 1e-6 (complex FP32 with FP64 reliable updates)",
             "n": n, "nnz": nnz, "m0": m0, "M": win["count"], "nc": w["nc_ra"], "q": w["q"],
             "p": w["p"], "tol_eig": w["tol_eig"], "tol_solve": w["tol_solve"],
         },

@@ -58,7 +58,7 @@ typedef enum rafeast_status {
 
 /* rafeast_params.precision: arithmetic of the shifted solves. */
 enum { RAFEAST_FP64 = 0,          /* complex FP64 COCG */
-       RAFEAST_FP32_REFINED = 1 };/* complex FP32 COCG with FP64 true-residual refinement */
+       RAFEAST_FP32_REFINED = 1 };/* complex FP32 COCG with FP64 true-residual updates */
 
 /* rafeast_params.ws_op: Phase-1 operator (eq. B-def and Assumption 1.2). */
 enum { RAFEAST_WS_AUTO = 0,       /* FLIP for a bottom window, LITERAL for a top window,
@@ -76,8 +76,9 @@ enum { RAFEAST_RHS_RESIDUAL = 0,  /* solve against Ritz residuals r_i and use
 
 /* rafeast_params.engine: COCG engine.  AUTO takes RESIDENT when n fits on
  * chip (n <= 8192 at FP32_REFINED, n <= 4096 at FP64, row lengths permitting)
- * and STREAM otherwise.  Both run the same method (COCG with FP64
- * true-residual refinement) to the same stopping test. */
+ * and STREAM otherwise.  Both run the same method (COCG with reliable updates:
+ * FP64 true-residual checks that keep the search direction) to the same
+ * stopping test. */
 enum { RAFEAST_ENGINE_AUTO = 0,
        RAFEAST_ENGINE_RESIDENT = 1,  /* one workgroup per system, vectors in LDS/registers */
        RAFEAST_ENGINE_STREAM = 2 };  /* all systems in lock step, vectors in HBM, rows
@@ -115,7 +116,7 @@ typedef struct rafeast_params {
                               ||A q - theta q|| / (max(|lmin|,|lmax|) ||q||) <= tol_eig */
   double tol_solve;        /* relative residual of each COCG solve */
   int32_t max_iter;        /* FEAST iterations (filter applications) */
-  int32_t max_cocg;        /* COCG iterations per system, refinement restarts included */
+  int32_t max_cocg;        /* COCG iterations per system, over all residual checks */
   int32_t precision;       /* RAFEAST_FP64 | RAFEAST_FP32_REFINED */
   int32_t ws_op;           /* RAFEAST_WS_* */
   int32_t rhs_form;        /* RAFEAST_RHS_* */
@@ -144,7 +145,8 @@ typedef struct rafeast_result {
   int32_t iters;           /* out: FEAST filter applications performed */
   int64_t cocg_iters;      /* out: COCG iterations summed over all systems */
   int32_t cocg_max;        /* out: largest COCG iteration count of one system */
-  int32_t refinements;     /* out: FP64 residual restarts summed over all systems */
+  int32_t refinements;     /* out: FP64 true-residual checks that continued the
+                              iteration, summed over all systems */
   double max_resid;        /* out: max scaled residual over the M pairs */
   double t_ms[RAFEAST_NPHASE]; /* out: device time per phase (HIP events) */
 } rafeast_result;

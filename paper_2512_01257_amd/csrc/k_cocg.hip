@@ -17,16 +17,22 @@
 // matrices (the batching form); a workgroup reloads the graph's descriptor
 // only when its next item belongs to another graph.
 //
-// Per system: b is scaled to unit norm.  Mixed-precision iterative
-// refinement: each cycle runs COCG in T (float or double; per-thread sums in
-// T, cross-thread sums in FP64) on the current residual until its recurrence
-// residual is <= max(tol, eps_inner * its starting norm) (eps_inner 1e-6 in
-// FP32), accumulating the correction in T; the correction is then added to
-// the FP64 solution x_hi (a per-workgroup global buffer, indexed by slot),
-// and the true residual s = b - (zI - A) x_hi is formed in FP64 with FP64
-// values of A.  If ||s|| > tol the next cycle starts from r = p = s, at most
-// max_refine times.  A breakdown (p^T w = 0 or a non-finite step) also ends
-// the cycle.
+// Per system: b is scaled to unit norm.  COCG runs in T (float or double;
+// per-thread sums in T, cross-thread sums in FP64) with reliable updates in
+// FP64: whenever the recursive residual has dropped by the factor delta
+// (0.1 in FP32, 1e-4 in FP64) since the last check, or below tol, the
+// correction accumulated in T is added to the FP64 solution x_hi (a
+// per-workgroup global buffer, indexed by slot) and the true residual
+// s = b - (zI - A) x_hi is formed in FP64 with FP64 values of A.  If
+// ||s|| > tol the recurrence continues from r = s with the same search
+// direction (beta = s^T s / rho_prev), which removes the drift between the
+// recursive and the true residual that FP32 storage causes without throwing
+// the Krylov recurrence away.  It restarts from p = s only after a breakdown
+// (p^T w = 0 or a non-finite step), when ||s|| has not at least halved since
+// the previous check, or after a stall: no drop by delta within 4x the
+// previous check interval (and 2x the first interval after the last start,
+// at least 256 iterations) sends the system to an early check.  At most
+// max_refine checks per system.
 #include "device.h"
 #include "kernels.h"
 
@@ -293,16 +299,20 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     double rho_re = rho_s[0], rho_im = 0.0;
     int it = 0, nref = 0, nbd = 0;
     double last_res = 1.0;
-    // x_hi is first written at the end of the first cycle (kept out of L2
-    // while the cycle iterates)
+    // x_hi is first written at the first check (kept out of L2 before)
     bool first_cycle = true;
-    // A cycle stops at max(tol, eps_inner * ||r at cycle start||): the
-    // relative reduction one cycle in T can deliver reliably.
-    const double eps_inner = sizeof(T) == 4 ? 1e-6 : 1e-14;
-    double cyc_tol2 = fmax(tol2, eps_inner * eps_inner * rho_s[0]);
+    // next check when the recursive residual is below
+    // max(tol, delta * ||s at the last check||)
+    const double delta = sizeof(T) == 4 ? 0.1 : 1e-4;
+    double cyc_tol2 = fmax(tol2, delta * delta * rho_s[0]);
+    // check bookkeeping: iteration of the last check and of the last start,
+    // length of the previous interval and of the longest first interval
+    // after a start, ||s||^2 at the last check
+    int lastit = 0, rstart = 0, span = 0, span0 = 0;
+    double sprev = rho_s[0];
 
     for (;;) {
-      bool verify = false;
+      bool verify = false, restart = false;
       // Slot addresses are cheap to recompute; hiding the lane index from
       // loop-invariant code motion keeps them out of the register budget.
       int ln = lane;
@@ -381,6 +391,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       if (!(isfinite(alpha.re) && isfinite(alpha.im)) || (mu[0] == 0.0 && mu[1] == 0.0)) {
         ++nbd;
         verify = true;
+        restart = true;
       } else {
         // ---- x += alpha p, r -= alpha w, rho' = r^T r, ||r||^2 ----
         T s3_t[3] = {T(0), T(0), T(0)};
@@ -405,7 +416,9 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
         double s3[3];
         block_sum<3>(s3_t, s3, red, 1);
         ++it;
-        if (s3[2] <= cyc_tol2 || it >= maxit) {
+        const bool stall =
+            span > 0 && it - lastit > max(max(4 * span, 2 * span0), 256);
+        if (s3[2] <= cyc_tol2 || it >= maxit || stall) {
           verify = true;
         } else {
           const zd beta = zdiv(zd{s3[0], s3[1]}, zd{rho_re, rho_im});
@@ -470,16 +483,35 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       last_res = sqrt(s3[2]);
       if (s3[2] <= tol2 || nref >= max_refine || it >= maxit || nbd > 3) break;
       ++nref;
+      // reliable update (keep p, beta = s^T s / rho_prev) or restart (p = s)
+      zd beta{0.0, 0.0};
+      if (!restart && s3[2] <= 0.25 * sprev) {
+        beta = zdiv(zd{s3[0], s3[1]}, zd{rho_re, rho_im});
+        if (!(isfinite(beta.re) && isfinite(beta.im))) beta = zd{0.0, 0.0};
+      }
+      const bool keep = beta.re != 0.0 || beta.im != 0.0;
+      span = it - lastit;
+      if (lastit == rstart) span0 = max(span0, span);
+      lastit = it;
+      if (!keep) rstart = it;
+      sprev = s3[2];
       rho_re = s3[0];
       rho_im = s3[1];
-      cyc_tol2 = fmax(tol2, eps_inner * eps_inner * s3[2]);
+      cyc_tol2 = fmax(tol2, delta * delta * s3[2]);
+      const T br = T(beta.re), bi = T(beta.im);
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         const int slice = slc[t];
         if (slice >= 0) {
           const int s = slice * 64 + ln;
-          P[s] = w[t];
-          R[s] = w[t];
+          const cpx<T> rv = w[t];
+          cpx<T> pv = rv;
+          if (keep) {
+            const cpx<T> pr = P[s];
+            pv = cpx<T>{rv.re + br * pr.re - bi * pr.im, rv.im + br * pr.im + bi * pr.re};
+          }
+          P[s] = pv;
+          R[s] = rv;
         }
       }
       __syncthreads();

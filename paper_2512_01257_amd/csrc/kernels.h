@@ -133,7 +133,7 @@ struct ResGraph {
   const double* zs = nullptr;           // shifts (re, im)
   int* iters = nullptr;                 // [nz kcols] iterations per system
   double* resid = nullptr;              // nullable [nz kcols] final relative true residual
-  int* stats = nullptr;                 // [2]: refinements, breakdowns (accumulated)
+  int* stats = nullptr;                 // [2]: continued checks, breakdowns (accumulated)
 };
 
 struct CocgLaunch {
@@ -141,7 +141,7 @@ struct CocgLaunch {
   const int* items = nullptr;   // [3*nitems] (graph g, shift j, column i), longest first
   double tol = 1e-6;
   int maxit = 20000;
-  int max_refine = 4;
+  int max_refine = 64;          // FP64 residual checks per system
   int* counter = nullptr;       // zeroed work counter
   void* xhi = nullptr;          // FP64 complex solution scratch, xhi_slots entries
   size_t xhi_slots = 0;         // >= blocks * (max_n rounded up to 64)

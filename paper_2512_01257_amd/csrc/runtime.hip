@@ -663,7 +663,7 @@ rafeast_status run_cocg(rafeast_plan_s* P, int nitems, const int* d_items, const
   L.items = d_items;
   L.tol = tol;
   L.maxit = P->prm.max_cocg;
-  L.max_refine = 4;
+  L.max_refine = 64;
   L.counter = P->d_counter;
   L.xhi = P->d_xhi;
   L.xhi_slots = P->xhi_slots;
@@ -1632,7 +1632,7 @@ rafeast_status batch_resident_solves(rafeast_batch_s* B, const std::vector<char>
     L.items = B->d_items;
     L.tol = P0->prm.tol_solve;
     L.maxit = P0->prm.max_cocg;
-    L.max_refine = 4;
+    L.max_refine = 64;
     L.counter = B->d_counter;
     L.xhi = B->d_xhi;
     L.xhi_slots = B->xhi_slots;
