@@ -46,7 +46,9 @@ constexpr int kResWaves = kResThreads / 64;
 
 // Workgroup sum of NV values given per-thread partials of type A (float or
 // double): DPP wave sums (no LDS), one LDS slot per wave, a barrier, then
-// every thread adds the kResWaves wave sums in the same order in FP64.
+// wave 0 adds the kResWaves wave sums in FP64 (fixed order) and publishes the
+// totals in LDS for a second barrier.  One wave finishing the sum, instead of
+// every wave repeating it, frees the SIMDs for the other waves' work.
 template <int NV, typename A>
 __device__ __forceinline__ void block_sum(const A (&part)[NV], double (&v)[NV],
                                           double (*red)[kResWaves][4], int set) {
@@ -64,14 +66,26 @@ __device__ __forceinline__ void block_sum(const A (&part)[NV], double (&v)[NV],
     for (int q = 0; q < NV; ++q) red[set][wv][q] = ws[q];
   }
   __syncthreads();
-  // lane w < kResWaves reads wave w's sum; a DPP sum over the wave (the
-  // same fixed order in every wave) gives every thread the same total
+  // wave 0: lane w < kResWaves reads wave w's sum, a DPP sum over the wave;
+  // the totals overwrite wave 0's slots (read before they are written).
+  // Every caller passes another barrier after reading the totals and before
+  // the next call on the same set writes its partials.
   const int ln = threadIdx.x & 63;
+  if (wv == 0) {
+    double t[NV];
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const double x = ln < kResWaves ? red[set][ln][q] : 0.0;
-    v[q] = wave_sum_f64(x);
+    for (int q = 0; q < NV; ++q) {
+      const double x = ln < kResWaves ? red[set][ln][q] : 0.0;
+      t[q] = wave_sum_f64(x);
+    }
+    if (ln == 0) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) red[set][0][q] = t[q];
+    }
   }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = red[set][0][q];
 }
 
 struct __align__(16) EPair {
@@ -387,7 +401,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       }
       double mu[2];
       block_sum<2>(mu_t, mu, red, 0);
-      const zd alpha = zdiv(zd{rho_re, rho_im}, zd{mu[0], mu[1]});
+      const zd alpha = zdiv_fast(zd{rho_re, rho_im}, zd{mu[0], mu[1]});
       if (!(isfinite(alpha.re) && isfinite(alpha.im)) || (mu[0] == 0.0 && mu[1] == 0.0)) {
         ++nbd;
         verify = true;
@@ -421,7 +435,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
         if (s3[2] <= cyc_tol2 || it >= maxit || stall) {
           verify = true;
         } else {
-          const zd beta = zdiv(zd{s3[0], s3[1]}, zd{rho_re, rho_im});
+          const zd beta = zdiv_fast(zd{s3[0], s3[1]}, zd{rho_re, rho_im});
           rho_re = s3[0];
           rho_im = s3[1];
           const T br = T(beta.re), bi = T(beta.im);
@@ -486,7 +500,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       // reliable update (keep p, beta = s^T s / rho_prev) or restart (p = s)
       zd beta{0.0, 0.0};
       if (!restart && s3[2] <= 0.25 * sprev) {
-        beta = zdiv(zd{s3[0], s3[1]}, zd{rho_re, rho_im});
+        beta = zdiv_fast(zd{s3[0], s3[1]}, zd{rho_re, rho_im});
         if (!(isfinite(beta.re) && isfinite(beta.im))) beta = zd{0.0, 0.0};
       }
       const bool keep = beta.re != 0.0 || beta.im != 0.0;

@@ -17,10 +17,17 @@ __device__ __forceinline__ int packed_index(int k, int i, int j) {  // i <= j
 }
 
 // ============================================================================
-// CholQR factor.  LDS: dsc[k] (column scales) | U (packed upper, k(k+1)/2).
-// The inverse X = U^{-1} is built column by column directly in M (global,
-// visible across the workgroup after each barrier), then rows scaled by dsc.
+// CholQR factor.  LDS: dsc[k] (column scales) | U (packed upper, k(k+1)/2)
+// [| X = U^{-1} (packed upper) when kXInLds].  Right-looking Cholesky with
+// one barrier per column: step j reads the unscaled pivot d_j = U[j][j]
+// (every thread, so the failure test is uniform), updates the trailing block
+// by U[i][l] -= U[j][i] U[j][l] / d_j from the unscaled row j, and scales
+// row j-1 (which no thread of step j reads) by 1/sqrt(d_{j-1}).  The inverse
+// is built column by column, X[j][j] = 1/U[j][j] and
+// X[i][j] = -(sum_{t=i}^{j-1} X[i][t] U[t][j]) / U[j][j], in LDS when it fits
+// (else directly in M, global), then its rows are scaled by dsc.
 // ============================================================================
+template <bool kXInLds>
 __global__ __launch_bounds__(kSmallThreads) void k_chol_inv(int k, double shift_unit,
                                                             const double* __restrict__ G,
                                                             int ldg, double* __restrict__ M,
@@ -28,6 +35,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_inv(int k, double shift_
   extern __shared__ double sm[];
   double* dsc = sm;
   double* U = sm + k;
+  double* X = U + (size_t)k * (k + 1) / 2;  // used when kXInLds
   __shared__ int s_fail;
   const int tid = threadIdx.x;
   if (tid == 0) s_fail = 0;
@@ -56,34 +64,41 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_inv(int k, double shift_
         U[packed_index(k, i, j)] = g;
       }
       __syncthreads();
+      bool ok = true;
       for (int j = 0; j < k; ++j) {
-        if (tid == 0) {
-          const double d = U[packed_index(k, j, j)];
-          if (!(d > 0.0) || !isfinite(d))
-            s_fail = 1;
-          else
-            U[packed_index(k, j, j)] = sqrt(d);
+        const double d = U[packed_index(k, j, j)];
+        if (!(d > 0.0) || !isfinite(d)) {
+          ok = false;
+          break;
+        }
+        if (j > 0) {  // finish row j - 1
+          const int r = j - 1;
+          const double piv = sqrt(U[packed_index(k, r, r)]);
+          for (int l = r + 1 + tid; l < k; l += kSmallThreads) U[packed_index(k, r, l)] /= piv;
+        }
+        const double inv_d = 1.0 / d;
+        // trailing block rows ii, columns ll >= ii, on a 32 x 32 thread grid
+        const int rj = packed_index(k, j, j);  // U[j][c] = U[rj + c - j]
+        for (int ii = j + 1 + (tid >> 5); ii < k; ii += kSmallThreads / 32) {
+          const double a = U[rj + ii - j] * inv_d;
+          const int ri = packed_index(k, ii, ii);  // U[ii][c] = U[ri + c - ii]
+          for (int ll = ii + (tid & 31); ll < k; ll += 32) U[ri + ll - ii] -= a * U[rj + ll - j];
         }
         __syncthreads();
-        if (s_fail) break;
-        const double piv = U[packed_index(k, j, j)];
-        for (int l = j + 1 + tid; l < k; l += kSmallThreads) U[packed_index(k, j, l)] /= piv;
-        __syncthreads();
-        const int m = k - 1 - j;
-        for (int e = tid; e < m * m; e += kSmallThreads) {
-          const int ii = j + 1 + e / m, ll = j + 1 + e % m;
-          if (ll < ii) continue;
-          U[packed_index(k, ii, ll)] -= U[packed_index(k, j, ii)] * U[packed_index(k, j, ll)];
+        if (j > 0 && tid == 0) {
+          const int r = j - 1;
+          U[packed_index(k, r, r)] = sqrt(U[packed_index(k, r, r)]);
         }
-        __syncthreads();
       }
-      if (!s_fail) {
+      if (ok) {
+        // last row: only its diagonal; the previous diagonal write is
+        // ordered by this barrier
+        if (tid == 0) U[packed_index(k, k - 1, k - 1)] = sqrt(U[packed_index(k, k - 1, k - 1)]);
+        __syncthreads();
         status = attempt;
         break;
       }
       status = 2;
-      __syncthreads();
-      if (tid == 0) s_fail = 0;
       __syncthreads();
     }
   }
@@ -95,33 +110,55 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_inv(int k, double shift_
     if (tid == 0) *flag = 2;
     return;
   }
-  // X = U^{-1}, column j: X[j][j] = 1/U[j][j];
-  // X[i][j] = -(sum_{t=i}^{j-1} X[i][t] U[t][j]) / U[j][j] for i < j.
   // Four lanes of one wave share row i and split the sum.
-  for (int e = tid; e < k * k; e += kSmallThreads) {
-    const int i = e / k, j = e % k;
-    if (j < i) M[(size_t)i * ldm + j] = 0.0;
-  }
-  for (int j = 0; j < k; ++j) {
-    const double ujj = U[packed_index(k, j, j)];
-    const int i = tid >> 2, qd = tid & 3;
-    double part = 0.0;
-    if (i < j) {
-      for (int t = i + qd; t < j; t += 4)
-        part += M[(size_t)i * ldm + t] * U[packed_index(k, t, j)];
+  const int i = tid >> 2, qd = tid & 3;
+  if constexpr (kXInLds) {
+    for (int j = 0; j < k; ++j) {
+      const double ujj = U[packed_index(k, j, j)];
+      double part = 0.0;
+      if (i < j) {
+        for (int t = i + qd; t < j; t += 4)
+          part += X[packed_index(k, i, t)] * U[packed_index(k, t, j)];
+      }
+      part += __shfl_xor(part, 1, 64);
+      part += __shfl_xor(part, 2, 64);
+      if (i < j && qd == 0) X[packed_index(k, i, j)] = -part / ujj;
+      if (tid == kSmallThreads - 1) X[packed_index(k, j, j)] = 1.0 / ujj;
+      __syncthreads();
     }
-    part += __shfl_xor(part, 1, 64);
-    part += __shfl_xor(part, 2, 64);
-    if (i < j && qd == 0) M[(size_t)i * ldm + j] = -part / ujj;
-    if (tid == kSmallThreads - 1) M[(size_t)j * ldm + j] = 1.0 / ujj;
-    __syncthreads();
-  }
-  for (int e = tid; e < k * k; e += kSmallThreads) {
-    const int i = e / k, j = e % k;
-    if (j >= i) M[(size_t)i * ldm + j] *= dsc[i];
+    for (int e = tid; e < k * k; e += kSmallThreads) {
+      const int r = e / k, c = e % k;
+      M[(size_t)r * ldm + c] = c >= r ? X[packed_index(k, r, c)] * dsc[r] : 0.0;
+    }
+  } else {
+    for (int e = tid; e < k * k; e += kSmallThreads) {
+      const int r = e / k, c = e % k;
+      if (c < r) M[(size_t)r * ldm + c] = 0.0;
+    }
+    for (int j = 0; j < k; ++j) {
+      const double ujj = U[packed_index(k, j, j)];
+      double part = 0.0;
+      if (i < j) {
+        for (int t = i + qd; t < j; t += 4)
+          part += M[(size_t)i * ldm + t] * U[packed_index(k, t, j)];
+      }
+      part += __shfl_xor(part, 1, 64);
+      part += __shfl_xor(part, 2, 64);
+      if (i < j && qd == 0) M[(size_t)i * ldm + j] = -part / ujj;
+      if (tid == kSmallThreads - 1) M[(size_t)j * ldm + j] = 1.0 / ujj;
+      __syncthreads();
+    }
+    for (int e = tid; e < k * k; e += kSmallThreads) {
+      const int r = e / k, c = e % k;
+      if (c >= r) M[(size_t)r * ldm + c] *= dsc[r];
+    }
   }
   if (tid == 0) *flag = status;
 }
+
+// Dynamic LDS budget of the one-workgroup kernels (the static arrays of
+// k_jacobi take under 8 KB of the 160 KB).
+constexpr size_t kSmallLdsMax = 160 * 1024 - 8192;
 
 hipError_t launch_chol_inv(hipStream_t st, int k, int64_t nrows, const double* G, int ldg,
                            double* M, int ldm, int* flag) {
@@ -130,12 +167,19 @@ hipError_t launch_chol_inv(hipStream_t st, int k, int64_t nrows, const double* G
   // s = 11 (m n + n (n+1)) u ||X||_2^2 with ||X||_2^2 <= trace(G) = k after scaling.
   const double u = 0x1.0p-53;
   const double shift = 11.0 * ((double)nrows * k + (double)k * (k + 1)) * u * (double)k;
-  const size_t lds = sizeof(double) * ((size_t)k + (size_t)k * (k + 1) / 2);
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol_inv,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const size_t base = sizeof(double) * ((size_t)k + (size_t)k * (k + 1) / 2);
+  const size_t with_x = base + sizeof(double) * (size_t)k * (k + 1) / 2;
+  const bool x_lds = with_x <= kSmallLdsMax;
+  const size_t lds = x_lds ? with_x : base;
+  const void* fn = x_lds ? (const void*)k_chol_inv<true> : (const void*)k_chol_inv<false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kSmallThreads), lds, st, k, shift, G, ldg, M, ldm,
-                     flag);
+  if (x_lds)
+    hipLaunchKernelGGL(k_chol_inv<true>, dim3(1), dim3(kSmallThreads), lds, st, k, shift, G, ldg,
+                       M, ldm, flag);
+  else
+    hipLaunchKernelGGL(k_chol_inv<false>, dim3(1), dim3(kSmallThreads), lds, st, k, shift, G, ldg,
+                       M, ldm, flag);
   return hipGetLastError();
 }
 
@@ -145,9 +189,9 @@ hipError_t launch_chol_inv(hipStream_t st, int k, int64_t nrows, const double* G
 // J_qp = -s) zeroing H_pq follows Golub & Van Loan, Alg. 8.5.1.  H <- J^T H J
 // is applied per (row pair, column pair) 2x2 block, each block by one thread,
 // and V <- V J per (row, pair).  H lives in LDS for k <= 128, else in global
-// workspace; V is in global workspace.
+// workspace; V lives in LDS too when both fit, else in global workspace.
 // ============================================================================
-template <bool kHInLds>
+template <bool kHInLds, bool kVInLds>
 __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* __restrict__ Hin,
                                                           int ldh, double* __restrict__ theta,
                                                           double* __restrict__ S, int lds,
@@ -157,7 +201,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
   __shared__ double rc[kSmallMaxK / 2 + 1], rs[kSmallMaxK / 2 + 1], dg[kSmallMaxK];
   __shared__ double red[2][kSmallThreads / 64];
   double* H = kHInLds ? sh_h : work;
-  double* V = work + (size_t)k * k;
+  double* V = kVInLds ? sh_h + (size_t)k * k : work + (size_t)k * k;
   const int tid = threadIdx.x;
   for (int e = tid; e < k * k; e += kSmallThreads) {
     const int i = e / k, j = e % k;
@@ -168,14 +212,16 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
   const int kk = k + (k & 1);
   const int np = kk / 2;
   const int players = kk - 1;  // the last player stays fixed
+  const float inv_np = 1.0f / (float)np;
   for (int sweep = 0; sweep < 40; ++sweep) {
     // convergence test on the off-diagonal mass
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < k * k; e += kSmallThreads) {
-      const double h = H[e];
-      tot += h * h;
-      if (e / k != e % k) off += h * h;
-    }
+    for (int i = tid >> 5; i < k; i += kSmallThreads / 32)
+      for (int j = tid & 31; j < k; j += 32) {
+        const double h = H[i * k + j];
+        tot += h * h;
+        if (i != j) off += h * h;
+      }
     off = wave_sum(off);
     tot = wave_sum(tot);
     if ((tid & 63) == 0) {
@@ -222,7 +268,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
       }
       __syncthreads();
       for (int b = tid; b < np * np; b += kSmallThreads) {
-        const int t1 = b / np, t2 = b % np;
+        // b / np in float: exact for b, e < 2^15 and np <= 96
+        const int t1 = (int)(((float)b + 0.5f) * inv_np), t2 = b - t1 * np;
         const int p1 = rp[t1], q1 = rq[t1], p2 = rp[t2], q2 = rq[t2];
         const double c1 = rc[t1], s1 = rs[t1], c2 = rc[t2], s2 = rs[t2];
         const bool v_p1 = p1 < k, v_q1 = q1 < k, v_p2 = p2 < k, v_q2 = q2 < k;
@@ -242,7 +289,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
         if (v_q1 && v_q2) H[q1 * k + q2] = f11;
       }
       for (int e = tid; e < k * np; e += kSmallThreads) {
-        const int row = e / np, t = e % np;
+        const int row = (int)(((float)e + 0.5f) * inv_np), t = e - row * np;
         const int p = rp[t], q = rq[t];
         if (p < k && q < k) {
           const double c = rc[t], s = rs[t];
@@ -273,16 +320,22 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
 hipError_t launch_jacobi(hipStream_t st, int k, const double* H, int ldh, double* theta,
                          double* S, int lds, double* work) {
   if (k < 1 || k > kSmallMaxK) return hipErrorInvalidValue;
-  if (k <= 128) {
-    const size_t bytes = sizeof(double) * (size_t)k * k;
-    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const size_t hb = sizeof(double) * (size_t)k * k;
+  if (2 * hb <= kSmallLdsMax) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<true, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * hb));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(kSmallThreads), bytes, st, k, H, ldh, theta,
-                       S, lds, work);
+    hipLaunchKernelGGL((k_jacobi<true, true>), dim3(1), dim3(kSmallThreads), 2 * hb, st, k, H,
+                       ldh, theta, S, lds, work);
+  } else if (k <= 128) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<true, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)hb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_jacobi<true, false>), dim3(1), dim3(kSmallThreads), hb, st, k, H, ldh,
+                       theta, S, lds, work);
   } else {
-    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(kSmallThreads), 0, st, k, H, ldh, theta, S,
-                       lds, work);
+    hipLaunchKernelGGL((k_jacobi<false, false>), dim3(1), dim3(kSmallThreads), 0, st, k, H, ldh,
+                       theta, S, lds, work);
   }
   return hipGetLastError();
 }

@@ -550,6 +550,9 @@ rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, 
     HIPCHK(P, launch_chol_inv(P->st, k, n, P->d_G, k, P->d_M, k, P->d_flag));
     int flag = 0;
     HIPCHK(P, hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, P->st));
+    if (mtot)
+      HIPCHK(P, hipMemcpyAsync(hm.data(), P->d_M, hm.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, P->st));
     HIPCHK(P, hipStreamSynchronize(P->st));
     if (flag == 2) {
       if (info) *info = 2;
@@ -557,15 +560,14 @@ rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, 
     }
     if (flag == 1 && pass == 0) passes = 3;
     worst = std::max(worst, flag);
-    if (mtot) {  // mtot <- mtot * M of this pass
-      HIPCHK(P, hipMemcpyAsync(hm.data(), P->d_M, hm.size() * sizeof(double),
-                               hipMemcpyDeviceToHost, P->st));
-      HIPCHK(P, hipStreamSynchronize(P->st));
+    if (mtot) {  // mtot <- mtot * M of this pass (sums over t in increasing order)
+      std::fill(prod.begin(), prod.end(), 0.0);
       for (int r = 0; r < k; ++r)
-        for (int c = 0; c < k; ++c) {
-          double a = 0.0;
-          for (int t = 0; t < k; ++t) a += (*mtot)[(size_t)r * k + t] * hm[(size_t)t * k + c];
-          prod[(size_t)r * k + c] = a;
+        for (int t = 0; t < k; ++t) {
+          const double a = (*mtot)[(size_t)r * k + t];
+          const double* hr = &hm[(size_t)t * k];
+          double* pr = &prod[(size_t)r * k];
+          for (int c = 0; c < k; ++c) pr[c] += a * hr[c];
         }
       mtot->swap(prod);
     }
@@ -610,16 +612,19 @@ rafeast_status rayleigh_ritz(rafeast_plan_s* P, std::vector<double>& theta,
   // ||rho(A) Q_prev y_i|| / ||Q_prev y_i||; 1 before the first filter step
   mu.assign(m0, 1.0);
   if (P->have_filter) {
+    // Y = Mt S row by row (sums over t in increasing order), then column norms
     const std::vector<double>& Mt = P->mtot;
-    for (int i = 0; i < m0; ++i) {
-      double ss = 0.0;
-      for (int r = 0; r < m0; ++r) {
-        double y = 0.0;
-        for (int t = 0; t < m0; ++t) y += Mt[(size_t)r * m0 + t] * S[(size_t)t * m0 + i];
-        ss += y * y;
+    std::vector<double> ss(m0, 0.0), yr(m0);
+    for (int r = 0; r < m0; ++r) {
+      std::fill(yr.begin(), yr.end(), 0.0);
+      for (int t = 0; t < m0; ++t) {
+        const double a = Mt[(size_t)r * m0 + t];
+        const double* sr = &S[(size_t)t * m0];
+        for (int i = 0; i < m0; ++i) yr[i] += a * sr[i];
       }
-      mu[i] = ss > 0.0 ? 1.0 / std::sqrt(ss) : 0.0;
+      for (int i = 0; i < m0; ++i) ss[i] += yr[i] * yr[i];
     }
+    for (int i = 0; i < m0; ++i) mu[i] = ss[i] > 0.0 ? 1.0 / std::sqrt(ss[i]) : 0.0;
   }
   return RAFEAST_OK;
 }
