@@ -88,6 +88,45 @@ __device__ __forceinline__ void block_sum(const A (&part)[NV], double (&v)[NV],
   for (int q = 0; q < NV; ++q) v[q] = red[set][0][q];
 }
 
+// As block_sum, but wave 0 also maps the NV totals to NO published values
+// (the COCG step lengths), so no other wave repeats that arithmetic.
+template <int NV, int NO, typename A, typename F>
+__device__ __forceinline__ void block_sum_fin(const A (&part)[NV], double (&o)[NO],
+                                              double (*red)[kResWaves][4], int set, F fin) {
+  const int wv = threadIdx.x >> 6;
+  double ws[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if constexpr (sizeof(A) == 4)
+      ws[q] = (double)wave_sum_f32(part[q]);
+    else
+      ws[q] = wave_sum_f64(part[q]);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[set][wv][q] = ws[q];
+  }
+  __syncthreads();
+  const int ln = threadIdx.x & 63;
+  double* flat = &red[set][0][0];
+  if (wv == 0) {
+    double t[NV], r[NO];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double x = ln < kResWaves ? red[set][ln][q] : 0.0;
+      t[q] = wave_sum_f64(x);
+    }
+    fin(t, r);
+    if (ln == 0) {
+#pragma unroll
+      for (int q = 0; q < NO; ++q) flat[q] = r[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NO; ++q) o[q] = flat[q];
+}
+
 struct __align__(16) EPair {
   SellEntry32 a, b;
 };
@@ -399,9 +438,16 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
           mu_t[1] += pr.re * w[t].im + pr.im * w[t].re;
         }
       }
-      double mu[2];
-      block_sum<2>(mu_t, mu, red, 0);
-      const zd alpha = zdiv_fast(zd{rho_re, rho_im}, zd{mu[0], mu[1]});
+      double mo[4];
+      block_sum_fin<2, 4>(mu_t, mo, red, 0, [&](const double* t, double* r) {
+        const zd a = zdiv_fast(zd{rho_re, rho_im}, zd{t[0], t[1]});
+        r[0] = t[0];
+        r[1] = t[1];
+        r[2] = a.re;
+        r[3] = a.im;
+      });
+      const double mu[2] = {mo[0], mo[1]};
+      const zd alpha{mo[2], mo[3]};
       if (!(isfinite(alpha.re) && isfinite(alpha.im)) || (mu[0] == 0.0 && mu[1] == 0.0)) {
         ++nbd;
         verify = true;
@@ -427,15 +473,23 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
             s3_t[2] += rv.re * rv.re + rv.im * rv.im;
           }
         }
-        double s3[3];
-        block_sum<3>(s3_t, s3, red, 1);
+        double so[5];
+        block_sum_fin<3, 5>(s3_t, so, red, 1, [&](const double* t, double* r) {
+          const zd b = zdiv_fast(zd{t[0], t[1]}, zd{rho_re, rho_im});
+          r[0] = t[0];
+          r[1] = t[1];
+          r[2] = t[2];
+          r[3] = b.re;
+          r[4] = b.im;
+        });
+        const double s3[3] = {so[0], so[1], so[2]};
         ++it;
         const bool stall =
             span > 0 && it - lastit > max(max(4 * span, 2 * span0), 256);
         if (s3[2] <= cyc_tol2 || it >= maxit || stall) {
           verify = true;
         } else {
-          const zd beta = zdiv_fast(zd{s3[0], s3[1]}, zd{rho_re, rho_im});
+          const zd beta{so[3], so[4]};
           rho_re = s3[0];
           rho_im = s3[1];
           const T br = T(beta.re), bi = T(beta.im);
