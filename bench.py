@@ -354,6 +354,85 @@ def main_grid64(args):
     print(json.dumps(line), flush=True)
 
 
+def main_rgg(args):
+    """The paper's sweep (Section 5.1, Table 1, Figure 1): random geometric
+    graph Laplacians L = D - A (unit square, radius 1.5 sqrt(ln n / n)),
+    window [0.001, 5.0], m0 = 40 (ceil(1.5 count) where the window holds 40
+    or more eigenvalues).  Standard FEAST
+    (N_c = 8, random start, run to residual 1e-10) against RA-FEAST with
+    N_c in {2, 4, 8} and max_iter in {2, 4}; per configuration the mean
+    time of warm start + solve over the seeds, the speedup over standard
+    FEAST and the Max Error max_i |lambda_i - lambda_i^ref| against the
+    stored reference spectra (oracle shift-invert Lanczos).  value = speedup
+    of RA-FEAST (N_c = 2, max_iter = 4) at the largest n."""
+    import numpy as np
+    import torch
+
+    from paper_2512_01257_amd import native
+    from workloads import rgg_laplacian
+
+    with open(os.path.join(ROOT, "tests", "golden", "windows.json")) as f:
+        fix = json.load(f)["rgg"]
+    ns = [int(v) for v in args.rgg_n.split(",")]
+    configs = [("standard", 8, 20, "none")] + [
+        (f"ra_nc{nc}_it{it}", nc, it, "auto") for nc in (8, 4, 2) for it in (4, 2)]
+    table = {}
+    for n in ns:
+        rows = {name: dict(ms=[], err=[], ws_ms=[], found=0, feast_iters=[]) for name, *_ in configs}
+        trials = [w for w in fix if w["n"] == n][: args.seeds]
+        for w in trials:
+            csr = rgg_laplacian(n, w["seed"])
+            if csr.nnz != w["nnz"]:
+                raise RuntimeError("workload generator does not reproduce the stored fixture")
+            ref = np.array(w["eigenvalues"])
+            for name, nc, it, ws_op in configs:
+                plan = native.Plan(csr, w["lmin"], w["lmax"], w["m0"], nc=nc, q=2, p=-1,
+                                   tol_eig=1e-10, tol_solve=1e-6, max_iter=it, precision="fp32",
+                                   ws_op=ws_op, seed=w["seed"])
+                lam = torch.zeros(w["m0"], dtype=torch.float64, device="cuda")
+                res = torch.zeros(w["m0"], dtype=torch.float64, device="cuda")
+                if w is trials[0]:
+                    run_steps(plan, 1, lam, res, None, warmstart=True)  # first-use costs
+                secs, recs = run_steps(plan, 1, lam, res, None, warmstart=True)
+                ws, out = recs[0]
+                plan.close()
+                r = rows[name]
+                r["ms"].append(secs * 1e3)
+                r["ws_ms"].append(ws["t_ms"])
+                r["feast_iters"].append(out["iters"])
+                got = lam.cpu().numpy()[: out["M"]]
+                if out["M"] == len(ref):
+                    r["found"] += 1
+                    r["err"].append(float(np.abs(got - ref).max()) if len(ref) else 0.0)
+            log(f"rgg n={n} seed={w['seed']} count={w['count']} m0={w['m0']}: " + ", ".join(
+                f"{nm} {rows[nm]['ms'][-1]:.0f} ms" for nm, *_ in configs))
+        base = float(np.mean(rows["standard"]["ms"]))
+        table[str(n)] = {
+            name: dict(mean_ms=round(float(np.mean(r["ms"])), 2),
+                       speedup=round(base / float(np.mean(r["ms"])), 2),
+                       max_error_mean=float(np.mean(r["err"])) if r["err"] else None,
+                       max_error_max=float(np.max(r["err"])) if r["err"] else None,
+                       all_found=f"{r['found']}/{len(r['ms'])}",
+                       phase1_ms=round(float(np.mean(r["ws_ms"])), 3),
+                       feast_iters=round(float(np.mean(r["feast_iters"])), 2))
+            for name, r in rows.items()}
+    top = table[str(ns[-1])]["ra_nc2_it4"]
+    line = {
+        "metric": "speedup of RA-FEAST over standard FEAST (N_c=8), RGG Laplacians, window [0.001, 5]",
+        "value": top["speedup"],
+        "unit": "x (standard FEAST time / RA-FEAST N_c=2, max_iter=4 time)",
+        "n_gpus": 1, "steps": args.seeds, "warmup": 1,
+        "ms_per_step": top["mean_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": "random geometric graph Laplacians L = D - A, n points in the unit "
+                               "square, radius 1.5 sqrt(ln n / n); window [0.001, 5.0]; "
+                               "m0 = 40, or ceil(1.5 count) if count >= 40; COCG tol 1e-6",
+                   "n": ns, "seeds": args.seeds},
+        "table": table,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,13 +444,16 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (a dispatch of known traffic "
                          "for scaling memory counters)")
-    ap.add_argument("--workload", choices=("knn8000", "batch32", "learned", "grid64"),
+    ap.add_argument("--workload", choices=("knn8000", "batch32", "learned", "grid64", "rgg"),
                     default="knn8000",
                     help="knn8000: the headline workload (default); batch32: the batching "
                          "form over 32 graphs; learned: the learned preconditioner at n=1e6; "
-                         "grid64: the precision form on the 64^3 grid")
+                         "grid64: the precision form on the 64^3 grid; rgg: the paper's "
+                         "random-geometric-graph sweep")
     ap.add_argument("--max-iter", type=int, default=20, help="grid64: FEAST iteration cap")
     ap.add_argument("--max-cocg", type=int, default=20000, help="grid64: COCG iteration cap")
+    ap.add_argument("--rgg-n", default="2000,4000,8000,16000", help="rgg: graph sizes")
+    ap.add_argument("--seeds", type=int, default=3, help="rgg: seeds per size (at most 40)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -384,6 +466,8 @@ def main():
         return main_learned(args)
     if args.workload == "grid64":
         return main_grid64(args)
+    if args.workload == "rgg":
+        return main_rgg(args)
 
     import numpy as np
     import torch

@@ -2,7 +2,7 @@
 
 Calls only oracle/ (spectra) and workloads/ (the seeded matrices).  Run from
 the repository root:  python tests/golden/make_windows.py [entry ...]
-(entries: knn8000, batch32, learned; default all; others are kept).
+(entries: knn8000, batch32, learned, rgg; default all; others are kept).
 """
 
 import json
@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle.spectrum import bottom_eigvalsh  # noqa: E402
-from workloads import knn_laplacian  # noqa: E402
+from workloads import knn_laplacian, rgg_laplacian  # noqa: E402
 from workloads.graphs import batch_graph_specs  # noqa: E402
 
 
@@ -68,7 +68,33 @@ def learned():
                   method="power law fitted to the mid-gap lambda_100/101 at n=1e4, 2e4, 5e4"))
 
 
-ENTRIES = dict(knn8000=knn8000, batch32=batch32, learned=learned)
+def rgg():
+    # The paper's sweep (Section 5.1): random geometric graph Laplacians
+    # L = D - A, n points in the unit square, radius 1.5 sqrt(ln n / n),
+    # window [0.001, 5.0]; 40 seeds per n.  Stored per graph: the eigenvalues
+    # in the window, the ones just outside it, and the subspace size: the
+    # paper's m0 = 40, or ceil(1.5 count) where the window holds 40 or more
+    # eigenvalues (at n = 16000).
+    out = []
+    for n in (2000, 4000, 8000, 16000):
+        for seed in range(40):
+            A = rgg_laplacian(n, seed).to_scipy()
+            ev = bottom_eigvalsh(A, 64)
+            inside = ev[(ev >= 0.001) & (ev <= 5.0)]
+            c = int(len(inside))
+            if c >= 60:
+                raise RuntimeError(f"rgg n={n} seed={seed}: window holds {c} >= 60 eigenvalues")
+            out.append(dict(
+                recipe=f"rgg_laplacian({n}, seed={seed})", n=n, seed=seed, count=c,
+                lmin=0.001, lmax=5.0, m0=40 if c < 40 else -(-3 * c // 2),
+                below=[float(v) for v in ev[ev < 0.001]],
+                eigenvalues=[float(v) for v in inside],
+                above=[float(v) for v in ev[ev > 5.0][:2]], nnz=int(A.nnz)))
+            print(f"rgg n={n} seed={seed} count={c}", flush=True)
+    return out
+
+
+ENTRIES = dict(knn8000=knn8000, batch32=batch32, learned=learned, rgg=rgg)
 
 
 def main(names):
