@@ -6,9 +6,11 @@
 // Resident engine: one 1024-thread workgroup owns one system for its whole
 // solve.  The search direction p (gathered by the SpMM) and the residual r
 // live in LDS; w = (zI - A) p and the iterate x live in registers (RPT slots
-// per thread).  A is streamed from L2 in the row-sorted
-// SELL-64 layout of kernels.h (one 8- or 16-byte load per nonzero, coalesced
-// across the wave, the column already an LDS byte offset).  Both COCG
+// per thread).  A is streamed from L2 in the row-sorted SELL-64 layout of
+// kernels.h, coalesced across the wave, with the column already an LDS byte
+// offset: in FP32 a float value and a 16-bit offset per nonzero, eight per
+// lane in three 16-byte loads (the pace of this SpMV is set by the number of
+// load instructions, not by the bytes); in FP64 16 bytes per nonzero.  Both COCG
 // reductions per iteration are workgroup reductions: no grid-wide
 // synchronisation, and systems with different iteration counts retire
 // independently.  Workgroups take systems from an atomic work counter in the
@@ -127,20 +129,6 @@ __device__ __forceinline__ void block_sum_fin(const A (&part)[NV], double (&o)[N
   for (int q = 0; q < NO; ++q) o[q] = flat[q];
 }
 
-struct __align__(16) EPair {
-  SellEntry32 a, b;
-};
-
-template <typename T>
-struct EntryOf;
-template <>
-struct EntryOf<float> {
-  using type = SellEntry32;
-};
-template <>
-struct EntryOf<double> {
-  using type = SellEntry64;
-};
 
 template <typename T>
 __device__ __forceinline__ cpx<T> gather(const char* __restrict__ base, int byte_off) {
@@ -206,7 +194,7 @@ __device__ __forceinline__ const ResGraph* const_graph(const ResGraph* graphs, i
 template <typename T, int RPT, bool MULTI>
 __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     int a_nslices, const int* __restrict__ a_sbase, const int* __restrict__ a_perm,
-    const void* __restrict__ a_ent, const SellEntry64* __restrict__ a_ent64, int nitems,
+    const void* __restrict__ a_ent, const SellEntry64* __restrict__ a_ent64, int a_n32, int nitems,
     const int* __restrict__ items, const double* __restrict__ a_zs,
     const double* __restrict__ a_B, int a_ldb, int a_kcols, void* __restrict__ a_D, int a_ldd,
     double tol, int maxit, int max_refine, int* __restrict__ counter, int* __restrict__ a_iters,
@@ -232,10 +220,10 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
   // through the constant address space: scalar, invariant loads the compiler
   // may repeat instead of keeping every field live in registers.  With a
   // single graph, everything is read once, before the work loop.
-  int nslices = 0, zero_base = 0, ldb = 0, kcols = 0, ldd = 0;
+  int nslices = 0, zero_base = 0, ldb = 0, kcols = 0, ldd = 0, n32 = 0;
   const int* __restrict__ sbase = nullptr;
   const int* __restrict__ perm = nullptr;
-  const typename EntryOf<T>::type* __restrict__ ent = nullptr;
+  const void* __restrict__ ent = nullptr;
   const SellEntry64* __restrict__ ent64 = nullptr;
   const double* __restrict__ Bm = nullptr;
   cpx<T>* __restrict__ D = nullptr;
@@ -253,7 +241,8 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     ldd = G.ldd;
     sbase = G.sbase;
     perm = G.perm;
-    ent = reinterpret_cast<const typename EntryOf<T>::type*>(G.ent);
+    ent = G.ent;
+    n32 = G.n32;
     ent64 = G.ent64;
     Bm = G.B;
     D = reinterpret_cast<cpx<T>*>(G.D);
@@ -276,6 +265,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     g0.perm = a_perm;
     g0.ent = a_ent;
     g0.ent64 = a_ent64;
+    g0.n32 = a_n32;
     g0.wave_slices = a_wave_slices;
     g0.B = a_B;
     g0.D = a_D;
@@ -371,14 +361,6 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       int ln = lane;
       asm volatile("" : "+v"(ln));
       // ---- w = (zI - A) p,  mu = p^T w ----
-      // All RPT slots of a thread advance together in batches of KB entries:
-      // the entry loads of every slot in a batch are issued before any
-      // gather, so one L2 round trip serves RPT * KB nonzeros per lane.
-      // Slices are sorted by decreasing width, so slot 0 is the widest; a
-      // slot past its width reads the shared zero entries instead (a
-      // wave-uniform select, no branch), which keeps the batch straight-line.
-      constexpr int KB = (sizeof(T) == 4 && RPT <= 4) ? 4 : 2;
-      using E = typename EntryOf<T>::type;
       T acc_re[RPT], acc_im[RPT];
       int bse[RPT], wde[RPT];
 #pragma unroll
@@ -389,39 +371,109 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
         bse[t] = slice >= 0 ? sbase[slice] : zero_base;
         wde[t] = slice >= 0 ? (sbase[slice + 1] - bse[t]) >> 6 : 0;
       }
-      for (int kk = 0; kk < wde[0]; kk += KB) {
-        E e[RPT][KB];
+      if constexpr (sizeof(T) == 4) {
+        // FP32: the SpMV issues few wide loads (the load instruction count,
+        // not the bytes, sets its pace): per lane and slot, eight entries
+        // take three 16-byte loads (eight values, eight 16-bit LDS offsets)
+        // and a trailing four take two; slots go in pairs so that the loads
+        // of two slots are in flight together; slots past their width load
+        // nothing (wave-uniform bounds).
+        const float* __restrict__ vals = reinterpret_cast<const float*>(ent);
+        const unsigned short* __restrict__ offs =
+            reinterpret_cast<const unsigned short*>(vals + n32);
 #pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-          // uniform base pointer of this slot's batch (or of the zero entries);
-          // the per-lane part of the address is the fixed ln
-          const E* __restrict__ ep = kk < wde[t] ? ent + bse[t] + kk * 64 : ent + zero_base;
-          if constexpr (sizeof(E) == 8) {
-            // FP32 entries are pair-major: one 16-byte load per two entries
-#pragma unroll
-            for (int u = 0; u < KB; u += 2) {
-              const EPair pr = reinterpret_cast<const EPair*>(ep + u * 64)[ln];
-              e[t][u] = pr.a;
-              e[t][u + 1] = pr.b;
+        for (int t = 0; t < RPT; t += 2) {
+          const int ta = t, tb = t + 1 < RPT ? t + 1 : t;
+          const int na = wde[ta] >> 3, nb = tb != ta ? wde[tb] >> 3 : 0;
+          for (int o = 0; o < na; ++o) {
+            const int ba = bse[ta] + o * 512;
+            const float4 va0 = load_entry(reinterpret_cast<const float4*>(vals + ba), (unsigned)ln);
+            const float4 va1 =
+                load_entry(reinterpret_cast<const float4*>(vals + ba + 256), (unsigned)ln);
+            const uint4 oa = load_entry(reinterpret_cast<const uint4*>(offs + ba), (unsigned)ln);
+            float4 vb0 = make_float4(0.f, 0.f, 0.f, 0.f), vb1 = vb0;
+            uint4 ob = make_uint4(0u, 0u, 0u, 0u);
+            const bool hb = o < nb;
+            if (hb) {
+              const int bb = bse[tb] + o * 512;
+              vb0 = load_entry(reinterpret_cast<const float4*>(vals + bb), (unsigned)ln);
+              vb1 = load_entry(reinterpret_cast<const float4*>(vals + bb + 256), (unsigned)ln);
+              ob = load_entry(reinterpret_cast<const uint4*>(offs + bb), (unsigned)ln);
             }
-          } else {
+            const float va[8] = {va0.x, va0.y, va0.z, va0.w, va1.x, va1.y, va1.z, va1.w};
+            const unsigned oaw[4] = {oa.x, oa.y, oa.z, oa.w};
+            cpx<T> ga[8];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              ga[2 * u] = lds_gather<T>((int)(oaw[u] & 0xffffu));
+              ga[2 * u + 1] = lds_gather<T>((int)(oaw[u] >> 16));
+            }
+            if (hb) {
+              const float vbv[8] = {vb0.x, vb0.y, vb0.z, vb0.w, vb1.x, vb1.y, vb1.z, vb1.w};
+              const unsigned obw[4] = {ob.x, ob.y, ob.z, ob.w};
+              cpx<T> gb[8];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                gb[2 * u] = lds_gather<T>((int)(obw[u] & 0xffffu));
+                gb[2 * u + 1] = lds_gather<T>((int)(obw[u] >> 16));
+              }
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                acc_re[tb] += vbv[u] * gb[u].re;
+                acc_im[tb] += vbv[u] * gb[u].im;
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              acc_re[ta] += va[u] * ga[u].re;
+              acc_im[ta] += va[u] * ga[u].im;
+            }
+          }
+          // remaining octs of slot tb cannot exist (widths are non-increasing
+          // within a wave); trailing quads of both slots
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int tq = q == 0 ? ta : tb;
+            if ((q == 0 || tb != ta) && (wde[tq] & 4)) {
+              const int bq = bse[tq] + (wde[tq] >> 3) * 512;
+              const float4 v = load_entry(reinterpret_cast<const float4*>(vals + bq), (unsigned)ln);
+              const uint2 oq = load_entry(reinterpret_cast<const uint2*>(offs + bq), (unsigned)ln);
+              const cpx<T> g0 = lds_gather<T>((int)(oq.x & 0xffffu));
+              const cpx<T> g1 = lds_gather<T>((int)(oq.x >> 16));
+              const cpx<T> g2 = lds_gather<T>((int)(oq.y & 0xffffu));
+              const cpx<T> g3 = lds_gather<T>((int)(oq.y >> 16));
+              acc_re[tq] += v.x * g0.re + v.y * g1.re + v.z * g2.re + v.w * g3.re;
+              acc_im[tq] += v.x * g0.im + v.y * g1.im + v.z * g2.im + v.w * g3.im;
+            }
+          }
+        }
+      } else {
+        // FP64: 16-byte entries, two per lane and slot per batch, the loads
+        // of all slots issued before any gather
+        constexpr int KB = 2;
+        const SellEntry64* __restrict__ e64 = reinterpret_cast<const SellEntry64*>(ent);
+        for (int kk = 0; kk < wde[0]; kk += KB) {
+          SellEntry64 e[RPT][KB];
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) {
+            const SellEntry64* __restrict__ ep =
+                kk < wde[t] ? e64 + bse[t] + kk * 64 : e64 + zero_base;
 #pragma unroll
             for (int u = 0; u < KB; ++u) e[t][u] = ep[u * 64 + ln];
           }
-        }
-        // all gathers of the batch are issued before the FMAs consume them
-        cpx<T> g[RPT][KB];
+          cpx<T> g[RPT][KB];
 #pragma unroll
-        for (int t = 0; t < RPT; ++t) {
+          for (int t = 0; t < RPT; ++t) {
 #pragma unroll
-          for (int u = 0; u < KB; ++u) g[t][u] = lds_gather<T>(e[t][u].c);
-        }
+            for (int u = 0; u < KB; ++u) g[t][u] = lds_gather<T>(e[t][u].c);
+          }
 #pragma unroll
-        for (int t = 0; t < RPT; ++t) {
+          for (int t = 0; t < RPT; ++t) {
 #pragma unroll
-          for (int u = 0; u < KB; ++u) {
-            acc_re[t] += e[t][u].v * g[t][u].re;
-            acc_im[t] += e[t][u].v * g[t][u].im;
+            for (int u = 0; u < KB; ++u) {
+              acc_re[t] += e[t][u].v * g[t][u].re;
+              acc_im[t] += e[t][u].v * g[t][u].im;
+            }
           }
         }
       }
@@ -673,8 +725,9 @@ static hipError_t launch_res(hipStream_t st, const ResGraph& g0, const ResGraph*
   if (e != hipSuccess) return e;
   const int max_npad = (max_n + 63) / 64 * 64;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(kResThreads), lds, st, g0.nslices, g0.sbase,
-                     g0.perm, g0.ent, g0.ent64, L.nitems, L.items, g0.zs, g0.B, g0.ldb, g0.kcols,
-                     g0.D, g0.ldd, L.tol, L.maxit, L.max_refine, L.counter, g0.iters, g0.stats,
+                     g0.perm, g0.ent, g0.ent64, g0.n32, L.nitems, L.items, g0.zs, g0.B, g0.ldb,
+                     g0.kcols, g0.D, g0.ldd, L.tol, L.maxit, L.max_refine, L.counter, g0.iters,
+                     g0.stats,
                      g0.resid, (cpx<double>*)L.xhi, g0.zero_base, g0.wave_slices, graphs,
                      max_npad);
   return hipGetLastError();

@@ -92,10 +92,6 @@ hipError_t launch_select(hipStream_t st, int k, int m0, const double* theta, con
 // precision (slot * 8 for FP32 complex, slot * 16 for FP64 complex), so a
 // gather needs no address arithmetic.  Slice widths are padded to a multiple
 // of 4 with (own slot, 0).
-struct SellEntry32 {
-  int c;    // slot * 8
-  float v;
-};
 struct SellEntry64 {
   int c;    // slot * 16
   int pad;
@@ -106,7 +102,12 @@ struct SellMatrix {
   int nslices = 0;
   const int* sbase = nullptr;           // [nslices+1] entry offsets (multiples of 256)
   const int* perm = nullptr;            // [nslices*64] slot -> row (-1: empty slot)
-  const SellEntry32* e32 = nullptr;     // FP32 entries
+  // FP32 entries: n32 values, then n32 uint16 LDS byte offsets (slot * 8).
+  // A slice of width w holds w / 8 octs of 512 entries (values: two halves
+  // of 64 lanes x 4; offsets: 64 lanes x 8), then a quad of 256 entries
+  // (64 lanes x 4) if w % 8 == 4.
+  const float* v32 = nullptr;
+  int n32 = 0;
   const SellEntry64* e64 = nullptr;     // FP64 entries
   int zero_base = 0;                    // 256 entries (slot 0, value 0) start here
   const int* wave_slices = nullptr;     // [waves * wave_rpt] slice of each wave slot, -1 none
@@ -122,10 +123,10 @@ struct ResGraph {
   int ldb = 0;
   int kcols = 0;                        // RHS columns of this graph
   int ldd = 0;
-  int pad_ = 0;
+  int n32 = 0;                          // FP32 entry count (offsets follow the values)
   const int* sbase = nullptr;           // SellMatrix fields of A_g
   const int* perm = nullptr;
-  const void* ent = nullptr;            // SellEntry32 (FP32 engine) or SellEntry64
+  const void* ent = nullptr;            // FP32 values (+ offsets) or SellEntry64
   const SellEntry64* ent64 = nullptr;
   const int* wave_slices = nullptr;     // table built for the launch's slots per wave
   const double* B = nullptr;            // n_g x kcols RHS (FP64), ldb

@@ -53,7 +53,7 @@ struct rafeast_plan_s {
   int* d_sbase = nullptr;
   int* d_perm = nullptr;
   int* d_wtab = nullptr;
-  SellEntry32* d_e32 = nullptr;
+  float* d_v32 = nullptr;  // FP32 SELL values followed by their 16-bit offsets
   SellEntry64* d_e64 = nullptr;
   size_t sell_entries = 0;
   // n x w blocks (row-major, ld = w)
@@ -365,7 +365,7 @@ rafeast_status dalloc(rafeast_plan_s* P, T** p, size_t count, const char* what) 
 
 void free_plan(rafeast_plan_s* P) {
   if (!P) return;
-  void* ptrs[] = {P->d_rowptr, P->d_col,  P->d_val,   P->d_sbase, P->d_perm, P->d_wtab, P->d_e32,
+  void* ptrs[] = {P->d_rowptr, P->d_col,  P->d_val,   P->d_sbase, P->d_perm, P->d_wtab, P->d_v32,
                   P->d_e64,   P->d_Q,    P->d_W,     P->d_R,     P->d_T,    P->d_Y,
                   P->d_G,      P->d_M,    P->d_S,     P->d_Ssel,  P->d_jw,   P->d_theta,
                   P->d_res,    P->d_qn,   P->d_gamma, P->d_info,  P->d_zw,   P->d_part,
@@ -642,7 +642,8 @@ ResGraph resident_graph(const rafeast_plan_s* P, const double* d_zs, int k, cons
   gd.ldd = ldd;
   gd.sbase = P->sell.sbase;
   gd.perm = P->sell.perm;
-  gd.ent = P->fp32 ? (const void*)P->sell.e32 : (const void*)P->sell.e64;
+  gd.ent = P->fp32 ? (const void*)P->sell.v32 : (const void*)P->sell.e64;
+  gd.n32 = P->sell.n32;
   gd.ent64 = P->sell.e64;
   gd.wave_slices = wave_slices;
   gd.B = B;
@@ -1105,7 +1106,10 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
       sb[s + 1] = sb[s] + wd * 64;
     }
     const size_t tot = (size_t)sb[nsl] + 256;  // + a block of zero entries
-    std::vector<SellEntry32> e32(tot, SellEntry32{0, 0.0f});
+    // FP32: values then 16-bit LDS byte offsets (slot * 8 < 65536 since the
+    // FP32 resident engine holds at most 8192 slots)
+    std::vector<float> v32(tot, 0.0f);
+    std::vector<uint16_t> o32(tot, 0);
     std::vector<SellEntry64> e64(tot, SellEntry64{0, 0, 0.0});
     for (int s = 0; s < nsl; ++s) {
       const int wd = (sb[s + 1] - sb[s]) / 64;
@@ -1114,33 +1118,48 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
           const int64_t sl = (int64_t)s * 64 + l;
           const size_t e = (size_t)sb[s] + (size_t)kk * 64 + l;
           const int row = sl < n ? order[sl] : -1;
-          // FP32: pair-major position of entry kk of lane l
-          const size_t e2 = (size_t)sb[s] + (size_t)(kk / 2) * 128 + (size_t)l * 2 + (kk % 2);
+          // FP32 positions: octs of eight entries (values as two 16-byte
+          // halves for all lanes, offsets 16 bytes per lane), then a quad
+          size_t vi, oi;
+          const int n8 = wd / 8;
+          if (kk < 8 * n8) {
+            const int o = kk / 8, j = kk % 8;
+            vi = (size_t)sb[s] + (size_t)o * 512 + (size_t)(j / 4) * 256 + (size_t)l * 4 + j % 4;
+            oi = (size_t)sb[s] + (size_t)o * 512 + (size_t)l * 8 + j;
+          } else {
+            vi = oi = (size_t)sb[s] + (size_t)n8 * 512 + (size_t)l * 4 + (kk - 8 * n8);
+          }
           if (row >= 0 && kk < rp[row + 1] - rp[row]) {
             const int t = rp[row] + kk;
-            e32[e2] = SellEntry32{slot_of[cl[t]] * 8, (float)A->values[t]};
+            v32[vi] = (float)A->values[t];
+            o32[oi] = (uint16_t)(slot_of[cl[t]] * 8);
             e64[e] = SellEntry64{slot_of[cl[t]] * 16, 0, A->values[t]};
           } else {
-            e32[e2] = SellEntry32{(int)sl * 8, 0.0f};  // padding: own slot, zero value
+            // padding: own slot, zero value
+            o32[oi] = (uint16_t)(sl * 8);
             e64[e] = SellEntry64{(int)sl * 16, 0, 0.0};
           }
         }
     }
     PRCHK(dalloc(P, &P->d_sbase, nsl + 1, "sell base"));
     PRCHK(dalloc(P, &P->d_perm, (size_t)nsl * 64, "sell perm"));
-    PRCHK(dalloc(P, &P->d_e32, tot, "sell e32"));
+    if (fp32 && (size_t)nsl * 64 * 8 > 65536)
+      return bail(fail(P, RAFEAST_UNSUPPORTED, "too many rows for 16-bit SELL offsets"));
+    PRCHK(dalloc(P, &P->d_v32, tot + tot / 2, "sell v32"));
     PRCHK(dalloc(P, &P->d_e64, tot, "sell e64"));
     PCHK(hipMemcpy(P->d_sbase, sb.data(), (nsl + 1) * sizeof(int), hipMemcpyHostToDevice));
     PCHK(hipMemcpy(P->d_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
     if (tot) {
-      PCHK(hipMemcpy(P->d_e32, e32.data(), tot * sizeof(SellEntry32), hipMemcpyHostToDevice));
+      PCHK(hipMemcpy(P->d_v32, v32.data(), tot * sizeof(float), hipMemcpyHostToDevice));
+      PCHK(hipMemcpy(P->d_v32 + tot, o32.data(), tot * sizeof(uint16_t), hipMemcpyHostToDevice));
       PCHK(hipMemcpy(P->d_e64, e64.data(), tot * sizeof(SellEntry64), hipMemcpyHostToDevice));
     }
     P->sell.n = (int)n;
     P->sell.nslices = nsl;
     P->sell.sbase = P->d_sbase;
     P->sell.perm = P->d_perm;
-    P->sell.e32 = P->d_e32;
+    P->sell.v32 = P->d_v32;
+    P->sell.n32 = (int)tot;
     P->sell.e64 = P->d_e64;
     P->sell.zero_base = sb[nsl];
     P->sell_entries = tot;
