@@ -31,9 +31,11 @@
 // recursive and the true residual that FP32 storage causes without throwing
 // the Krylov recurrence away.  It restarts from p = s only after a breakdown
 // (p^T w = 0 or a non-finite step), when ||s|| has not at least halved since
-// the previous check, or after a stall: no drop by delta within 4x the
-// previous check interval (and 2x the first interval after the last start,
-// at least 256 iterations) sends the system to an early check.  At most
+// the previous check, or after a stall: no drop by delta within twice the
+// previous check interval (and twice the first interval after the last
+// start, at least 256 iterations) sends the system to an early check, which
+// bounds the iterations an FP32 recurrence can spend drifting away from the
+// true residual on an ill-conditioned system.  At most
 // max_refine checks per system.
 #include "device.h"
 #include "kernels.h"
@@ -537,7 +539,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
         const double s3[3] = {so[0], so[1], so[2]};
         ++it;
         const bool stall =
-            span > 0 && it - lastit > max(max(4 * span, 2 * span0), 256);
+            span > 0 && it - lastit > max(2 * max(span, span0), 256);
         if (s3[2] <= cyc_tol2 || it >= maxit || stall) {
           verify = true;
         } else {

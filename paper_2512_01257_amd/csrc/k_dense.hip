@@ -29,8 +29,22 @@ __global__ __launch_bounds__(256) void k_spmm_f64(int n, int k, const int* __res
   for (int c0 = 0; c0 < k; c0 += 64) {
     const int c = c0 + lane;
     const bool ok = c < k;
+    // four gathered rows in flight per wave; even and odd nonzeros go to two
+    // partial sums in row order
     double acc0 = 0.0, acc1 = 0.0;
     int t = s;
+    for (; t + 3 < e; t += 4) {
+      const int j0 = col[t], j1 = col[t + 1], j2 = col[t + 2], j3 = col[t + 3];
+      const double a0 = val[t], a1 = val[t + 1], a2 = val[t + 2], a3 = val[t + 3];
+      if (ok) {
+        const double x0 = X[(size_t)j0 * ldx + c], x1 = X[(size_t)j1 * ldx + c];
+        const double x2 = X[(size_t)j2 * ldx + c], x3 = X[(size_t)j3 * ldx + c];
+        acc0 += a0 * x0;
+        acc1 += a1 * x1;
+        acc0 += a2 * x2;
+        acc1 += a3 * x3;
+      }
+    }
     for (; t + 1 < e; t += 2) {
       const int j0 = col[t], j1 = col[t + 1];
       const double a0 = val[t], a1 = val[t + 1];
