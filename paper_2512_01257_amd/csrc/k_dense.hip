@@ -63,10 +63,110 @@ __global__ __launch_bounds__(256) void k_spmm_f64(int n, int k, const int* __res
   }
 }
 
+// Two columns per lane (16-byte loads) and 64 / L rows per wave, L the
+// power of two of lanes that covers k / 2 columns pairs (k even, ld even and
+// 16-byte aligned blocks): each load instruction moves twice the bytes of the
+// one-column form, and a wave serves several short rows at once.  Nonzeros
+// go to two partial sums (even and odd positions) in row order.
+template <int L>
+__global__ __launch_bounds__(256) void k_spmm_f64_x2(int n, int k, const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ X, int ldx,
+                                                     double* __restrict__ Y, int ldy, double alpha,
+                                                     double beta, const double* __restrict__ X2,
+                                                     int ldx2, double gamma) {
+  constexpr int RW = 64 / L;  // rows per wave
+  const int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RW + lane / L;
+  if (row >= n) return;
+  const int sub = lane % L;
+  const int s = rowptr[row], e = rowptr[row + 1];
+  for (int c0 = 0; c0 < k; c0 += 2 * L) {
+    const int c = c0 + 2 * sub;
+    const bool ok = c < k;
+    double2 acc0 = make_double2(0.0, 0.0), acc1 = acc0;
+    int t = s;
+    for (; t + 3 < e; t += 4) {
+      const int j0 = col[t], j1 = col[t + 1], j2 = col[t + 2], j3 = col[t + 3];
+      const double a0 = val[t], a1 = val[t + 1], a2 = val[t + 2], a3 = val[t + 3];
+      if (ok) {
+        const double2 x0 = *reinterpret_cast<const double2*>(X + (size_t)j0 * ldx + c);
+        const double2 x1 = *reinterpret_cast<const double2*>(X + (size_t)j1 * ldx + c);
+        const double2 x2 = *reinterpret_cast<const double2*>(X + (size_t)j2 * ldx + c);
+        const double2 x3 = *reinterpret_cast<const double2*>(X + (size_t)j3 * ldx + c);
+        acc0.x += a0 * x0.x;
+        acc0.y += a0 * x0.y;
+        acc1.x += a1 * x1.x;
+        acc1.y += a1 * x1.y;
+        acc0.x += a2 * x2.x;
+        acc0.y += a2 * x2.y;
+        acc1.x += a3 * x3.x;
+        acc1.y += a3 * x3.y;
+      }
+    }
+    for (; t + 1 < e; t += 2) {
+      const int j0 = col[t], j1 = col[t + 1];
+      const double a0 = val[t], a1 = val[t + 1];
+      if (ok) {
+        const double2 x0 = *reinterpret_cast<const double2*>(X + (size_t)j0 * ldx + c);
+        const double2 x1 = *reinterpret_cast<const double2*>(X + (size_t)j1 * ldx + c);
+        acc0.x += a0 * x0.x;
+        acc0.y += a0 * x0.y;
+        acc1.x += a1 * x1.x;
+        acc1.y += a1 * x1.y;
+      }
+    }
+    if (t < e && ok) {
+      const double a0 = val[t];
+      const double2 x0 = *reinterpret_cast<const double2*>(X + (size_t)col[t] * ldx + c);
+      acc0.x += a0 * x0.x;
+      acc0.y += a0 * x0.y;
+    }
+    if (ok) {
+      double2 y = make_double2(alpha * (acc0.x + acc1.x), alpha * (acc0.y + acc1.y));
+      if (beta != 0.0) {
+        const double2 xr = *reinterpret_cast<const double2*>(X + (size_t)row * ldx + c);
+        y.x += beta * xr.x;
+        y.y += beta * xr.y;
+      }
+      if (X2 != nullptr) {
+        const double2 x2r = *reinterpret_cast<const double2*>(X2 + (size_t)row * ldx2 + c);
+        y.x += gamma * x2r.x;
+        y.y += gamma * x2r.y;
+      }
+      *reinterpret_cast<double2*>(Y + (size_t)row * ldy + c) = y;
+    }
+  }
+}
+
 hipError_t launch_spmm_f64(hipStream_t st, int n, int k, const int* rowptr, const int* col,
                            const double* val, const double* X, int ldx, double* Y, int ldy,
                            double alpha, double beta, const double* X2, int ldx2, double gamma) {
   if (n <= 0 || k <= 0) return hipSuccess;
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const bool x2_ok = X2 == nullptr || (ldx2 % 2 == 0 && al16(X2));
+  if (k % 2 == 0 && ldx % 2 == 0 && ldy % 2 == 0 && al16(X) && al16(Y) && x2_ok) {
+    // lanes per row: the power of two covering k / 2 column pairs (<= 64)
+    int L = 1;
+    while (L < 64 && 2 * L < k) L *= 2;
+    const int rw = 64 / L;
+    const dim3 grid((unsigned)((n + 4 * rw - 1) / (4 * rw)));
+#define RAFEAST_SPMM_X2(LL)                                                                      \
+  hipLaunchKernelGGL(k_spmm_f64_x2<LL>, grid, dim3(256), 0, st, n, k, rowptr, col, val, X, ldx, \
+                     Y, ldy, alpha, beta, X2, ldx2, gamma)
+    switch (L) {
+      case 1: RAFEAST_SPMM_X2(1); break;
+      case 2: RAFEAST_SPMM_X2(2); break;
+      case 4: RAFEAST_SPMM_X2(4); break;
+      case 8: RAFEAST_SPMM_X2(8); break;
+      case 16: RAFEAST_SPMM_X2(16); break;
+      case 32: RAFEAST_SPMM_X2(32); break;
+      default: RAFEAST_SPMM_X2(64); break;
+    }
+#undef RAFEAST_SPMM_X2
+    return hipGetLastError();
+  }
   dim3 grid((n + 3) / 4);
   hipLaunchKernelGGL(k_spmm_f64, grid, dim3(256), 0, st, n, k, rowptr, col, val, X, ldx, Y, ldy,
                      alpha, beta, X2, ldx2, gamma);
