@@ -487,6 +487,8 @@ def main():
                          "random-geometric-graph sweep")
     ap.add_argument("--max-iter", type=int, default=20, help="grid64: FEAST iteration cap")
     ap.add_argument("--max-cocg", type=int, default=20000, help="grid64: COCG iteration cap")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="only the FP64 SpMM rate measurement (for profiling)")
     ap.add_argument("--rgg-n", default="2000,4000,8000,16000", help="rgg: graph sizes")
     ap.add_argument("--seeds", type=int, default=3, help="rgg: seeds per size (at most 40)")
     args = ap.parse_args()
@@ -503,6 +505,17 @@ def main():
         return main_grid64(args)
     if args.workload == "rgg":
         return main_rgg(args)
+    if args.spmm_only:
+        import torch
+
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        if args.copy_probe:
+            src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+        print(json.dumps({"spmm": spmm_rate()}), flush=True)
+        return
 
     import numpy as np
     import torch
