@@ -207,6 +207,21 @@ rafeast_status rafeast_plan_info(rafeast_plan_t plan, double* sig_lo, double* si
  * 0 for a NULL plan. */
 int32_t rafeast_plan_engine(rafeast_plan_t plan);
 
+/* The launch shape rafeast_plan chose by measurement (autotuning; the
+ * batching form's tuned SpMM tiles).  Resident engine: the SELL slices each
+ * thread holds (1, 2, 4 or 8; it fixes the slice-to-wave table), every count
+ * from the smallest that fits up to the maximum timed on the plan's own
+ * matrix (64 COCG iterations of the first min(systems, CUs) systems on
+ * Gaussian right-hand sides); the fastest is used.  RAFEAST_TUNE=0 in the
+ * environment keeps the smallest.  Out: *chosen (0 for the streaming engine,
+ * which is not tuned), *count candidates, and up to max of them in cand[]
+ * with their measured milliseconds in ms[] (0 when untimed: a single
+ * candidate or tuning off).  Host pointers owned by the caller.  Errors:
+ * INVALID_ARG for a NULL plan, chosen or count, max < 0, or NULL cand/ms
+ * with max > 0. */
+rafeast_status rafeast_plan_tuning(rafeast_plan_t plan, int32_t* chosen, int32_t* count,
+                                   int32_t* cand, float* ms, int32_t max);
+
 /* Reverse Cuthill-McKee order of the graph of A (host only, needs no
  * device): per connected component, breadth-first search from a
  * pseudo-peripheral vertex (George-Liu), neighbours by increasing degree, the

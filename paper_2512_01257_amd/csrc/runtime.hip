@@ -87,6 +87,11 @@ struct rafeast_plan_s {
   void* d_xhi = nullptr;     // FP64 solution scratch of the resident COCG engine
   size_t xhi_slots = 0;
   std::vector<int> sell_widths; // slice widths, for wave tables of other slot counts
+  // autotuned launch shape (resident engine: slots per thread), candidates
+  // and their measured times
+  int tune_choice = 0;
+  std::vector<int> tune_cand;
+  std::vector<float> tune_ms;
   // streaming engine: A in reverse Cuthill-McKee order, FP64 and FP32 values
   int* d_srow = nullptr;
   int* d_scol = nullptr;
@@ -967,6 +972,81 @@ const char* rafeast_last_error(rafeast_plan_t plan) {
 
 void rafeast_destroy(rafeast_plan_t plan) { free_plan(plan); }
 
+// Autotuned launch shape of the resident engine: how many SELL slices
+// (slots) each thread holds, which fixes the wave table and the kernel
+// instance.  Every slot count from the smallest that fits up to the engine's
+// maximum is timed on the plan's own matrix: the first min(systems, CUs)
+// systems of the solve order (the hardest shift first) on Gaussian
+// right-hand sides, run for a fixed 64 iterations (tolerance 0), one untimed
+// launch and then the best of two timed ones; the fastest count wins (ties
+// to fewer slots).  RAFEAST_TUNE=0 keeps the smallest count.
+rafeast_status tune_resident(rafeast_plan_s* P) {
+  const int maxr = P->fp32 ? 8 : 4;
+  std::vector<std::vector<int>> tabs;
+  P->tune_cand.clear();
+  for (int r = P->sell.wave_rpt; r <= maxr; r *= 2) {
+    std::vector<int> t = cocg_resident_wave_table(P->sell_widths, r);
+    if (t.empty()) continue;
+    P->tune_cand.push_back(r);
+    tabs.push_back(std::move(t));
+  }
+  P->tune_ms.assign(P->tune_cand.size(), 0.0f);
+  P->tune_choice = P->sell.wave_rpt;
+  const char* env = std::getenv("RAFEAST_TUNE");
+  if (P->tune_cand.size() < 2 || (env && std::strcmp(env, "0") == 0)) return RAFEAST_OK;
+  const int m0 = P->m0, ld = P->ld;
+  HIPCHK(P, launch_gaussian(P->st, P->n, m0, 0x7u, P->d_R, ld));
+  CocgLaunch L;
+  L.nitems = std::min(P->nitems, std::max(P->num_cu, 1));
+  L.items = P->d_items;
+  L.tol = 0.0;
+  L.maxit = 64;
+  L.max_refine = 64;
+  L.counter = P->d_counter;
+  L.xhi = P->d_xhi;
+  L.xhi_slots = P->xhi_slots;
+  int* d_tab = nullptr;
+  HIPCHK(P, hipMalloc(&d_tab, (size_t)cocg_resident_waves() * maxr * sizeof(int)));
+  hipError_t e = hipSuccess;
+  size_t best = 0;
+  for (size_t c = 0; c < P->tune_cand.size() && e == hipSuccess; ++c) {
+    e = hipMemcpyAsync(d_tab, tabs[c].data(), tabs[c].size() * sizeof(int),
+                       hipMemcpyHostToDevice, P->st);
+    const ResGraph gd = resident_graph(P, P->d_zw, m0, P->d_R, ld, P->d_D, P->nc * m0,
+                                       P->d_iters, nullptr, d_tab);
+    float tbest = 0.0f;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+      e = launch_fill_int(P->st, P->d_counter, 0, 1);
+      if (e == hipSuccess) e = hipEventRecord(P->ev[0], P->st);
+      if (e == hipSuccess)
+        e = launch_cocg_resident(P->st, &gd, nullptr, (int)P->n, P->tune_cand[c], L, P->fp32,
+                                 P->num_cu);
+      if (e == hipSuccess) e = hipEventRecord(P->ev[1], P->st);
+      if (e == hipSuccess) e = hipEventSynchronize(P->ev[1]);
+      const float t = elapsed(P->ev[0], P->ev[1]);
+      if (rep == 1 || (rep == 2 && t < tbest)) tbest = t;
+    }
+    P->tune_ms[c] = tbest;
+    if (tbest < P->tune_ms[best]) best = c;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P->d_wtab, tabs[best].data(), tabs[best].size() * sizeof(int),
+                       hipMemcpyHostToDevice, P->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(P->st);
+  (void)hipFree(d_tab);
+  HIPCHK(P, e);
+  P->tune_choice = P->tune_cand[best];
+  P->sell.wave_rpt = P->tune_choice;
+  if (verbose_log()) {
+    std::fprintf(stderr, "rafeast: resident slots per thread:");
+    for (size_t c = 0; c < P->tune_cand.size(); ++c)
+      std::fprintf(stderr, " %d: %.3f ms%s", P->tune_cand[c], P->tune_ms[c],
+                   c == best ? " (chosen)" : "");
+    std::fprintf(stderr, "\n");
+  }
+  return RAFEAST_OK;
+}
+
 rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
                             rafeast_plan_t* out) {
   g_plan_error.clear();
@@ -1183,7 +1263,8 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
       engine = RAFEAST_ENGINE_STREAM;  // AUTO: rows too long for the on-chip layout
     } else {
       engine = RAFEAST_ENGINE_RESIDENT;
-      PRCHK(dalloc(P, &P->d_wtab, tab.size(), "wave table"));
+      // room for the largest slot count the tuner may choose
+      PRCHK(dalloc(P, &P->d_wtab, (size_t)cocg_resident_waves() * 8, "wave table"));
       PCHK(hipMemcpy(P->d_wtab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
       P->sell.wave_slices = P->d_wtab;
       P->sell.wave_rpt = rpt;
@@ -1284,11 +1365,25 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
     std::vector<int> items = make_items(P->nc, P->zw.data(), P->m0);
     PCHK(hipMemcpy(P->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
   }
+  if (P->engine == RAFEAST_ENGINE_RESIDENT) PRCHK(tune_resident(P));
   PCHK(hipMemset(P->d_stats, 0, 2 * sizeof(int)));
   PCHK(hipDeviceSynchronize());
 #undef PCHK
 #undef PRCHK
   *out = P;
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_plan_tuning(rafeast_plan_t P, int32_t* chosen, int32_t* count,
+                                   int32_t* cand, float* ms, int32_t max) {
+  if (!P || !chosen || !count || max < 0 || (max > 0 && (!cand || !ms)))
+    return fail(P, RAFEAST_INVALID_ARG, "null argument");
+  *chosen = P->engine == RAFEAST_ENGINE_RESIDENT ? P->tune_choice : 0;
+  *count = (int32_t)P->tune_cand.size();
+  for (int32_t i = 0; i < max && i < *count; ++i) {
+    cand[i] = P->tune_cand[i];
+    ms[i] = P->tune_ms[i];
+  }
   return RAFEAST_OK;
 }
 

@@ -97,6 +97,9 @@ def lib():
     L.rafeast_plan_info.restype = C.c_int
     L.rafeast_plan_engine.argtypes = [P]
     L.rafeast_plan_engine.restype = C.c_int32
+    L.rafeast_plan_tuning.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_float), C.c_int32]
+    L.rafeast_plan_tuning.restype = C.c_int
     L.rafeast_rcm_order.argtypes = [C.POINTER(Csr), C.POINTER(C.c_int32)]
     L.rafeast_rcm_order.restype = C.c_int
     L.rafeast_pc_param_count.argtypes = []
@@ -277,6 +280,16 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def tuning(self):
+        """rafeast_plan_tuning: the chosen resident slots per thread (0 for the
+        streaming engine) and the timed candidates as (slots, ms) pairs."""
+        ch, cnt = C.c_int32(), C.c_int32()
+        cand = (C.c_int32 * 8)()
+        ms = (C.c_float * 8)()
+        self._check(lib().rafeast_plan_tuning(self._h, C.byref(ch), C.byref(cnt), cand, ms, 8))
+        return dict(chosen=ch.value, candidates=[(cand[i], ms[i]) for i in range(min(cnt.value, 8))])
 
     @property
     def engine(self):

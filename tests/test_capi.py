@@ -162,3 +162,11 @@ def test_batch_argument_errors(native):
     assert L.rafeast_plan_batch(0, As, (native.Params * 2)(p0, p0), C.byref(h)) == 1
     if not _has_gpu():
         assert L.rafeast_plan_batch(2, As, (native.Params * 2)(p0, p0), C.byref(h)) == 5
+
+
+def test_plan_tuning_argument_errors(native):
+    L = native.lib()
+    ch, cnt = C.c_int32(), C.c_int32()
+    cand = (C.c_int32 * 4)()
+    ms = (C.c_float * 4)()
+    assert L.rafeast_plan_tuning(None, C.byref(ch), C.byref(cnt), cand, ms, 4) == 1

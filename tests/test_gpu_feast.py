@@ -233,3 +233,32 @@ def test_spurious_ritz_value_excluded(gpu_lib):
         assert out["status"] == "OK" and out["M"] == 5, (precision, out["status"], out["M"])
         np.testing.assert_allclose(out["lam"], inside, atol=1e-12)
         assert abs(out["iters"] - ref["iters"]) <= 1
+
+
+def test_resident_autotune(gpu_lib, monkeypatch):
+    # rafeast_plan times every fitting slots-per-thread count and keeps the
+    # fastest; the tuned and the untuned (smallest count) plans agree
+    dims, shift = (40, 40), 0.01
+    csr = grid_laplacian(dims, shift)
+    lmin, lmax = CFG1_WIN
+    vals, _ = window_basis(dims, shift, lmin, lmax)
+    lam = {}
+    for tune in ("1", "0"):
+        monkeypatch.setenv("RAFEAST_TUNE", tune)
+        with gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10) as plan:
+            assert plan.engine == "resident"
+            t = plan.tuning
+            cands = [c for c, _ in t["candidates"]]
+            assert len(cands) >= 2 and cands == sorted(cands) and t["chosen"] in cands
+            if tune == "1":
+                assert all(ms > 0 for _, ms in t["candidates"])
+            else:
+                assert t["chosen"] == cands[0] and all(ms == 0 for _, ms in t["candidates"])
+            plan.warmstart(omega=gaussian(csr.n, plan.w, 0))
+            out = plan.solve(want_vectors=False)
+        assert out["status"] == "OK" and out["M"] == len(vals)
+        np.testing.assert_allclose(out["lam"], vals, atol=1e-10 * lmax)
+        lam[tune] = out["lam"]
+    np.testing.assert_allclose(lam["1"], lam["0"], atol=1e-10 * lmax)
+    with gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10, engine="stream") as plan:
+        assert plan.tuning == dict(chosen=0, candidates=[])
