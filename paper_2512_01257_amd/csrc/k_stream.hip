@@ -33,6 +33,10 @@
 // converge early stop costing bandwidth.  Group order follows the column
 // order c = j * k + i.
 //
+// An iteration: K1 forms p = r + beta p on the rows each wave owns, K2 the
+// SpMV w = (zI - A) p gathering only p (a fused form that gathered r and the
+// old p and formed p on the fly read twice the neighbour bytes, 20% slower),
+// the finalisers turn partials into alpha, K3 updates x and r.
 // Row kernels: 256 threads (4 waves).  Each XCD sweeps one contiguous eighth
 // of the rows with all its waves side by side (see wave_rows), keeping the
 // neighbour gathers in that XCD's L2.  A wave takes one row at a time; its 64
@@ -165,39 +169,71 @@ __device__ __forceinline__ void col_sums(const double* __restrict__ part, int nb
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// K1 of an iteration: p_new = r + beta p_old (own row and every gathered row),
-// w = z p_new - A p_new, partials of mu = p_new^T w.  Columns not in state 1
-// copy p_old and get w = 0.
-//
-// Latency: a wave's row pointers are loaded 64 rows at a time (one lane per
-// row) and a row's entries with one lane per entry, the next row's entries
-// while the current row's gathers are in flight; column indices and values
-// are then broadcast from lanes, and the gathers go out 8 entries at a time.
+// K1: the new search direction of the group's live columns, p = r + beta p
+// (frozen columns keep p), written to the other p buffer; own rows only, so
+// the SpMV after it gathers a single vector.
 template <typename T, int CPL>
-__global__ __launch_bounds__(kST) void k_s_spmm(int n, const int* __restrict__ rowptr,
-                                                const int* __restrict__ col,
-                                                const T* __restrict__ val, int Bp,
-                                                StreamGroups grp, const double* __restrict__ zc,
+__global__ __launch_bounds__(kST) void k_s_pupd(int n, int Bp, StreamGroups grp,
                                                 const double* __restrict__ beta,
                                                 const int* __restrict__ state,
                                                 const cpx<T>* __restrict__ r,
-                                                cpx<T>* __restrict__ pa, cpx<T>* __restrict__ pb,
-                                                cpx<T>* __restrict__ w,
-                                                double* __restrict__ part) {
-  extern __shared__ double sh[];
+                                                cpx<T>* __restrict__ pa, cpx<T>* __restrict__ pb) {
   const int lane = threadIdx.x & 63;
   const int c0 = grp.g[blockIdx.y] * 64 * CPL;
-  // the group's current p is read, the next one written to the other buffer
   const cpx<T>* __restrict__ pold = grp.par[blockIdx.y] ? pb : pa;
   cpx<T>* __restrict__ pnew = grp.par[blockIdx.y] ? pa : pb;
   const int cl = c0 + lane * CPL;
-  T bre[CPL], bim[CPL], zre[CPL], zim[CPL];
+  T bre[CPL], bim[CPL];
   bool live[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     bre[q] = T(beta[2 * (cl + q)]);
     bim[q] = T(beta[2 * (cl + q) + 1]);
+    live[q] = state[cl + q] == 1;
+  }
+  const WaveRows wr = wave_rows(n);
+  for (int k = 0; k < wr.count; ++k) {
+    const size_t ro = (size_t)(wr.first + wr.stride * k) * Bp + cl;
+    const Chunk<T, CPL> r0 = ld<T, CPL>(r + ro);
+    const Chunk<T, CPL> p0 = ld<T, CPL>(pold + ro);
+    Chunk<T, CPL> pn;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      if (live[q]) {
+        pn.v[q].re = r0.v[q].re + bre[q] * p0.v[q].re - bim[q] * p0.v[q].im;
+        pn.v[q].im = r0.v[q].im + bre[q] * p0.v[q].im + bim[q] * p0.v[q].re;
+      } else {
+        pn.v[q] = p0.v[q];
+      }
+    }
+    st<T, CPL>(pnew + ro, pn);
+  }
+}
+
+// K2: w = (z I - A) p over the group's columns (p the current buffer, frozen
+// columns give w = 0) and the partials of mu = p^T w.  A wave takes one row
+// at a time; the row's entries come lane-parallel (lane l holds entry l) and
+// are broadcast with readlane, the next row's entries in flight during this
+// row's gathers; each gather is one 16-byte load per lane.
+template <typename T, int CPL>
+__global__ __launch_bounds__(kST) void k_s_spmm(int n, const int* __restrict__ rowptr,
+                                                const int* __restrict__ col,
+                                                const T* __restrict__ val, int Bp,
+                                                StreamGroups grp, const double* __restrict__ zc,
+                                                const int* __restrict__ state,
+                                                const cpx<T>* __restrict__ pa,
+                                                const cpx<T>* __restrict__ pb,
+                                                cpx<T>* __restrict__ w,
+                                                double* __restrict__ part) {
+  extern __shared__ double sh[];
+  const int lane = threadIdx.x & 63;
+  const int c0 = grp.g[blockIdx.y] * 64 * CPL;
+  const cpx<T>* __restrict__ p = grp.par[blockIdx.y] ? pb : pa;
+  const int cl = c0 + lane * CPL;
+  T zre[CPL], zim[CPL];
+  bool live[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
     zre[q] = T(zc[2 * (cl + q)]);
     zim[q] = T(zc[2 * (cl + q) + 1]);
     live[q] = state[cl + q] == 1;
@@ -237,8 +273,7 @@ __global__ __launch_bounds__(kST) void k_s_spmm(int n, const int* __restrict__ r
     const int row = wr.first + wr.stride * k;
     const int len = e - s;
     const size_t ro = (size_t)row * Bp + cl;
-    const Chunk<T, CPL> r0 = ld<T, CPL>(r + ro);
-    const Chunk<T, CPL> p0 = ld<T, CPL>(pold + ro);
+    const Chunk<T, CPL> p0 = ld<T, CPL>(p + ro);
     // next row's entries, in flight during this row's gathers
     int s2 = 0, e2 = 0, mc2 = 0;
     T mv2 = T(0);
@@ -263,39 +298,31 @@ __global__ __launch_bounds__(kST) void k_s_spmm(int n, const int* __restrict__ r
           j[u] = __builtin_amdgcn_readlane(cc, t0 + u);
           a[u] = lane_bcast(cv, t0 + u);
         }
-        Chunk<T, CPL> rj[NB], pj[NB];
+        Chunk<T, CPL> pj[NB];
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-          const size_t jo = (size_t)j[u] * Bp + cl;
-          rj[u] = ld<T, CPL>(r + jo);
-          pj[u] = ld<T, CPL>(pold + jo);
-        }
+        for (int u = 0; u < NB; ++u) pj[u] = ld<T, CPL>(p + (size_t)j[u] * Bp + cl);
 #pragma unroll
         for (int u = 0; u < NB; ++u)
 #pragma unroll
           for (int q = 0; q < CPL; ++q) {
-            ar[q] += a[u] * (rj[u].v[q].re + bre[q] * pj[u].v[q].re - bim[q] * pj[u].v[q].im);
-            ai[q] += a[u] * (rj[u].v[q].im + bre[q] * pj[u].v[q].im + bim[q] * pj[u].v[q].re);
+            ar[q] += a[u] * pj[u].v[q].re;
+            ai[q] += a[u] * pj[u].v[q].im;
           }
       }
     }
-    Chunk<T, CPL> pn, ww;
+    Chunk<T, CPL> ww;
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
       if (live[q]) {
-        pn.v[q].re = r0.v[q].re + bre[q] * p0.v[q].re - bim[q] * p0.v[q].im;
-        pn.v[q].im = r0.v[q].im + bre[q] * p0.v[q].im + bim[q] * p0.v[q].re;
-        ww.v[q].re = zre[q] * pn.v[q].re - zim[q] * pn.v[q].im - ar[q];
-        ww.v[q].im = zre[q] * pn.v[q].im + zim[q] * pn.v[q].re - ai[q];
+        ww.v[q].re = zre[q] * p0.v[q].re - zim[q] * p0.v[q].im - ar[q];
+        ww.v[q].im = zre[q] * p0.v[q].im + zim[q] * p0.v[q].re - ai[q];
       } else {
-        pn.v[q] = p0.v[q];
         ww.v[q] = cpx<T>{T(0), T(0)};
       }
-      const double pr = pn.v[q].re, pi = pn.v[q].im, wr_ = ww.v[q].re, wi = ww.v[q].im;
+      const double pr = p0.v[q].re, pi = p0.v[q].im, wr_ = ww.v[q].re, wi = ww.v[q].im;
       acc[q][0] += pr * wr_ - pi * wi;
       acc[q][1] += pr * wi + pi * wr_;
     }
-    st<T, CPL>(pnew + ro, pn);
     st<T, CPL>(w + ro, ww);
     s = s2;
     e = e2;
@@ -806,12 +833,14 @@ static hipError_t run_stream_t(hipStream_t stm, const StreamMatrix& A, const Str
     if (live.count > 0) {
       const dim3 gl(nb, live.count);
       for (int k = 0; k < chunk; ++k) {
-        SLAUNCH((k_s_spmm<T, CPL>), gl, blk, shm(2), stm, n, A.rowptr, A.col, val, Bp, live, W.zc,
-                W.cols.beta, W.cols.state, R, Pa, Pb, Wv, W.part);
+        SLAUNCH((k_s_pupd<T, CPL>), gl, blk, 0, stm, n, Bp, live, W.cols.beta, W.cols.state, R,
+                Pa, Pb);
         for (int i = 0; i < live.count; ++i) {  // the new p is now current
           live.par[i] ^= 1;
           parity[live.g[i]] ^= 1;
         }
+        SLAUNCH((k_s_spmm<T, CPL>), gl, blk, shm(2), stm, n, A.rowptr, A.col, val, Bp, live, W.zc,
+                W.cols.state, Pa, Pb, Wv, W.part);
         SLAUNCH(k_s_fin_mu, fgrid, fblk, 0, stm, Bp, nb, W.part, W.cols);
         SLAUNCH((k_s_update<T, CPL>), gl, blk, shm(3), stm, n, Bp, live, W.cols.alpha, X, R, Pa,
                 Pb, Wv, W.part);
