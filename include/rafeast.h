@@ -123,6 +123,15 @@ typedef struct rafeast_params {
   int32_t engine;          /* RAFEAST_ENGINE_* */
   uint64_t seed;           /* Philox key of the device-generated sketch */
   void* hip_stream;        /* hipStream_t to run on; NULL: the plan creates its own */
+  double tol_solve_relaxed; /* Phase 2 with relaxed solves (Section 3.3: k_inexact, from
+                              relaxed tolerances; Theorem 2).  0, or a value <= tol_solve:
+                              every solve uses tol_solve.  A value in (tol_solve, 1):
+                              the solves of each rafeast_solve start at this relative
+                              tolerance, and whenever a filter application fails to halve
+                              the largest counted residual the tolerance drops 100-fold,
+                              not below tol_solve.  Needs rhs_form RESIDUAL, whose solve
+                              error scales with the Ritz residual (a literal-form solve
+                              error sets a floor near the tolerance) */
 } rafeast_params;
 
 /* Phase-1 diagnostics (Remark 1's post-hoc check of the power-count condition,
@@ -149,11 +158,14 @@ typedef struct rafeast_result {
                               iteration, summed over all systems */
   double max_resid;        /* out: max scaled residual over the M pairs */
   double t_ms[RAFEAST_NPHASE]; /* out: device time per phase (HIP events) */
+  double tol_solve_last;   /* out: COCG tolerance of the last filter application
+                              (the starting one when none ran) */
 } rafeast_result;
 
 /* Fills *p with defaults: m0 = 0 (must be set), nc = 8, q = 2, p = -1,
  * tol_eig = 1e-10, tol_solve = 1e-6, max_iter = 20, max_cocg = 20000,
- * precision FP32_REFINED, ws_op AUTO, rhs_form RESIDUAL, engine AUTO, seed 0. */
+ * precision FP32_REFINED, ws_op AUTO, rhs_form RESIDUAL, engine AUTO, seed 0,
+ * tol_solve_relaxed 0 (fixed tolerance). */
 void rafeast_params_default(rafeast_params* p);
 
 /* Validates A and the parameters, copies A to the device (FP64 values plus an

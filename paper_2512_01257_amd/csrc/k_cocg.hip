@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const double tol2 = tol * tol;
+  double tol2 = tol * tol;  // of the current graph
   cpx<double>* __restrict__ XH = xhi_all + (size_t)blockIdx.x * max_npad;
 
   // The graph of the current item.  A descriptor from the array is read
@@ -252,6 +252,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     iters = G.iters;
     resid_out = G.resid;
     stats = G.stats;
+    tol2 = G.tol * G.tol;
     R = P + nslices * 64;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) slc[t] = G.wave_slices[wv * RPT + t];
@@ -275,6 +276,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     g0.iters = a_iters;
     g0.resid = a_resid;
     g0.stats = a_stats;
+    g0.tol = tol;
     load_graph(g0);
   }
 

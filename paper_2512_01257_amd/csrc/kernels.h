@@ -135,6 +135,7 @@ struct ResGraph {
   int* iters = nullptr;                 // [nz kcols] iterations per system
   double* resid = nullptr;              // nullable [nz kcols] final relative true residual
   int* stats = nullptr;                 // [2]: continued checks, breakdowns (accumulated)
+  double tol = 0.0;                     // relative residual tolerance of this graph's systems
 };
 
 struct CocgLaunch {

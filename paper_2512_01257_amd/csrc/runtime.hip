@@ -107,6 +107,9 @@ struct rafeast_plan_s {
   // transforms, k x k row-major, host); valid while have_filter
   std::vector<double> mtot;
   bool have_filter = false;
+  // COCG tolerance of the next filter application (tol_solve, or the relaxed
+  // tolerance of Phase 2 while it still contracts)
+  double tau = 0.0;
   int ws_used = RAFEAST_WS_NONE;
   std::string err;
   hipEvent_t ev[8] = {};
@@ -246,6 +249,10 @@ rafeast_status validate_params(const rafeast_params* p, int64_t n, std::string& 
   }
   if (!(p->tol_eig > 0.0) || !(p->tol_solve > 0.0) || !(p->tol_solve < 1.0)) {
     msg = "tolerances must satisfy tol_eig > 0 and 0 < tol_solve < 1";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (!(p->tol_solve_relaxed >= 0.0) || !(p->tol_solve_relaxed < 1.0)) {
+    msg = "tol_solve_relaxed must satisfy 0 <= tol_solve_relaxed < 1";
     return RAFEAST_INVALID_ARG;
   }
   if (p->max_iter < 0 || p->max_cocg < 1) {
@@ -657,6 +664,7 @@ ResGraph resident_graph(const rafeast_plan_s* P, const double* d_zs, int k, cons
   gd.iters = d_iters;
   gd.resid = d_resid;
   gd.stats = P->d_stats;
+  gd.tol = P->tau;
   return gd;
 }
 
@@ -747,6 +755,7 @@ struct SolveRun {
   rafeast_status status = RAFEAST_NO_CONVERGENCE;
   int it = 0, M = 0;
   double maxres = 0.0;
+  double prev_maxres = 0.0;  // largest counted residual of the previous test (0: none)
   int64_t cocg_sum = 0;
   int cocg_max = 0;
   bool breakdown = false, done = false;
@@ -782,6 +791,7 @@ rafeast_status solve_begin(rafeast_plan_s* P, const double* Q_init, SolveRun& S)
   }
   HIPCHK(P, hipMemsetAsync(P->d_stats, 0, 2 * sizeof(int), P->st));
   P->have_filter = false;
+  P->tau = std::max(P->prm.tol_solve, P->prm.tol_solve_relaxed);
   S = SolveRun();
   S.iters.assign(P->nitems, 0);
   return RAFEAST_OK;
@@ -813,6 +823,16 @@ rafeast_status solve_test(rafeast_plan_s* P, SolveRun& S) {
   } else if (S.it >= P->prm.max_iter) {
     S.done = true;
   }
+  // Relaxed solves (Theorem 2): e_{m+1} <= rho e_m + eps^(m), and in the
+  // residual-correction form a solve of relative accuracy tau contributes
+  // eps^(m) of order tau e_m.  While the iteration keeps contracting, tau
+  // stays; a filter application that fails to halve the largest counted
+  // residual means the solve error has caught up with the contraction, and
+  // tau drops 100-fold, not below tol_solve.
+  if (!S.done && S.it >= 1 && S.prev_maxres > 0.0 && S.M > 0 && P->tau > P->prm.tol_solve &&
+      S.maxres > 0.5 * S.prev_maxres)
+    P->tau = std::max(P->prm.tol_solve, 1e-2 * P->tau);
+  if (S.M > 0) S.prev_maxres = S.maxres;
   return RAFEAST_OK;
 }
 
@@ -822,9 +842,9 @@ rafeast_status solve_shifted_systems(rafeast_plan_s* P) {
   const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
   if (P->engine == RAFEAST_ENGINE_STREAM)
     return run_stream(P, P->swork, nc, m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D, nc * m0,
-                      P->prm.tol_solve, P->d_iters);
+                      P->tau, P->d_iters);
   return run_cocg(P, P->nitems, P->d_items, P->d_zw, m0, residual_form ? P->d_R : P->d_Q, ld,
-                  P->d_D, nc * m0, P->prm.tol_solve, P->d_iters);
+                  P->d_D, nc * m0, P->tau, P->d_iters);
 }
 
 // After the solves (between events ev[2] and ev[3]): combination
@@ -915,6 +935,7 @@ rafeast_status solve_finish(rafeast_plan_s* P, SolveRun& S, rafeast_result* res)
   res->cocg_max = S.cocg_max;
   res->refinements = stats[0];
   res->max_resid = S.maxres;
+  res->tol_solve_last = P->tau;
   for (int i = 0; i < RAFEAST_NPHASE; ++i) res->t_ms[i] = S.t_ph[i];
   if (stats[1] > 0 && status != RAFEAST_OK)
     P->err = std::to_string(stats[1]) + " COCG systems broke down";
@@ -1719,6 +1740,7 @@ rafeast_status batch_resident_solves(rafeast_batch_s* B, const std::vector<char>
     const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
     B->h_graphs[k] = resident_graph(P, P->d_zw, P->m0, residual_form ? P->d_R : P->d_Q, P->ld,
                                     P->d_D, P->nc * P->m0, P->d_iters, nullptr, B->wtab[g]);
+    B->h_graphs[k].tol = P->tau;  // each member's own Phase-2 tolerance
     const double width = std::max(P->sig_hi - P->sig_lo, 1e-300);
     for (int j = 0; j < P->nc; ++j) {
       const double im = std::max(std::fabs(P->zw[2 * j + 1]), 1e-300);

@@ -44,7 +44,7 @@ class Params(C.Structure):
                 ("tol_eig", C.c_double), ("tol_solve", C.c_double), ("max_iter", C.c_int32),
                 ("max_cocg", C.c_int32), ("precision", C.c_int32), ("ws_op", C.c_int32),
                 ("rhs_form", C.c_int32), ("engine", C.c_int32), ("seed", C.c_uint64),
-                ("hip_stream", C.c_void_p)]
+                ("hip_stream", C.c_void_p), ("tol_solve_relaxed", C.c_double)]
 
 
 class WsInfo(C.Structure):
@@ -56,7 +56,8 @@ class Result(C.Structure):
     _fields_ = [("flags", C.c_int32), ("lam", C.c_void_p), ("resid", C.c_void_p),
                 ("X", C.c_void_p), ("M", C.c_int32), ("iters", C.c_int32),
                 ("cocg_iters", C.c_int64), ("cocg_max", C.c_int32), ("refinements", C.c_int32),
-                ("max_resid", C.c_double), ("t_ms", C.c_double * NPHASE)]
+                ("max_resid", C.c_double), ("t_ms", C.c_double * NPHASE),
+                ("tol_solve_last", C.c_double)]
 
 
 _lib = None
@@ -209,7 +210,7 @@ def _csr_struct(csr):
 
 
 def _params(lmin, lmax, m0, nc, q, p, tol_eig, tol_solve, max_iter, max_cocg, precision,
-            ws_op, rhs_form, engine, seed, stream):
+            ws_op, rhs_form, engine, seed, stream, tol_solve_relaxed=0.0):
     prm = default_params()
     prm.lmin, prm.lmax, prm.m0, prm.nc, prm.q, prm.p = lmin, lmax, m0, nc, q, p
     prm.tol_eig, prm.tol_solve, prm.max_iter, prm.max_cocg = tol_eig, tol_solve, max_iter, max_cocg
@@ -219,6 +220,7 @@ def _params(lmin, lmax, m0, nc, q, p, tol_eig, tol_solve, max_iter, max_cocg, pr
     prm.engine = ENGINE[engine]
     prm.seed = seed
     prm.hip_stream = stream
+    prm.tol_solve_relaxed = tol_solve_relaxed
     return prm
 
 
@@ -233,11 +235,11 @@ class Plan:
 
     def __init__(self, csr, lmin, lmax, m0, nc=8, q=2, p=-1, tol_eig=1e-10, tol_solve=1e-6,
                  max_iter=20, max_cocg=20000, precision="fp32", ws_op="auto",
-                 rhs_form="residual", engine="auto", seed=0, stream=None):
+                 rhs_form="residual", engine="auto", seed=0, stream=None, tol_solve_relaxed=0.0):
         L = lib()
         A, keep = _csr_struct(csr)
         prm = _params(lmin, lmax, m0, nc, q, p, tol_eig, tol_solve, max_iter, max_cocg,
-                      precision, ws_op, rhs_form, engine, seed, stream)
+                      precision, ws_op, rhs_form, engine, seed, stream, tol_solve_relaxed)
         h = C.c_void_p()
         st = L.rafeast_plan(C.byref(A), C.byref(prm), C.byref(h))
         if st != 0:
@@ -415,7 +417,7 @@ class Plan:
         return dict(status=STATUS[st], lam=lam[:M].copy(), resid=res[:M].copy(),
                     X=X[:, :M].copy() if X is not None else None, M=M, iters=r.iters,
                     cocg_iters=r.cocg_iters, cocg_max=r.cocg_max, refinements=r.refinements,
-                    max_resid=r.max_resid,
+                    max_resid=r.max_resid, tol_solve_last=r.tol_solve_last,
                     t_ms={k: r.t_ms[i] for i, k in enumerate(PHASES)})
 
     def solve_device(self, lam, resid, X=None, Q_init=None):
@@ -435,6 +437,7 @@ class Plan:
             self._check(st)
         return dict(status=STATUS[st], M=r.M, iters=r.iters, cocg_iters=r.cocg_iters,
                     cocg_max=r.cocg_max, refinements=r.refinements, max_resid=r.max_resid,
+                    tol_solve_last=r.tol_solve_last,
                     t_ms={k: r.t_ms[i] for i, k in enumerate(PHASES)})
 
     # ------------------------------------------------ step-level (device) ---
@@ -492,7 +495,7 @@ class Plan:
 
 _PLAN_DEFAULTS = dict(nc=8, q=2, p=-1, tol_eig=1e-10, tol_solve=1e-6, max_iter=20,
                       max_cocg=20000, precision="fp32", ws_op="auto", rhs_form="residual",
-                      engine="auto", seed=0)
+                      engine="auto", seed=0, tol_solve_relaxed=0.0)
 
 
 class Batch:
@@ -516,7 +519,7 @@ class Batch:
             prms[g] = _params(pr["lmin"], pr["lmax"], pr["m0"], kw["nc"], kw["q"], kw["p"],
                               kw["tol_eig"], kw["tol_solve"], kw["max_iter"], kw["max_cocg"],
                               kw["precision"], kw["ws_op"], kw["rhs_form"], kw["engine"],
-                              kw["seed"], stream)
+                              kw["seed"], stream, kw["tol_solve_relaxed"])
             self._spec.append((int(pr["csr"].n), pr["m0"], kw["nc"], pr["lmin"], pr["lmax"],
                                kw["precision"], kw["p"]))
         h = C.c_void_p()
@@ -570,7 +573,8 @@ class Batch:
             results.append(dict(status=STATUS[sts[g]], lam=lam[:M].copy(), resid=rs[:M].copy(),
                                 X=X[:, :M].copy() if X is not None else None, M=M,
                                 iters=r.iters, cocg_iters=r.cocg_iters, cocg_max=r.cocg_max,
-                                refinements=r.refinements, max_resid=r.max_resid))
+                                refinements=r.refinements, max_resid=r.max_resid,
+                                tol_solve_last=r.tol_solve_last))
         return results, {k: float(tb[i]) for i, k in enumerate(PHASES)}, STATUS[st]
 
     def close(self):

@@ -46,7 +46,7 @@ def test_every_declared_symbol_is_exported(native):
 def test_params_default_and_status_strings(native):
     p = native.default_params()
     assert (p.nc, p.q, p.p, p.max_iter, p.max_cocg) == (8, 2, -1, 20, 20000)
-    assert p.tol_eig == 1e-10 and p.tol_solve == 1e-6
+    assert p.tol_eig == 1e-10 and p.tol_solve == 1e-6 and p.tol_solve_relaxed == 0.0
     assert p.precision == native.PRECISION["fp32"] and p.ws_op == 0 and p.rhs_form == 0
     L = native.lib()
     for code, name in native.STATUS.items():
@@ -117,6 +117,9 @@ def test_invalid_params_rejected(native):
     assert _plan_status(native, csr, q=-1) == "INVALID_ARG"
     assert _plan_status(native, csr, tol_eig=0.0) == "INVALID_ARG"
     assert _plan_status(native, csr, tol_solve=1.0) == "INVALID_ARG"
+    assert _plan_status(native, csr, tol_solve_relaxed=-1e-3) == "INVALID_ARG"
+    assert _plan_status(native, csr, tol_solve_relaxed=1.0) == "INVALID_ARG"
+    assert _plan_status(native, csr, tol_solve_relaxed=math.nan) == "INVALID_ARG"
 
 
 def test_oversized_subspace_unsupported(native):

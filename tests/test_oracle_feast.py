@@ -276,3 +276,45 @@ def test_spurious_ritz_value_is_excluded(monkeypatch):
     np.testing.assert_allclose(out["lam"], inside, atol=1e-12)
     sel = (out["theta_all"] >= -1) & (out["theta_all"] <= 1) & (out["mu_all"] >= F.SPURIOUS_GAIN)
     np.testing.assert_allclose(out["mu_all"][sel], np.abs(filter_value(inside, z, w)), rtol=1e-6)
+
+
+class _RelativeErrorSolver:
+    """Exact shifted solves plus a random error of relative size tau in every
+    column: a stand-in for an iterative solver stopped at tolerance tau."""
+
+    def __init__(self, A, z, tau, seed):
+        self.exact = F.ShiftedSolver(A, z)
+        self.tau = tau
+        self.rng = np.random.default_rng(seed)
+
+    def solve(self, j, B):
+        X = self.exact.solve(j, B)
+        E = self.rng.standard_normal(X.shape) + 1j * self.rng.standard_normal(X.shape)
+        E *= self.tau * np.linalg.norm(X, axis=0) / np.linalg.norm(E, axis=0)
+        return X + E
+
+
+@pytest.mark.parametrize("tau", [1e-2, 1e-4])
+def test_relaxed_solves_residual_form(tau):
+    # Phase 2 with relaxed solves (Section 3.3, k_inexact; Theorem 2): in the
+    # residual-correction form the error a solve of relative accuracy tau
+    # puts into the filtered block is tau times the Ritz residual, so
+    # eps^(m) shrinks with e_m and the iteration still reaches 1e-10; with
+    # the solves taken against Q the same tau leaves a floor near tau.
+    dims, shift = (40, 40), 0.01
+    A = grid_laplacian(dims, shift).to_scipy()
+    lmin, lmax = CFG1_WIN
+    vals, _ = window_basis(dims, shift, lmin, lmax)
+    z, _ = half_circle(lmin, lmax, 4)
+    om = gaussian(1600, 40, 0)
+    exact = F.ra_feast(A, lmin, lmax, 30, 4, om, q=2)
+    got = F.ra_feast(A, lmin, lmax, 30, 4, om, q=2, solver=_RelativeErrorSolver(A, z, tau, 3))
+    assert exact["status"] == "ok" and got["status"] == "ok"
+    assert got["M"] == len(vals)
+    np.testing.assert_allclose(got["lam"], vals, rtol=0, atol=1e-10 * lmax)
+    assert got["iters"] <= exact["iters"] + 1
+    _check_pairs(got, A, lmin, lmax, 1e-10)
+    lit = F.ra_feast(A, lmin, lmax, 30, 4, om, q=2, max_iter=12, form="literal",
+                     solver=_RelativeErrorSolver(A, z, tau, 3))
+    assert lit["status"] == "no_convergence"
+    assert lit["res_all"][: len(vals)].max() > 1e-3 * tau
