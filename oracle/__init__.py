@@ -19,4 +19,6 @@ subspace  Canonical angles / sin-Theta between subspaces.
 spectrum  Gershgorin bounds and reference spectra for window fixtures.
 cocg      Plain COCG for complex-symmetric systems.
 mlp       Forward/backward of the small preconditioner MLP and its loss.
+stats     Sample covariance, its spectrum through X X^T, the variance-explained
+          rule and top windows (Section 4).
 """

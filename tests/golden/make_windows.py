@@ -2,7 +2,7 @@
 
 Calls only oracle/ (spectra) and workloads/ (the seeded matrices).  Run from
 the repository root:  python tests/golden/make_windows.py [entry ...]
-(entries: knn8000, batch32, learned, rgg; default all; others are kept).
+(entries: knn8000, batch32, learned, rgg, stats; default all; others are kept).
 """
 
 import json
@@ -15,6 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle.spectrum import bottom_eigvalsh  # noqa: E402
+from oracle.stats import (covariance_spectrum, dense_spectrum, top_window,  # noqa: E402
+                          variance_count)
 from workloads import knn_laplacian, rgg_laplacian  # noqa: E402
 from workloads.graphs import batch_graph_specs  # noqa: E402
 
@@ -94,7 +96,37 @@ def rgg():
     return out
 
 
-ENTRIES = dict(knn8000=knn8000, batch32=batch32, learned=learned, rgg=rgg)
+def stats():
+    # Section 4 workloads: top windows chosen by the 95%-variance rule, from
+    # the midpoint of the gap below lambda_k to 1.05 lambda_1; m0 = 2k.
+    # Sample covariance of spiked data (spectrum through X X^T) and Gaussian
+    # kernel matrices (dense spectrum).
+    from workloads.stats import rbf_kernel, spiked_data
+
+    out = {}
+    for name, rows, p, nc in (("cov_small", 200, 2400, 8), ("cov_bench", 1024, 65536, 8)):
+        X = spiked_data(rows, p, seed=1)
+        ev = covariance_spectrum(X)
+        tr = float((X * X).sum() / (rows - 1))
+        k = variance_count(ev, tr)
+        lo, hi = top_window(ev, k, 1.05 * ev[0])
+        out[name] = dict(recipe=f"spiked_data({rows}, {p}, seed=1), scale 1/(rows-1)",
+                         kind="covariance", rows=rows, p=p, count=k, lmin=float(lo),
+                         lmax=float(hi), m0=2 * k, nc=nc, trace=tr,
+                         eigenvalues=[float(v) for v in ev[: 2 * k + 2]])
+    for name, n, nc in (("kpca_small", 1200, 16), ("kpca_bench", 8192, 16)):
+        K = rbf_kernel(n, bandwidth=0.4, seed=2)
+        ev = dense_spectrum(K)
+        tr = float(np.trace(K))
+        k = variance_count(ev, tr)
+        lo, hi = top_window(ev, k, 1.05 * ev[0])
+        out[name] = dict(recipe=f"rbf_kernel({n}, bandwidth=0.4, seed=2)", kind="kernel", n=n,
+                         count=k, lmin=float(lo), lmax=float(hi), m0=2 * k, nc=nc, trace=tr,
+                         eigenvalues=[float(v) for v in ev[: 2 * k + 2]])
+    return out
+
+
+ENTRIES = dict(knn8000=knn8000, batch32=batch32, learned=learned, rgg=rgg, stats=stats)
 
 
 def main(names):
