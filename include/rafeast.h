@@ -176,6 +176,34 @@ void rafeast_params_default(rafeast_params* p);
  * (rafeast_last_error(NULL) holds the text). */
 rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm, rafeast_plan_t* out);
 
+/* Plans for the statistical applications of Section 4, whose operators are
+ * dense: the same Phase 1 / Phase 2 calls (rafeast_warmstart, rafeast_solve,
+ * rafeast_destroy, ...) then run with A applied as a matrix product (two for
+ * the covariance form) instead of a sparse one, on the streaming COCG engine
+ * (prm->engine AUTO or STREAM; RESIDENT is UNSUPPORTED).  Top windows suit
+ * the literal warmstart operator (Assumption 1.3); ws_op AUTO picks it when
+ * lmax reaches the upper spectral bound.  The learned-preconditioner calls and
+ * the batching form take CSR plans only (UNSUPPORTED otherwise).
+ *
+ * rafeast_plan_dense: A = K, the kernel matrix of kernel PCA (eq.
+ * kernel-eig).  K: host, n x n, column-major with leading dimension ldk >= n,
+ * symmetric to 1e-14 relative (NOT_SYMMETRIC otherwise) and finite (BAD_CSR
+ * otherwise, the status of malformed input); 1 <= n < 2^31.  The plan copies
+ * K to the device (FP64, plus an FP32 copy for the FP32 engine).  Spectral
+ * bounds: Gershgorin discs of K.  rafeast_plan_info reports nnz = n^2. */
+rafeast_status rafeast_plan_dense(int64_t n, const double* K, int64_t ldk,
+                                  const rafeast_params* prm, rafeast_plan_t* out);
+
+/* rafeast_plan_gram: A = scale X^T X, the sample covariance of eq.
+ * sample-cov with scale = 1/(rows - 1) (any scale > 0 is accepted).  X: host,
+ * rows x n data matrix (rows samples of n features), column-major with
+ * leading dimension ldx >= rows, finite; A (order n) is never formed: each
+ * application is X^T (X V).  Spectral bounds: [0, scale ||X||_F^2] (A is
+ * positive semidefinite and its largest eigenvalue is at most its trace).
+ * rafeast_plan_info reports nnz = rows * n. */
+rafeast_status rafeast_plan_gram(int64_t rows, int64_t n, const double* X, int64_t ldx,
+                                 double scale, const rafeast_params* prm, rafeast_plan_t* out);
+
 /* Phase 1 of Algorithm 2.  omega: nullable host array, column-major
  * n x (m0+p), the Gaussian sketch; NULL draws it on the device from
  * Philox4x32-10 keyed by prm.seed (rafeast_gaussian).  The op (chosen by

@@ -548,6 +548,104 @@ __global__ __launch_bounds__(kST) void k_s_resid64(
   put_partials<CPL, 3>(acc, part, Bp, c0, sh);
 }
 
+// Dense operator, K2 after the product: w holds A p for the group's columns
+// (a GEMM wrote it); w = z p - A p for iterating columns, 0 for frozen ones,
+// and the partials of mu = p^T w, as k_s_spmm.
+template <typename T, int CPL>
+__global__ __launch_bounds__(kST) void k_s_shiftw(int n, int Bp, StreamGroups grp,
+                                                  const double* __restrict__ zc,
+                                                  const int* __restrict__ state,
+                                                  const cpx<T>* __restrict__ pa,
+                                                  const cpx<T>* __restrict__ pb,
+                                                  cpx<T>* __restrict__ w,
+                                                  double* __restrict__ part) {
+  extern __shared__ double sh[];
+  const int c0 = grp.g[blockIdx.y] * 64 * CPL;
+  const cpx<T>* __restrict__ p = grp.par[blockIdx.y] ? pb : pa;
+  const int cl = c0 + (threadIdx.x & 63) * CPL;
+  T zre[CPL], zim[CPL];
+  bool live[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    zre[q] = T(zc[2 * (cl + q)]);
+    zim[q] = T(zc[2 * (cl + q) + 1]);
+    live[q] = state[cl + q] == 1;
+  }
+  double acc[CPL][2];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q][0] = acc[q][1] = 0.0;
+  const WaveRows wr = wave_rows(n);
+  for (int k = 0; k < wr.count; ++k) {
+    const size_t ro = (size_t)(wr.first + wr.stride * k) * Bp + cl;
+    const Chunk<T, CPL> p0 = ld<T, CPL>(p + ro);
+    Chunk<T, CPL> ww = ld<T, CPL>(w + ro);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      if (live[q]) {
+        const T ar = ww.v[q].re, ai = ww.v[q].im;
+        ww.v[q].re = zre[q] * p0.v[q].re - zim[q] * p0.v[q].im - ar;
+        ww.v[q].im = zre[q] * p0.v[q].im + zim[q] * p0.v[q].re - ai;
+      } else {
+        ww.v[q] = cpx<T>{T(0), T(0)};
+      }
+      const double pr = p0.v[q].re, pi = p0.v[q].im, wr_ = ww.v[q].re, wi = ww.v[q].im;
+      acc[q][0] += pr * wr_ - pi * wi;
+      acc[q][1] += pr * wi + pi * wr_;
+    }
+    st<T, CPL>(w + ro, ww);
+  }
+  put_partials<CPL, 2>(acc, part, Bp, c0, sh);
+}
+
+// Dense operator, check step 2 after the product: ax holds A x_hi (FP64,
+// from a GEMM); the rest as k_s_resid64.
+template <typename T, int CPL>
+__global__ __launch_bounds__(kST) void k_s_resid64d(
+    int n, int Bp, StreamGroups grp, const double* __restrict__ zc,
+    const int* __restrict__ state, const double* __restrict__ B, int ldb, int kcols,
+    const double* __restrict__ scale, const cpx<double>* __restrict__ xh,
+    const cpx<double>* __restrict__ ax, cpx<T>* __restrict__ r, cpx<T>* __restrict__ pa,
+    cpx<T>* __restrict__ pb, double* __restrict__ part) {
+  extern __shared__ double sh[];
+  const int c0 = grp.g[blockIdx.y] * 64 * CPL;
+  cpx<T>* __restrict__ p = grp.par[blockIdx.y] ? pb : pa;
+  const int cl = c0 + (threadIdx.x & 63) * CPL;
+  double zre[CPL], zim[CPL], scl[CPL];
+  bool on[CPL], rst[CPL];
+  int ci[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    zre[q] = zc[2 * (cl + q)];
+    zim[q] = zc[2 * (cl + q) + 1];
+    on[q] = waiting(state[cl + q]);
+    rst[q] = state[cl + q] == 3;
+    ci[q] = (cl + q) % kcols;
+    scl[q] = scale[cl + q];
+  }
+  double acc[CPL][3];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+  const WaveRows wr = wave_rows(n);
+  for (int k = 0; k < wr.count; ++k) {
+    const int row = wr.first + k * wr.stride;
+    const size_t ro = (size_t)row * Bp + cl;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      if (!on[q]) continue;
+      const cpx<double> xr = xh[ro + q], a = ax[ro + q];
+      const double b = scl[q] != 0.0 ? B[(size_t)row * ldb + ci[q]] * scl[q] : 0.0;
+      const double sr = b - (zre[q] * xr.re - zim[q] * xr.im - a.re);
+      const double si = -(zre[q] * xr.im + zim[q] * xr.re - a.im);
+      r[ro + q] = cpx<T>{T(sr), T(si)};
+      if (rst[q]) p[ro + q] = cpx<T>{T(sr), T(si)};
+      acc[q][0] += sr * sr - si * si;
+      acc[q][1] += 2.0 * sr * si;
+      acc[q][2] += sr * sr + si * si;
+    }
+  }
+  put_partials<CPL, 3>(acc, part, Bp, c0, sh);
+}
+
 // Check, step 3: accept (true residual <= tol), give up (update, iteration
 // or breakdown budget spent), or continue: a reliable update keeps p and
 // takes beta = s^T s / rho_prev; a restart takes beta = 0, so the next p is
@@ -793,6 +891,40 @@ static hipError_t run_stream_t(hipStream_t stm, const StreamMatrix& A, const Str
     e = hipGetLastError();                \
     if (e != hipSuccess) return e;        \
   } while (0)
+  // Dense operator: the products over runs of consecutive groups that share
+  // a p buffer, as real row-major blocks (a complex column is two real ones).
+  auto dense_product = [&](const StreamGroups& grp) -> hipError_t {
+    for (int a = 0; a < grp.count;) {
+      int b = a + 1;
+      while (b < grp.count && grp.g[b] == grp.g[b - 1] + 1 && grp.par[b] == grp.par[a]) ++b;
+      const size_t c0 = (size_t)grp.g[a] * gw;
+      const int kr = 2 * gw * (b - a);
+      const cpx<T>* p = grp.par[a] ? Pb : Pa;
+      hipError_t e2;
+      if constexpr (sizeof(T) == 4)
+        e2 = dense_apply_f32(*A.dense, stm, kr, (const float*)(p + c0), 2 * Bp,
+                             (float*)(Wv + c0), 2 * Bp);
+      else
+        e2 = dense_apply_f64(*A.dense, stm, kr, (const double*)(p + c0), 2 * Bp,
+                             (double*)(Wv + c0), 2 * Bp, 1.0, 0.0);
+      if (e2 != hipSuccess) return e2;
+      a = b;
+    }
+    return hipSuccess;
+  };
+  auto dense_check_product = [&](const StreamGroups& grp) -> hipError_t {
+    for (int a = 0; a < grp.count;) {
+      int b = a + 1;
+      while (b < grp.count && grp.g[b] == grp.g[b - 1] + 1) ++b;
+      const size_t c0 = (size_t)grp.g[a] * gw;
+      const hipError_t e2 =
+          dense_apply_f64(*A.dense, stm, 2 * gw * (b - a), (const double*)(XH + c0), 2 * Bp,
+                          (double*)((cpx<double>*)W.axh + c0), 2 * Bp, 1.0, 0.0);
+      if (e2 != hipSuccess) return e2;
+      a = b;
+    }
+    return hipSuccess;
+  };
   const dim3 gall(nb, ng);
   SLAUNCH(k_s_bnorm<CPL>, gall, blk, shm(1), stm, n, Bp, L.B, L.ldb, L.k, L.ncols, W.part);
   SLAUNCH(k_s_fin_bnorm, fgrid, fblk, 0, stm, Bp, nb, W.part, L.ncols, W.scale, W.cols, L.tol,
@@ -839,8 +971,15 @@ static hipError_t run_stream_t(hipStream_t stm, const StreamMatrix& A, const Str
           live.par[i] ^= 1;
           parity[live.g[i]] ^= 1;
         }
-        SLAUNCH((k_s_spmm<T, CPL>), gl, blk, shm(2), stm, n, A.rowptr, A.col, val, Bp, live, W.zc,
-                W.cols.state, Pa, Pb, Wv, W.part);
+        if (A.dense) {
+          e = dense_product(live);
+          if (e != hipSuccess) return e;
+          SLAUNCH((k_s_shiftw<T, CPL>), gl, blk, shm(2), stm, n, Bp, live, W.zc, W.cols.state, Pa,
+                  Pb, Wv, W.part);
+        } else {
+          SLAUNCH((k_s_spmm<T, CPL>), gl, blk, shm(2), stm, n, A.rowptr, A.col, val, Bp, live,
+                  W.zc, W.cols.state, Pa, Pb, Wv, W.part);
+        }
         SLAUNCH(k_s_fin_mu, fgrid, fblk, 0, stm, Bp, nb, W.part, W.cols);
         SLAUNCH((k_s_update<T, CPL>), gl, blk, shm(3), stm, n, Bp, live, W.cols.alpha, X, R, Pa,
                 Pb, Wv, W.part);
@@ -853,8 +992,15 @@ static hipError_t run_stream_t(hipStream_t stm, const StreamMatrix& A, const Str
     if (wait.count > 0) {
       const dim3 gw2(nb, wait.count);
       SLAUNCH((k_s_xhi<T, CPL>), gw2, blk, 0, stm, n, Bp, wait, W.cols.state, X, XH);
-      SLAUNCH((k_s_resid64<T, CPL>), gw2, blk, shm(3), stm, n, A.rowptr, A.col, A.val64, Bp, wait,
-              W.zc, W.cols.state, L.B, L.ldb, L.k, W.scale, A.perm, XH, R, Pa, Pb, W.part);
+      if (A.dense) {
+        e = dense_check_product(wait);
+        if (e != hipSuccess) return e;
+        SLAUNCH((k_s_resid64d<T, CPL>), gw2, blk, shm(3), stm, n, Bp, wait, W.zc, W.cols.state,
+                L.B, L.ldb, L.k, W.scale, XH, (const cpx<double>*)W.axh, R, Pa, Pb, W.part);
+      } else {
+        SLAUNCH((k_s_resid64<T, CPL>), gw2, blk, shm(3), stm, n, A.rowptr, A.col, A.val64, Bp,
+                wait, W.zc, W.cols.state, L.B, L.ldb, L.k, W.scale, A.perm, XH, R, Pa, Pb, W.part);
+      }
       SLAUNCH(k_s_fin_verify, fgrid, fblk, 0, stm, Bp, nb, W.part, W.cols, L.tol, delta,
               L.maxit, L.max_updates);
       e = census();

@@ -184,8 +184,37 @@ struct StreamGroups {
   int g[kStreamMaxGroups];    // group of blockIdx.y
   int par[kStreamMaxGroups];  // which of the two p buffers holds the group's current p
 };
+// Dense symmetric operator of the statistical workloads: A = K (kind 1,
+// n x n) or A = scale X^T X (kind 2, X rows x n).  Device matrices are
+// column-major (leading dimension n for K, rows for X); the products run on
+// rocBLAS (MFMA GEMMs), the handle bound to the caller's stream per call.
+struct DenseOp {
+  int kind = 0;
+  int64_t n = 0, rows = 0;
+  double scale = 1.0;
+  const double* a64 = nullptr;     // K or X, FP64
+  const float* a32 = nullptr;      // the same, FP32
+  double* t64 = nullptr;           // kind 2: rows x tcols scratch for X V
+  float* t32 = nullptr;
+  int64_t tcols = 0;
+  void* blas = nullptr;            // rocblas_handle
+};
+// Y = alpha A X + beta Y for row-major n x k blocks X (ldx) and Y (ldy),
+// FP64; k <= tcols for kind 2.
+hipError_t dense_apply_f64(const DenseOp& A, hipStream_t st, int k, const double* X, int ldx,
+                           double* Y, int ldy, double alpha, double beta);
+// Y = A X in FP32, same layout.
+hipError_t dense_apply_f32(const DenseOp& A, hipStream_t st, int k, const float* X, int ldx,
+                           float* Y, int ldy);
+// y += a x over count contiguous doubles.
+hipError_t dense_axpy(const DenseOp& A, hipStream_t st, int64_t count, double a, const double* x,
+                      double* y);
+hipError_t dense_create_handle(void** blas);
+void dense_destroy_handle(void* blas);
+
 struct StreamMatrix {
   int n = 0;
+  const DenseOp* dense = nullptr;  // set: A is this dense operator (no CSR; perm identity)
   const int* rowptr = nullptr;     // CSR in engine row order, columns renumbered
   const int* col = nullptr;
   const float* val32 = nullptr;
@@ -218,6 +247,7 @@ struct StreamWork {
   void* p1 = nullptr;
   void* w = nullptr;
   void* xh = nullptr;              // n x Bp complex FP64
+  void* axh = nullptr;             // dense operator only: n x Bp complex FP64, A x_hi
   double* part = nullptr;          // stream_partial_doubles(n, Bp, num_cu)
   double* zc = nullptr;            // [2 Bp] shift of each column (padding: any finite value)
   double* scale = nullptr;         // [Bp]

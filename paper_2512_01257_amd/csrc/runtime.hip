@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <thread>
 #include <vector>
@@ -100,6 +101,11 @@ struct rafeast_plan_s {
   int* d_sperm = nullptr;
   StreamMatrix smat;
   StreamWork swork;               // sized for the nc * m0 systems of a solve
+  DenseOp dop;                    // dense operator (kind 0: A is the CSR matrix)
+  double* d_k64 = nullptr;        // its device matrices and scratch
+  float* d_k32 = nullptr;
+  double* d_t64 = nullptr;
+  float* d_t32 = nullptr;
   std::vector<void*> sbufs;       // device buffers behind swork
   int nitems = 0;
   bool have_start = false;
@@ -293,7 +299,7 @@ rafeast_status validate_csr(const rafeast_csr* A, int64_t& nnz, double& anorm, d
     return RAFEAST_INVALID_ARG;
   }
   const int64_t n = A->n;
-  const int base = A->index_base;
+    const int base = A->index_base;
   if (A->rowptr[0] != base) {
     msg = "rowptr[0] != index_base";
     return RAFEAST_BAD_CSR;
@@ -382,15 +388,103 @@ void free_plan(rafeast_plan_s* P) {
                   P->d_G,      P->d_M,    P->d_S,     P->d_Ssel,  P->d_jw,   P->d_theta,
                   P->d_res,    P->d_qn,   P->d_gamma, P->d_info,  P->d_zw,   P->d_part,
                   P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
-                  P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm};
+                  P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm,
+                  P->d_k64, P->d_k32, P->d_t64, P->d_t32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : P->sbufs)
     if (p) (void)hipFree(p);
   for (auto& e : P->ev)
     if (e) (void)hipEventDestroy(e);
+  dense_destroy_handle(P->dop.blas);
   if (P->own_stream && P->st) (void)hipStreamDestroy(P->st);
   delete P;
+}
+
+// A dense operator handed to rafeast_plan_dense (kind 1: K, n x n) or
+// rafeast_plan_gram (kind 2: scale X^T X, X rows x n), host, column-major.
+struct DenseSpec {
+  int kind = 0;
+  int64_t n = 0, rows = 0, ld = 0;
+  const double* M = nullptr;
+  double scale = 1.0;
+};
+
+// Checks a dense operator and returns nnz, ||A||_inf (kind 2: the trace
+// bound scale ||X||_F^2) and the spectral bounds [lo, hi].
+rafeast_status validate_dense(const DenseSpec& D, int64_t& nnz, double& anorm, double& lo,
+                              double& hi, std::string& msg) {
+  const int64_t lim = (int64_t)1 << 31;
+  if (!D.M) {
+    msg = "matrix is NULL";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (D.n < 1 || D.n >= lim) {
+    msg = "need 1 <= n < 2^31";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (D.kind == 1) {
+    const int64_t n = D.n;
+    if (D.ld < n) {
+      msg = "ldk < n";
+      return RAFEAST_INVALID_ARG;
+    }
+    anorm = 0.0;
+    lo = std::numeric_limits<double>::infinity();
+    hi = -lo;
+    for (int64_t i = 0; i < n; ++i) {
+      double rs = 0.0;
+      for (int64_t j = 0; j < n; ++j) {
+        const double v = D.M[i + j * D.ld];
+        if (!std::isfinite(v)) {
+          msg = "K has a non-finite entry";
+          return RAFEAST_BAD_CSR;
+        }
+        rs += std::fabs(v);
+      }
+      const double d = D.M[i + i * D.ld], off = rs - std::fabs(d);
+      lo = std::min(lo, d - off);
+      hi = std::max(hi, d + off);
+      anorm = std::max(anorm, rs);
+    }
+    const double stol = 1e-14 * anorm;
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t i = 0; i < j; ++i)
+        if (std::fabs(D.M[i + j * D.ld] - D.M[j + i * D.ld]) > stol) {
+          msg = "K is not symmetric";
+          return RAFEAST_NOT_SYMMETRIC;
+        }
+    if (!(hi > lo)) hi = lo + std::max(1.0, std::fabs(lo));  // K = c I: any interval holding c
+    nnz = n * n;
+    return RAFEAST_OK;
+  }
+  if (D.kind != 2 || D.rows < 1 || D.rows >= lim || D.ld < D.rows) {
+    msg = "need 1 <= rows < 2^31 and ldx >= rows";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (!(D.scale > 0.0) || !std::isfinite(D.scale)) {
+    msg = "scale must be positive and finite";
+    return RAFEAST_INVALID_ARG;
+  }
+  double fro2 = 0.0;
+  for (int64_t j = 0; j < D.n; ++j)
+    for (int64_t i = 0; i < D.rows; ++i) {
+      const double v = D.M[i + j * D.ld];
+      if (!std::isfinite(v)) {
+        msg = "X has a non-finite entry";
+        return RAFEAST_BAD_CSR;
+      }
+      fro2 += v * v;
+    }
+  if (!(fro2 > 0.0) || !std::isfinite(D.scale * fro2)) {
+    msg = "X must be nonzero with a finite covariance";
+    return RAFEAST_INVALID_ARG;
+  }
+  lo = 0.0;
+  hi = D.scale * fro2;
+  anorm = hi;
+  nnz = D.rows * D.n;
+  return RAFEAST_OK;
 }
 
 // Reverse Cuthill-McKee order of the graph of A (diagonal ignored): per
@@ -499,6 +593,11 @@ rafeast_status alloc_stream_work(rafeast_plan_s* P, int Bp, StreamWork& W,
   RCHK(get(&W.p1, blk * cs, "stream p'"));
   RCHK(get(&W.w, blk * cs, "stream w"));
   RCHK(get(&W.xh, blk * 2 * sizeof(double), "stream x_hi"));
+  if (P->dop.kind != 0) {
+    if (P->dop.kind == 2 && 2 * (int64_t)Bp > P->dop.tcols)
+      return fail(P, RAFEAST_UNSUPPORTED, "more columns than the covariance scratch holds");
+    RCHK(get(&W.axh, blk * 2 * sizeof(double), "stream A x_hi"));
+  }
   RCHK(get((void**)&W.part, stream_partial_doubles((int)n, Bp, P->num_cu) * sizeof(double),
            "stream partials"));
   RCHK(get((void**)&W.zc, 2 * (size_t)Bp * sizeof(double), "stream shifts"));
@@ -540,6 +639,14 @@ std::vector<double> stream_shifts(int nz, const double* z, int k, int Bp) {
 rafeast_status spmm(rafeast_plan_s* P, int k, const double* X, int ldx, double* Y, int ldy,
                     double alpha, double beta, const double* X2 = nullptr, int ldx2 = 0,
                     double gamma = 0.0) {
+  if (P->dop.kind != 0) {
+    HIPCHK(P, dense_apply_f64(P->dop, P->st, k, X, ldx, Y, ldy, alpha, beta));
+    if (X2) {
+      if (ldx2 != k || ldy != k) return fail(P, RAFEAST_UNSUPPORTED, "strided dense update");
+      HIPCHK(P, dense_axpy(P->dop, P->st, P->n * (int64_t)k, gamma, X2, Y));
+    }
+    return RAFEAST_OK;
+  }
   HIPCHK(P, launch_spmm_f64(P->st, (int)P->n, k, P->d_rowptr, P->d_col, P->d_val, X, ldx, Y, ldy,
                             alpha, beta, X2, ldx2, gamma));
   return RAFEAST_OK;
@@ -1068,20 +1175,23 @@ rafeast_status tune_resident(rafeast_plan_s* P) {
   return RAFEAST_OK;
 }
 
-rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
-                            rafeast_plan_t* out) {
+// rafeast_plan, rafeast_plan_dense and rafeast_plan_gram: exactly one of A
+// (CSR) and D (dense operator) is set.
+static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
+                                  const rafeast_params* prm, rafeast_plan_t* out) {
   g_plan_error.clear();
   if (!out) return fail(nullptr, RAFEAST_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (!A || !prm) return fail(nullptr, RAFEAST_INVALID_ARG, "A or prm is NULL");
+  if ((!A && !D) || !prm) return fail(nullptr, RAFEAST_INVALID_ARG, "A or prm is NULL");
   std::string msg;
   int64_t nnz = 0;
   double anorm = 0, lo = 0, hi = 0;
-  rafeast_status s = validate_csr(A, nnz, anorm, lo, hi, msg);
+  rafeast_status s = A ? validate_csr(A, nnz, anorm, lo, hi, msg)
+                       : validate_dense(*D, nnz, anorm, lo, hi, msg);
   if (s != RAFEAST_OK) return fail(nullptr, s, msg);
-  s = validate_params(prm, A->n, msg);
+  const int64_t n = A ? A->n : D->n;
+  s = validate_params(prm, n, msg);
   if (s != RAFEAST_OK) return fail(nullptr, s, msg);
-  const int64_t n = A->n;
   int pov = prm->p;
   if (pov < 0) pov = prm->m0 <= 50 ? 10 : std::min(20, (prm->m0 + 1) / 2);
   int w = (int)std::min<int64_t>((int64_t)prm->m0 + pov, n);
@@ -1090,6 +1200,9 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
                 "m0 + p = " + std::to_string(w) + " exceeds the small-matrix limit 192");
   const bool fp32 = prm->precision == RAFEAST_FP32_REFINED;
   int engine = prm->engine;
+  if (D && engine == RAFEAST_ENGINE_RESIDENT)
+    return fail(nullptr, RAFEAST_UNSUPPORTED, "dense operators run on the streaming engine");
+  if (D) engine = RAFEAST_ENGINE_STREAM;
   if (engine == RAFEAST_ENGINE_RESIDENT && n > cocg_resident_max_n(fp32))
     return fail(nullptr, RAFEAST_UNSUPPORTED,
                 "n too large for the resident COCG engine at this precision");
@@ -1170,9 +1283,53 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
     }
   }
 
+  if (D) {
+    // dense operator: device copies (FP64, FP32) compacted to leading
+    // dimension rows, scratch for the covariance form's X V, the BLAS handle,
+    // and the identity row order of the streaming engine
+    DenseOp& op = P->dop;
+    op.kind = D->kind;
+    op.n = n;
+    op.rows = D->kind == 2 ? D->rows : n;
+    op.scale = D->kind == 2 ? D->scale : 1.0;
+    const size_t cnt = (size_t)op.rows * n;
+    {
+      std::vector<double> h64(cnt);
+      std::vector<float> h32(cnt);
+      for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < op.rows; ++i) {
+          const double v = D->M[i + j * D->ld];
+          h64[(size_t)j * op.rows + i] = v;
+          h32[(size_t)j * op.rows + i] = (float)v;
+        }
+      PRCHK(dalloc(P, &P->d_k64, cnt, "dense operator"));
+      PRCHK(dalloc(P, &P->d_k32, cnt, "dense operator fp32"));
+      PCHK(hipMemcpy(P->d_k64, h64.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+      PCHK(hipMemcpy(P->d_k32, h32.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
+    }
+    op.a64 = P->d_k64;
+    op.a32 = P->d_k32;
+    if (op.kind == 2) {
+      const int Bp = stream_padded_columns(P->m0, P->nc * P->m0, fp32);
+      op.tcols = std::max<int64_t>(2 * (int64_t)Bp, kMaxSmallK);
+      PRCHK(dalloc(P, &P->d_t64, (size_t)op.rows * op.tcols, "covariance scratch"));
+      PRCHK(dalloc(P, &P->d_t32, (size_t)op.rows * op.tcols, "covariance scratch fp32"));
+      op.t64 = P->d_t64;
+      op.t32 = P->d_t32;
+    }
+    PCHK(dense_create_handle(&op.blas));
+    std::vector<int> ident(n);
+    for (int64_t r = 0; r < n; ++r) ident[r] = (int)r;
+    PRCHK(dalloc(P, &P->d_sperm, n, "stream perm"));
+    PCHK(hipMemcpy(P->d_sperm, ident.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    P->smat.n = (int)n;
+    P->smat.dense = &P->dop;
+    P->smat.perm = P->d_sperm;
+    P->engine = engine;
+  }
   // CSR (FP64) and SELL-64 copies of A
-  const int base = A->index_base;
-  {
+  if (A) {
+    const int base = A->index_base;
     std::vector<int> rp(n + 1), cl(nnz);
     for (int64_t i = 0; i <= n; ++i) rp[i] = A->rowptr[i] - base;
     for (int64_t t = 0; t < nnz; ++t) cl[t] = A->colind[t] - base;
@@ -1395,6 +1552,39 @@ rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
   return RAFEAST_OK;
 }
 
+rafeast_status rafeast_plan(const rafeast_csr* A, const rafeast_params* prm,
+                            rafeast_plan_t* out) {
+  if (!A) {
+    g_plan_error = "A or prm is NULL";
+    if (out) *out = nullptr;
+    return RAFEAST_INVALID_ARG;
+  }
+  return plan_create(A, nullptr, prm, out);
+}
+
+rafeast_status rafeast_plan_dense(int64_t n, const double* K, int64_t ldk,
+                                  const rafeast_params* prm, rafeast_plan_t* out) {
+  DenseSpec D;
+  D.kind = 1;
+  D.n = n;
+  D.rows = n;
+  D.ld = ldk;
+  D.M = K;
+  return plan_create(nullptr, &D, prm, out);
+}
+
+rafeast_status rafeast_plan_gram(int64_t rows, int64_t n, const double* X, int64_t ldx,
+                                 double scale, const rafeast_params* prm, rafeast_plan_t* out) {
+  DenseSpec D;
+  D.kind = 2;
+  D.n = n;
+  D.rows = rows;
+  D.ld = ldx;
+  D.M = X;
+  D.scale = scale;
+  return plan_create(nullptr, &D, prm, out);
+}
+
 rafeast_status rafeast_plan_tuning(rafeast_plan_t P, int32_t* chosen, int32_t* count,
                                    int32_t* cand, float* ms, int32_t max) {
   if (!P || !chosen || !count || max < 0 || (max > 0 && (!cand || !ms)))
@@ -1419,7 +1609,7 @@ rafeast_status rafeast_rcm_order(const rafeast_csr* A, int32_t* perm) {
   rafeast_status s = validate_csr(A, nnz, anorm, lo, hi, msg);
   if (s != RAFEAST_OK) return fail(nullptr, s, msg);
   const int64_t n = A->n;
-  const int base = A->index_base;
+    const int base = A->index_base;
   std::vector<int> rp(n + 1), cl(nnz);
   for (int64_t i = 0; i <= n; ++i) rp[i] = A->rowptr[i] - base;
   for (int64_t t = 0; t < nnz; ++t) cl[t] = A->colind[t] - base;
@@ -2048,6 +2238,8 @@ int32_t rafeast_pc_param_count(void) { return mlp_param_count(); }
 rafeast_status rafeast_pc_samples(rafeast_plan_t P, int32_t nz, const double* z, int32_t k,
                                   const double* R, int32_t ldr, double theta_lo, double theta_hi,
                                   double* X, double* G, double* h, double* rr) {
+  if (P && P->dop.kind != 0)
+    return fail(P, RAFEAST_UNSUPPORTED, "the learned preconditioner takes CSR plans");
   if (!P || !z || !R || !X || !G || !h || !rr || nz < 1 || k < 1 || ldr < k)
     return RAFEAST_INVALID_ARG;
   P->err.clear();
@@ -2152,6 +2344,8 @@ rafeast_status rafeast_pc_train(rafeast_plan_t P, int32_t ns, const double* X, c
 rafeast_status rafeast_pc_solve(rafeast_plan_t P, int32_t nz, const double* z, int32_t k,
                                 const double* B, int32_t ldb, const double* coef, void* Xout,
                                 double tol, int32_t* iters, double* resid) {
+  if (P && P->dop.kind != 0)
+    return fail(P, RAFEAST_UNSUPPORTED, "the learned preconditioner takes CSR plans");
   if (!P || !z || !B || !Xout || nz < 1 || k < 1 || ldb < k || !(tol > 0.0) || !(tol < 1.0))
     return RAFEAST_INVALID_ARG;
   P->err.clear();

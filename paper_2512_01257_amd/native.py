@@ -84,6 +84,11 @@ def lib():
     L.rafeast_params_default.restype = None
     L.rafeast_plan.argtypes = [C.POINTER(Csr), C.POINTER(Params), C.POINTER(P)]
     L.rafeast_plan.restype = C.c_int
+    L.rafeast_plan_dense.argtypes = [C.c_int64, dp, C.c_int64, C.POINTER(Params), C.POINTER(P)]
+    L.rafeast_plan_dense.restype = C.c_int
+    L.rafeast_plan_gram.argtypes = [C.c_int64, C.c_int64, dp, C.c_int64, C.c_double,
+                                    C.POINTER(Params), C.POINTER(P)]
+    L.rafeast_plan_gram.restype = C.c_int
     L.rafeast_warmstart.argtypes = [P, dp, dp, C.POINTER(WsInfo)]
     L.rafeast_warmstart.restype = C.c_int
     L.rafeast_solve.argtypes = [P, dp, C.POINTER(Result)]
@@ -245,6 +250,46 @@ class Plan:
         if st != 0:
             raise RafeastError(st, L.rafeast_last_error(None).decode())
         self._setup(h, int(csr.n), m0, nc, lmin, lmax, precision, p, owned=True)
+
+    @classmethod
+    def _from_dense(cls, make, n, lmin, lmax, m0, kw):
+        opts = dict(_PLAN_DEFAULTS)
+        opts.update(kw)
+        stream = opts.pop("stream", None)
+        prm = _params(lmin, lmax, m0, opts["nc"], opts["q"], opts["p"], opts["tol_eig"],
+                      opts["tol_solve"], opts["max_iter"], opts["max_cocg"], opts["precision"],
+                      opts["ws_op"], opts["rhs_form"], opts["engine"], opts["seed"], stream,
+                      opts["tol_solve_relaxed"])
+        h = C.c_void_p()
+        st = make(C.byref(prm), C.byref(h))
+        if st != 0:
+            raise RafeastError(st, lib().rafeast_last_error(None).decode())
+        self = cls.__new__(cls)
+        self._setup(h, int(n), m0, opts["nc"], lmin, lmax, opts["precision"], opts["p"],
+                    owned=True)
+        return self
+
+    @classmethod
+    def from_dense(cls, K, lmin, lmax, m0, **kw):
+        """rafeast_plan_dense: A = K, a dense symmetric matrix (kernel PCA).
+        Keyword arguments as Plan()."""
+        K = np.asfortranarray(K, dtype=np.float64)
+        n = K.shape[0]
+        if K.shape != (n, n):
+            raise ValueError("K must be square")
+        return cls._from_dense(lambda prm, h: lib().rafeast_plan_dense(n, _dptr(K), n, prm, h),
+                               n, lmin, lmax, m0, kw)
+
+    @classmethod
+    def from_covariance(cls, X, lmin, lmax, m0, scale=None, **kw):
+        """rafeast_plan_gram: A = scale X^T X (default scale 1/(rows - 1), the
+        sample covariance of the rows of X).  Keyword arguments as Plan()."""
+        X = np.asfortranarray(X, dtype=np.float64)
+        rows, n = X.shape
+        sc = 1.0 / (rows - 1) if scale is None else float(scale)
+        return cls._from_dense(
+            lambda prm, h: lib().rafeast_plan_gram(rows, n, _dptr(X), rows, sc, prm, h),
+            n, lmin, lmax, m0, kw)
 
     def _setup(self, h, n, m0, nc, lmin, lmax, precision, p, owned):
         self._h = h

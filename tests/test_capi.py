@@ -122,6 +122,48 @@ def test_invalid_params_rejected(native):
     assert _plan_status(native, csr, tol_solve_relaxed=math.nan) == "INVALID_ARG"
 
 
+def test_dense_plans_validated_before_the_device(native):
+    import ctypes as C
+
+    L = native.lib()
+    prm = native.default_params()
+    prm.lmin, prm.lmax, prm.m0 = 0.5, 2.0, 2
+    h = C.c_void_p()
+
+    def dense(K, ld=None, **over):
+        for k, v in over.items():
+            setattr(prm, k, v)
+        K = np.asfortranarray(K, dtype=np.float64)
+        st = L.rafeast_plan_dense(K.shape[0], native._dptr(K), ld or K.shape[0], C.byref(prm),
+                                  C.byref(h))
+        prm.engine = 0
+        return native.STATUS[st]
+
+    def gram(X, scale=0.5, ld=None):
+        X = np.asfortranarray(X, dtype=np.float64)
+        st = L.rafeast_plan_gram(X.shape[0], X.shape[1], native._dptr(X), ld or X.shape[0],
+                                 scale, C.byref(prm), C.byref(h))
+        return native.STATUS[st]
+
+    K = np.eye(5)
+    K[0, 3] = 1e-3
+    assert dense(K) == "NOT_SYMMETRIC"
+    K[3, 0] = 1e-3
+    assert dense(K, ld=4) == "INVALID_ARG"
+    assert dense(K, engine=native.ENGINE["resident"]) == "UNSUPPORTED"
+    K[1, 1] = np.inf
+    assert dense(K) == "BAD_CSR"
+    assert L.rafeast_plan_dense(5, None, 5, C.byref(prm), C.byref(h)) == 1
+    X = np.arange(12.0).reshape(3, 4)
+    assert gram(np.zeros((3, 4))) == "INVALID_ARG"
+    assert gram(X, scale=0.0) == "INVALID_ARG"
+    assert gram(X, ld=2) == "INVALID_ARG"
+    X[1, 2] = np.nan
+    assert gram(X) == "BAD_CSR"
+    if not _has_gpu():
+        assert gram(np.arange(12.0).reshape(3, 4)) == "DEVICE"
+
+
 def test_oversized_subspace_unsupported(native):
     csr = grid_laplacian((20, 20), 0.01)
     assert _plan_status(native, csr, m0=180, p=20) == "UNSUPPORTED"
