@@ -432,7 +432,7 @@ def main_stats(args):
         gen_ms = (time.perf_counter() - t0) * 1e3
         t0 = time.perf_counter()
         plan = make(data, fx["lmin"], fx["lmax"], fx["m0"], nc=fx["nc"], q=2, ws_op="literal",
-                    tol_solve_relaxed=rel)
+                    tol_solve_relaxed=rel, precision=args.precision)
         plan_ms = (time.perf_counter() - t0) * 1e3
         del data
         lam = torch.zeros(fx["m0"], dtype=torch.float64, device="cuda")
@@ -470,7 +470,8 @@ def main_stats(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
         "config": {"workload": "sample covariance of a 1024 x 65536 spiked data matrix and an "
                                "8192 x 8192 Gaussian kernel matrix; top windows by the 95% "
-                               "variance rule; COCG tol 1e-6", "tol_solve_relaxed": rel},
+                               "variance rule; COCG tol 1e-6", "tol_solve_relaxed": rel,
+                   "precision": args.precision},
         "table": rows,
     }
     print(json.dumps(line), flush=True)
@@ -579,6 +580,8 @@ def main():
                          "(covariance and kernel PCA top windows)")
     ap.add_argument("--relaxed", type=float, default=1e-2,
                     help="starting COCG tolerance of the relaxed Phase-2 figures (0: skip)")
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
+                    help="stats: COCG precision (complex FP32 with FP64 reliable updates, or FP64)")
     ap.add_argument("--relaxed-phase2", action="store_true",
                     help="grid64, batch32, rgg (RA configurations only): relaxed Phase-2 solves "
                          "starting at --relaxed")

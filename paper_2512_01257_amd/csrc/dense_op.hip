@@ -25,6 +25,37 @@ hipError_t to_hip(rocblas_status s) {
 
 bool fits_int(int64_t v) { return v >= 0 && v < ((int64_t)1 << 31); }
 
+// T^T (k x rows, leading dimension k) = X^T Xd^T for the covariance form.
+// Its output is small and its inner dimension n long, so a single GEMM
+// fills only a few tiles of the chip: with split > 1 the inner dimension is
+// cut into split equal chunks (and a remainder), their products formed as
+// one strided-batched GEMM into the partial slabs after T, and summed by a
+// GEMV with a vector of ones.
+template <typename R, typename Gemm, typename Batched, typename Gemv>
+rocblas_status xvt(const DenseOp& A, rocblas_handle h, int k, const R* X, int ldx, const R* Xd,
+                   R* T, const R* ones, Gemm gemm, Batched batched, Gemv gemv) {
+  const int n = (int)A.n, rows = (int)A.rows;
+  const R one = 1, zero = 0;
+  if (A.split <= 1 || (int64_t)k * rows >= ((int64_t)1 << 31))
+    return gemm(h, rocblas_operation_none, rocblas_operation_transpose, k, rows, n, &one, X, ldx,
+                Xd, rows, &zero, T, k);
+  const int S = A.split, c = n / S, rem = n - S * c;
+  const size_t slab = (size_t)k * rows;
+  R* part = T + (size_t)rows * A.tcols;
+  rocblas_status s = batched(h, rocblas_operation_none, rocblas_operation_transpose, k, rows, c,
+                             &one, X, ldx, (rocblas_stride)c * ldx, Xd, rows,
+                             (rocblas_stride)c * rows, &zero, part, k, (rocblas_stride)slab, S);
+  if (s != rocblas_status_success) return s;
+  if (rem > 0) {
+    s = gemm(h, rocblas_operation_none, rocblas_operation_transpose, k, rows, rem, &one,
+             X + (size_t)S * c * ldx, ldx, Xd + (size_t)S * c * rows, rows, &zero,
+             part + (size_t)S * slab, k);
+    if (s != rocblas_status_success) return s;
+  }
+  return gemv(h, rocblas_operation_none, (int)slab, S + (rem > 0 ? 1 : 0), &one, part, (int)slab,
+              ones, 1, &zero, T, 1);
+}
+
 }  // namespace
 
 hipError_t dense_create_handle(void** blas) {
@@ -55,10 +86,10 @@ hipError_t dense_apply_f64(const DenseOp& A, hipStream_t st, int k, const double
   }
   if (A.kind != 2 || k > A.tcols) return hipErrorInvalidValue;
   const int rows = (int)A.rows;
-  const double one = 1.0, zero = 0.0, as = alpha * A.scale;
+  const double as = alpha * A.scale;
   // T^T (k x rows) = X^T Xd^T, then Y^T = alpha scale T^T Xd + beta Y^T
-  s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, k, rows, n, &one, X,
-                    ldx, A.a64, rows, &zero, A.t64, k);
+  s = xvt<double>(A, h, k, X, ldx, A.a64, A.t64, A.ones64, rocblas_dgemm,
+                  rocblas_dgemm_strided_batched, rocblas_dgemv);
   if (s != rocblas_status_success) return to_hip(s);
   s = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, k, n, rows, &as, A.t64, k,
                     A.a64, rows, &beta, Y, ldy);
@@ -83,8 +114,8 @@ hipError_t dense_apply_f32(const DenseOp& A, hipStream_t st, int k, const float*
   if (A.kind != 2 || k > A.tcols) return hipErrorInvalidValue;
   const int rows = (int)A.rows;
   const float sc = (float)A.scale;
-  s = rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, k, rows, n, &one, X,
-                    ldx, A.a32, rows, &zero, A.t32, k);
+  s = xvt<float>(A, h, k, X, ldx, A.a32, A.t32, A.ones32, rocblas_sgemm,
+                 rocblas_sgemm_strided_batched, rocblas_sgemv);
   if (s != rocblas_status_success) return to_hip(s);
   s = rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, k, n, rows, &sc, A.t32, k,
                     A.a32, rows, &zero, Y, ldy);

@@ -194,9 +194,12 @@ struct DenseOp {
   double scale = 1.0;
   const double* a64 = nullptr;     // K or X, FP64
   const float* a32 = nullptr;      // the same, FP32
-  double* t64 = nullptr;           // kind 2: rows x tcols scratch for X V
-  float* t32 = nullptr;
+  double* t64 = nullptr;           // kind 2: X V (rows x tcols) and, when split > 1,
+  float* t32 = nullptr;            // split + 1 partial products after it
   int64_t tcols = 0;
+  int split = 1;                   // kind 2: chunks of the inner dimension n of X V
+  const double* ones64 = nullptr;  // [split + 1] ones (the partial sums as a GEMV)
+  const float* ones32 = nullptr;
   void* blas = nullptr;            // rocblas_handle
 };
 // Y = alpha A X + beta Y for row-major n x k blocks X (ldx) and Y (ldy),

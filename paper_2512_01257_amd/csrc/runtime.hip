@@ -106,6 +106,8 @@ struct rafeast_plan_s {
   float* d_k32 = nullptr;
   double* d_t64 = nullptr;
   float* d_t32 = nullptr;
+  double* d_ones64 = nullptr;
+  float* d_ones32 = nullptr;
   std::vector<void*> sbufs;       // device buffers behind swork
   int nitems = 0;
   bool have_start = false;
@@ -389,7 +391,7 @@ void free_plan(rafeast_plan_s* P) {
                   P->d_res,    P->d_qn,   P->d_gamma, P->d_info,  P->d_zw,   P->d_part,
                   P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
                   P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm,
-                  P->d_k64, P->d_k32, P->d_t64, P->d_t32};
+                  P->d_k64, P->d_k32, P->d_t64, P->d_t32, P->d_ones64, P->d_ones32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : P->sbufs)
@@ -1312,10 +1314,26 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     if (op.kind == 2) {
       const int Bp = stream_padded_columns(P->m0, P->nc * P->m0, fp32);
       op.tcols = std::max<int64_t>(2 * (int64_t)Bp, kMaxSmallK);
-      PRCHK(dalloc(P, &P->d_t64, (size_t)op.rows * op.tcols, "covariance scratch"));
-      PRCHK(dalloc(P, &P->d_t32, (size_t)op.rows * op.tcols, "covariance scratch fp32"));
+      // X V has a small output and a long inner dimension: split it in
+      // chunks of at least 1024 (at most 32 chunks) so its GEMM fills the chip
+      op.split = (int)std::min<int64_t>(32, std::max<int64_t>(1, n / 1024));
+      const size_t slabs = op.split > 1 ? (size_t)op.split + 2 : 1;
+      PRCHK(dalloc(P, &P->d_t64, slabs * op.rows * op.tcols, "covariance scratch"));
+      PRCHK(dalloc(P, &P->d_t32, slabs * op.rows * op.tcols, "covariance scratch fp32"));
       op.t64 = P->d_t64;
       op.t32 = P->d_t32;
+      if (op.split > 1) {
+        const std::vector<double> o64(op.split + 1, 1.0);
+        const std::vector<float> o32(op.split + 1, 1.0f);
+        PRCHK(dalloc(P, &P->d_ones64, o64.size(), "ones"));
+        PRCHK(dalloc(P, &P->d_ones32, o32.size(), "ones fp32"));
+        PCHK(hipMemcpy(P->d_ones64, o64.data(), o64.size() * sizeof(double),
+                       hipMemcpyHostToDevice));
+        PCHK(hipMemcpy(P->d_ones32, o32.data(), o32.size() * sizeof(float),
+                       hipMemcpyHostToDevice));
+        op.ones64 = P->d_ones64;
+        op.ones32 = P->d_ones32;
+      }
     }
     PCHK(dense_create_handle(&op.blas));
     std::vector<int> ident(n);

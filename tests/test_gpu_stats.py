@@ -115,6 +115,31 @@ def test_dense_products(gpu_lib, name):
     assert np.all(np.abs(got - want) <= bound)
 
 
+def test_covariance_products_split_inner_dimension(gpu_lib):
+    # p = 2501 features: the product X V runs as two chunks of 1250 and a
+    # remainder of 1, summed; FP64 (spmm) and FP32 (inside COCG) paths
+    import torch
+
+    X = spiked_data(150, 2501, spikes=5, seed=9)
+    A = sample_covariance(X)
+    n = A.shape[0]
+    Vh = np.random.default_rng(3).standard_normal((n, 20))
+    V = torch.tensor(Vh, device="cuda")
+    Y = torch.zeros_like(V)
+    ev = np.sort(np.linalg.eigvalsh(X @ X.T / 149))[::-1]
+    with gpu_lib.Plan.from_covariance(X, 0.5 * (ev[4] + ev[5]), 1.05 * ev[0], 10, nc=8,
+                                      ws_op="literal") as plan:
+        plan.spmm(V, Y)
+        got = Y.cpu().numpy()
+        plan.warmstart(omega=gaussian(n, plan.w, 1))
+        out = plan.solve()
+    u = np.finfo(np.float64).eps / 2
+    mag = np.abs(X).T @ (np.abs(X) @ np.abs(Vh)) / 149
+    assert np.all(np.abs(got - A @ Vh) <= 2 * (150 + 2501) * u * mag)
+    assert out["status"] == "OK" and out["M"] == 5
+    np.testing.assert_allclose(np.sort(out["lam"])[::-1], ev[:5], rtol=0, atol=1e-10 * 1.05 * ev[0])
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_dense_shifted_solves(gpu_lib, precision):
     import torch
