@@ -448,6 +448,16 @@ def main_stats(args):
         err = float(np.abs(got - np.array(fx["eigenvalues"][:k])).max()) / abs(fx["lmax"])
         if err > 1e-10:
             raise RuntimeError(f"{name}: eigenvalue error {err:.3e} relative to s_win")
+        # the FP64 operator product alone (warm start / Rayleigh-Ritz form),
+        # 192 columns, wall clock over 10 calls (each ends with a sync)
+        V = torch.randn((n, 192), dtype=torch.float64, device="cuda")
+        Yv = torch.empty_like(V)
+        plan.spmm(V, Yv)
+        t1 = time.perf_counter()
+        for _ in range(10):
+            plan.spmm(V, Yv)
+        prod_s = (time.perf_counter() - t1) / 10
+        del V, Yv
         plan.close()
         solve_ms = sum(o["t_ms"]["solve"] for _, o in recs) / args.steps
         coliters = sum(o["cocg_iters"] for _, o in recs) / args.steps
@@ -457,6 +467,8 @@ def main_stats(args):
             cocg_iters=int(coliters), solve_ms=round(solve_ms, 2),
             warmstart_ms=round(sum(w["t_ms"] for w, _ in recs) / args.steps, 2),
             solve_operator_tflops=round(flops_per_col * coliters / (solve_ms * 1e-3) / 1e12, 2),
+            fp64_product_192_ms=round(prod_s * 1e3, 3),
+            fp64_product_192_tflops=round(flops_per_col / 2 * 192 / prod_s / 1e12, 2),
             max_eig_error_rel=err, plan_ms=round(plan_ms, 1), generate_ms=round(gen_ms, 1))
         tot_m += k * args.steps
         tot_s += secs
