@@ -1283,6 +1283,23 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
       P->zw[2 * P->nc + 2 * j] = 0.5 * om[j] * r * er;
       P->zw[2 * P->nc + 2 * j + 1] = 0.5 * om[j] * r * ei;
     }
+    // nodes ordered by increasing |Im z| (the sum does not depend on the
+    // order): the systems nearest the real axis take the most COCG
+    // iterations, and the streaming engine's column groups (consecutive
+    // shifts) then keep the slow ones together, so groups of easy shifts
+    // stop costing bandwidth or flops early
+    std::vector<int> ord(P->nc);
+    for (int j = 0; j < P->nc; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+      return std::fabs(P->zw[2 * a + 1]) < std::fabs(P->zw[2 * b + 1]);
+    });
+    std::vector<double> zw2(P->zw.size());
+    for (int j = 0; j < P->nc; ++j)
+      for (int h = 0; h < 2; ++h) {
+        zw2[2 * j + h] = P->zw[2 * ord[j] + h];
+        zw2[2 * P->nc + 2 * j + h] = P->zw[2 * P->nc + 2 * ord[j] + h];
+      }
+    P->zw.swap(zw2);
   }
 
   if (D) {
