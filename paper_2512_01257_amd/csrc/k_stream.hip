@@ -548,43 +548,67 @@ __global__ __launch_bounds__(kST) void k_s_resid64(
   put_partials<CPL, 3>(acc, part, Bp, c0, sh);
 }
 
-// Dense operator, K2 after the product: w holds A p for the group's columns
-// (a GEMM wrote it); w = z p - A p for iterating columns, 0 for frozen ones,
-// and the partials of mu = p^T w, as k_s_spmm.
+// Dense operator: the iterating columns of the current p packed side by side
+// (packed column u holds column cidx[u] & 0xfffffff, read from the p buffer
+// of parity ((cidx[u] >> 30) & 1) ^ flip), so the GEMM multiplies only the
+// columns that iterate, not whole column groups.
+template <typename T>
+__global__ __launch_bounds__(kST) void k_s_pack(int n, int Bp, int nl,
+                                                const int* __restrict__ cidx, int flip,
+                                                const cpx<T>* __restrict__ pa,
+                                                const cpx<T>* __restrict__ pb,
+                                                cpx<T>* __restrict__ pc) {
+  const int u = blockIdx.y * 64 + (threadIdx.x & 63);
+  if (u >= nl) return;
+  const int code = cidx[u];
+  const int c = code & 0xfffffff;
+  const cpx<T>* __restrict__ src = (((code >> 30) & 1) ^ flip) ? pb : pa;
+  const WaveRows wr = wave_rows(n);
+  for (int k = 0; k < wr.count; ++k) {
+    const size_t r = (size_t)(wr.first + wr.stride * k) * Bp;
+    pc[r + u] = src[r + c];
+  }
+}
+
+// Dense operator, K2 after the packed product: w = z p - A p for iterating
+// columns (A p of column c at packed column cmap[c] of apc), 0 for frozen
+// ones, and the partials of mu = p^T w, as k_s_spmm.
 template <typename T, int CPL>
-__global__ __launch_bounds__(kST) void k_s_shiftw(int n, int Bp, StreamGroups grp,
-                                                  const double* __restrict__ zc,
-                                                  const int* __restrict__ state,
-                                                  const cpx<T>* __restrict__ pa,
-                                                  const cpx<T>* __restrict__ pb,
-                                                  cpx<T>* __restrict__ w,
-                                                  double* __restrict__ part) {
+__global__ __launch_bounds__(kST) void k_s_shiftw_packed(int n, int Bp, StreamGroups grp,
+                                                         const double* __restrict__ zc,
+                                                         const int* __restrict__ state,
+                                                         const int* __restrict__ cmap,
+                                                         const cpx<T>* __restrict__ pa,
+                                                         const cpx<T>* __restrict__ pb,
+                                                         const cpx<T>* __restrict__ apc,
+                                                         cpx<T>* __restrict__ w,
+                                                         double* __restrict__ part) {
   extern __shared__ double sh[];
   const int c0 = grp.g[blockIdx.y] * 64 * CPL;
   const cpx<T>* __restrict__ p = grp.par[blockIdx.y] ? pb : pa;
   const int cl = c0 + (threadIdx.x & 63) * CPL;
   T zre[CPL], zim[CPL];
-  bool live[CPL];
+  int pk[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     zre[q] = T(zc[2 * (cl + q)]);
     zim[q] = T(zc[2 * (cl + q) + 1]);
-    live[q] = state[cl + q] == 1;
+    pk[q] = state[cl + q] == 1 ? cmap[cl + q] : -1;
   }
   double acc[CPL][2];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) acc[q][0] = acc[q][1] = 0.0;
   const WaveRows wr = wave_rows(n);
   for (int k = 0; k < wr.count; ++k) {
-    const size_t ro = (size_t)(wr.first + wr.stride * k) * Bp + cl;
-    const Chunk<T, CPL> p0 = ld<T, CPL>(p + ro);
-    Chunk<T, CPL> ww = ld<T, CPL>(w + ro);
+    const size_t rb = (size_t)(wr.first + wr.stride * k) * Bp;
+    const Chunk<T, CPL> p0 = ld<T, CPL>(p + rb + cl);
+    Chunk<T, CPL> ww;
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
-      if (live[q]) {
-        const T ar = ww.v[q].re, ai = ww.v[q].im;
-        ww.v[q].re = zre[q] * p0.v[q].re - zim[q] * p0.v[q].im - ar;
-        ww.v[q].im = zre[q] * p0.v[q].im + zim[q] * p0.v[q].re - ai;
+      if (pk[q] >= 0) {
+        const cpx<T> a = apc[rb + pk[q]];
+        ww.v[q].re = zre[q] * p0.v[q].re - zim[q] * p0.v[q].im - a.re;
+        ww.v[q].im = zre[q] * p0.v[q].im + zim[q] * p0.v[q].re - a.im;
       } else {
         ww.v[q] = cpx<T>{T(0), T(0)};
       }
@@ -592,7 +616,7 @@ __global__ __launch_bounds__(kST) void k_s_shiftw(int n, int Bp, StreamGroups gr
       acc[q][0] += pr * wr_ - pi * wi;
       acc[q][1] += pr * wi + pi * wr_;
     }
-    st<T, CPL>(w + ro, ww);
+    st<T, CPL>(w + rb + cl, ww);
   }
   put_partials<CPL, 2>(acc, part, Bp, c0, sh);
 }
@@ -891,27 +915,8 @@ static hipError_t run_stream_t(hipStream_t stm, const StreamMatrix& A, const Str
     e = hipGetLastError();                \
     if (e != hipSuccess) return e;        \
   } while (0)
-  // Dense operator: the products over runs of consecutive groups that share
-  // a p buffer, as real row-major blocks (a complex column is two real ones).
-  auto dense_product = [&](const StreamGroups& grp) -> hipError_t {
-    for (int a = 0; a < grp.count;) {
-      int b = a + 1;
-      while (b < grp.count && grp.g[b] == grp.g[b - 1] + 1 && grp.par[b] == grp.par[a]) ++b;
-      const size_t c0 = (size_t)grp.g[a] * gw;
-      const int kr = 2 * gw * (b - a);
-      const cpx<T>* p = grp.par[a] ? Pb : Pa;
-      hipError_t e2;
-      if constexpr (sizeof(T) == 4)
-        e2 = dense_apply_f32(*A.dense, stm, kr, (const float*)(p + c0), 2 * Bp,
-                             (float*)(Wv + c0), 2 * Bp);
-      else
-        e2 = dense_apply_f64(*A.dense, stm, kr, (const double*)(p + c0), 2 * Bp,
-                             (double*)(Wv + c0), 2 * Bp, 1.0, 0.0);
-      if (e2 != hipSuccess) return e2;
-      a = b;
-    }
-    return hipSuccess;
-  };
+  // Dense operator: the check products over runs of consecutive waiting
+  // groups, as real row-major blocks (a complex column is two real ones).
   auto dense_check_product = [&](const StreamGroups& grp) -> hipError_t {
     for (int a = 0; a < grp.count;) {
       int b = a + 1;
@@ -933,13 +938,38 @@ static hipError_t run_stream_t(hipStream_t stm, const StreamMatrix& A, const Str
           R, Pa, XH, W.part);
   SLAUNCH(k_s_fin_start, fgrid, fblk, 0, stm, Bp, nb, W.part, W.cols);
   std::vector<int> cnt(2 * ng);
+  std::vector<int> hstate(A.dense ? Bp : 0), hidx, hmap;
   auto census = [&]() -> hipError_t {
     hipLaunchKernelGGL(k_s_count, dim3(ng), dim3(64), 0, stm, Bp, gw, W.cols, W.cnt);
     hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return e2;
     e2 = hipMemcpyAsync(cnt.data(), W.cnt, 2 * ng * sizeof(int), hipMemcpyDeviceToHost, stm);
     if (e2 != hipSuccess) return e2;
+    if (A.dense) {
+      e2 = hipMemcpyAsync(hstate.data(), W.cols.state, Bp * sizeof(int), hipMemcpyDeviceToHost,
+                          stm);
+      if (e2 != hipSuccess) return e2;
+    }
     return hipStreamSynchronize(stm);
+  };
+  // Dense operator: the packed list of the iterating columns, each with its
+  // group's p parity at the start of the chunk, and the column -> packed map.
+  int nl = 0;
+  auto pack_list = [&]() -> hipError_t {
+    hidx.clear();
+    hmap.assign(Bp, -1);
+    for (int c = 0; c < Bp; ++c)
+      if (hstate[c] == 1) {
+        hmap[c] = (int)hidx.size();
+        hidx.push_back(c | (parity[c / gw] << 30));
+      }
+    nl = (int)hidx.size();
+    hipError_t e2 = hipSuccess;
+    if (nl > 0)
+      e2 = hipMemcpyAsync(W.cidx, hidx.data(), nl * sizeof(int), hipMemcpyHostToDevice, stm);
+    if (e2 == hipSuccess)
+      e2 = hipMemcpyAsync(W.cmap, hmap.data(), Bp * sizeof(int), hipMemcpyHostToDevice, stm);
+    return e2;
   };
   e = census();
   if (e != hipSuccess) return e;
@@ -964,6 +994,10 @@ static hipError_t run_stream_t(hipStream_t stm, const StreamMatrix& A, const Str
     if (live.count == 0 && wait.count == 0) break;
     if (live.count > 0) {
       const dim3 gl(nb, live.count);
+      if (A.dense) {
+        e = pack_list();
+        if (e != hipSuccess) return e;
+      }
       for (int k = 0; k < chunk; ++k) {
         SLAUNCH((k_s_pupd<T, CPL>), gl, blk, 0, stm, n, Bp, live, W.cols.beta, W.cols.state, R,
                 Pa, Pb);
@@ -972,10 +1006,22 @@ static hipError_t run_stream_t(hipStream_t stm, const StreamMatrix& A, const Str
           parity[live.g[i]] ^= 1;
         }
         if (A.dense) {
-          e = dense_product(live);
+          // the packed columns' p (parity flipped once per iteration so far),
+          // their product, then the shift
+          cpx<T>* Pc = (cpx<T>*)W.pc;
+          cpx<T>* APc = (cpx<T>*)W.apc;
+          if (nl > 0)
+            SLAUNCH((k_s_pack<T>), dim3(nb, (nl + 63) / 64), blk, 0, stm, n, Bp, nl, W.cidx,
+                    (k + 1) & 1, Pa, Pb, Pc);
+          if constexpr (sizeof(T) == 4)
+            e = dense_apply_f32(*A.dense, stm, 2 * nl, (const float*)Pc, 2 * Bp, (float*)APc,
+                                2 * Bp);
+          else
+            e = dense_apply_f64(*A.dense, stm, 2 * nl, (const double*)Pc, 2 * Bp,
+                                (double*)APc, 2 * Bp, 1.0, 0.0);
           if (e != hipSuccess) return e;
-          SLAUNCH((k_s_shiftw<T, CPL>), gl, blk, shm(2), stm, n, Bp, live, W.zc, W.cols.state, Pa,
-                  Pb, Wv, W.part);
+          SLAUNCH((k_s_shiftw_packed<T, CPL>), gl, blk, shm(2), stm, n, Bp, live, W.zc,
+                  W.cols.state, W.cmap, Pa, Pb, APc, Wv, W.part);
         } else {
           SLAUNCH((k_s_spmm<T, CPL>), gl, blk, shm(2), stm, n, A.rowptr, A.col, val, Bp, live,
                   W.zc, W.cols.state, Pa, Pb, Wv, W.part);

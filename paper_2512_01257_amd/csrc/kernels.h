@@ -251,6 +251,10 @@ struct StreamWork {
   void* w = nullptr;
   void* xh = nullptr;              // n x Bp complex FP64
   void* axh = nullptr;             // dense operator only: n x Bp complex FP64, A x_hi
+  void* pc = nullptr;              // dense only: n x Bp complex, the iterating columns of p
+  void* apc = nullptr;             //   packed side by side, and A times them
+  int* cidx = nullptr;             // dense only: [Bp] packed column -> column (+ parity bit 30)
+  int* cmap = nullptr;             // dense only: [Bp] column -> packed column (-1: none)
   double* part = nullptr;          // stream_partial_doubles(n, Bp, num_cu)
   double* zc = nullptr;            // [2 Bp] shift of each column (padding: any finite value)
   double* scale = nullptr;         // [Bp]

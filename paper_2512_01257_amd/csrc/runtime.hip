@@ -599,6 +599,10 @@ rafeast_status alloc_stream_work(rafeast_plan_s* P, int Bp, StreamWork& W,
     if (P->dop.kind == 2 && 2 * (int64_t)Bp > P->dop.tcols)
       return fail(P, RAFEAST_UNSUPPORTED, "more columns than the covariance scratch holds");
     RCHK(get(&W.axh, blk * 2 * sizeof(double), "stream A x_hi"));
+    RCHK(get(&W.pc, blk * cs, "stream packed p"));
+    RCHK(get(&W.apc, blk * cs, "stream packed A p"));
+    RCHK(get((void**)&W.cidx, (size_t)Bp * sizeof(int), "stream packed index"));
+    RCHK(get((void**)&W.cmap, (size_t)Bp * sizeof(int), "stream packed map"));
   }
   RCHK(get((void**)&W.part, stream_partial_doubles((int)n, Bp, P->num_cu) * sizeof(double),
            "stream partials"));
