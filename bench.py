@@ -95,6 +95,48 @@ def spmm_rate(reps=20):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def gram_shapes(reps=5):
+    """The FP64 MFMA kernels of Rayleigh-Ritz and CholQR2 (k_gram_partial /
+    k_gram_reduce, k_tsmm, k_chol_inv) on tall-skinny blocks of a large
+    problem: Gram products X^T X of n = 1e6 rows and k = 84 (the warm start's
+    m0 + p of the headline) or 192 (the largest block) columns, and CholQR2 of
+    the 84-column block.  Wall-clock per call (each call allocates its partial
+    sums); the kernels' own durations and MFMA utilisation come from rocprofv3."""
+    import torch
+
+    from paper_2512_01257_amd import native
+    from workloads import grid_laplacian
+
+    csr = grid_laplacian((100, 100, 100), 0.01)
+    plan = native.Plan(csr, 0.5, 0.6, 1, nc=1, q=0, p=4, engine="stream")
+    out = {}
+    for k in (84, 192):
+        X = torch.randn((csr.n, k), dtype=torch.float64, device="cuda")
+        G = torch.empty((k, k), dtype=torch.float64, device="cuda")
+        plan.gram(X, X, G)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.gram(X, X, G)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        ref = (X.T @ X)
+        err = float((G - ref).abs().max() / ref.abs().max())
+        out[f"gram_k{k}"] = dict(n=csr.n, k=k, wall_ms=round(ms, 3),
+                                 flops=2.0 * csr.n * k * k, rel_diff_vs_torch=err)
+        del X, G
+    Y = torch.randn((csr.n, 84), dtype=torch.float64, device="cuda")
+    plan.cholqr2(Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.cholqr2(Y)
+    torch.cuda.synchronize()
+    out["cholqr2_k84"] = dict(n=csr.n, k=84, wall_ms=round((time.perf_counter() - t0) / reps * 1e3, 3))
+    plan.close()
+    return out
+
+
 def cpu_baseline(csr, win, runs):
     """The oracle (FP64, sparse LU shifted solves) on the same workload."""
     import numpy as np
@@ -599,6 +641,8 @@ def main():
                          "starting at --relaxed")
     ap.add_argument("--max-iter", type=int, default=20, help="grid64: FEAST iteration cap")
     ap.add_argument("--max-cocg", type=int, default=20000, help="grid64: COCG iteration cap")
+    ap.add_argument("--gram-only", action="store_true",
+                    help="only the tall-skinny FP64 MFMA kernels (Gram, CholQR2) at n = 1e6")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the FP64 SpMM rate measurement (for profiling)")
     ap.add_argument("--rgg-n", default="2000,4000,8000,16000", help="rgg: graph sizes")
@@ -619,6 +663,12 @@ def main():
         return main_rgg(args)
     if args.workload == "stats":
         return main_stats(args)
+    if args.gram_only:
+        import torch
+
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps({"gram": gram_shapes()}), flush=True)
+        return
     if args.spmm_only:
         import torch
 

@@ -37,16 +37,19 @@ def small_plan(gpu_lib):
     p.close()
 
 
-@pytest.mark.parametrize("n,k1,k2", [(1000, 30, 45), (4096, 64, 64), (777, 1, 17),
-                                     (130, 148, 148), (3000, 192, 7), (100_003, 128, 128)])
-def test_gram_parity(small_plan, torch_dev, n, k1, k2):
+@pytest.mark.parametrize("n,k1,k2,same", [(1000, 30, 45, False), (4096, 64, 64, False),
+                                          (777, 1, 17, False), (130, 148, 148, False),
+                                          (3000, 192, 7, False), (100_003, 128, 128, False),
+                                          (5003, 84, 84, True), (262_147, 192, 192, True)])
+def test_gram_parity(small_plan, torch_dev, n, k1, k2, same):
+    # same: X^T X with one buffer for both operands (one LDS slab serves both)
     torch = torch_dev
     _, plan = small_plan
     rng = np.random.default_rng(n + k1)
     X = rng.standard_normal((n, k1))
-    Y = rng.standard_normal((n, k2))
+    Y = X if same else rng.standard_normal((n, k2))
     Xd = torch.from_numpy(X).cuda()
-    Yd = torch.from_numpy(Y).cuda()
+    Yd = Xd if same else torch.from_numpy(Y).cuda()
     G = torch.zeros((k1, k2), dtype=torch.float64, device="cuda")
     plan.gram(Xd, Yd, G)
     ref = X.T @ Y
