@@ -89,3 +89,26 @@ def test_grid3d_64_interior_window(gpu_lib):
     assert ws["op"] == "fold"
     assert out["status"] == "OK"
     check_against(out, A, vals, V, lmin, lmax, 1e-10, gap)
+
+
+# The same window with relaxed Phase-2 solves (COCG starting at 1e-2, tightened
+# by the contraction control): about a minute and a half, so it runs by default.
+def test_grid3d_64_interior_window_relaxed(gpu_lib):
+    dims, shift = (64, 64, 64), 0.01
+    csr = grid_laplacian(dims, shift)
+    A = csr.to_scipy()
+    lmin, lmax = 0.493673151133, 0.506687779116
+    vals, V = window_basis(dims, shift, lmin, lmax)
+    assert len(vals) == 39
+    allv, _ = grid_eigs(dims, shift)
+    gap = gap_out(allv, lmin, lmax)
+    m0, nc, p = 64, 8, 20
+    with gpu_lib.Plan(csr, lmin, lmax, m0, nc=nc, q=2, p=p, precision="fp32",
+                      tol_solve=1e-6, tol_eig=1e-10, tol_solve_relaxed=1e-2) as plan:
+        assert plan.engine == "stream"
+        om = gaussian(csr.n, m0 + p, 0)
+        ws = plan.warmstart(omega=om)
+        out = plan.solve()
+    assert ws["op"] == "fold"
+    assert out["status"] == "OK"
+    check_against(out, A, vals, V, lmin, lmax, 1e-10, gap)
