@@ -113,3 +113,32 @@ def test_batch_repeated_solves_agree(gpu_lib):
     for a, b in zip(*res):
         assert np.array_equal(a["lam"], b["lam"]) and a["iters"] == b["iters"]
         assert np.array_equal(a["X"], b["X"])
+
+
+def test_batch32_workload(gpu_lib):
+    # the batching form at its full size: the 32 stored graphs (n from 2000 to
+    # 60000, 9 in the shared resident launch), each member's eigenvalues
+    # against its stored spectrum
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "windows.json")) as f:
+        wins = json.load(f)["batch32"]
+    probs = []
+    for wn in wins:
+        csr = knn_laplacian(wn["n"], wn["dim"], wn["k"], seed=wn["seed"], weighted=False)
+        assert csr.nnz == wn["nnz"]
+        probs.append(dict(csr=csr, lmin=wn["lmin"], lmax=wn["lmax"], m0=wn["m0"]))
+    with gpu_lib.Batch(probs, nc=4, q=2, tol_eig=1e-10, tol_solve=1e-6, precision="fp32",
+                       seed=0) as B:
+        assert B.resident_count == 9
+        for m in B.members:
+            m.warmstart()
+        outs, _, status = B.solve(want_vectors=False)
+    assert status == "OK"
+    for wn, o in zip(wins, outs):
+        ev = np.array(wn["eigenvalues"][: wn["count"]])
+        assert o["M"] == wn["count"]
+        s_win = max(abs(wn["lmin"]), wn["lmax"])
+        assert np.abs(o["lam"] - ev).max() <= 1e-10 * s_win
+        assert o["max_resid"] <= 1e-10
