@@ -195,6 +195,10 @@ size_t gram_partial_doubles(int64_t n, int k1, int k2) {
   return (size_t)gram_chunks(n) * (size_t)k1 * (size_t)k2;
 }
 
+// Each wave owns a TA x TB block of 16 x 16 output tiles: per 4-row step it
+// loads TA + TB operand fragments and issues TA * TB MFMAs on them, so each
+// fragment feeds several MFMAs (a 1 x 4 block loads 5 fragments for 4).
+template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k1, int k2,
                                                       const double* __restrict__ X, int ldx,
                                                       const double* __restrict__ Y, int ldy,
@@ -206,44 +210,57 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k1, int k2,
   if (r_end > n) r_end = n;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ta_n = (k1 + 15) >> 4, tb_n = (k2 + 15) >> 4;
-  const int gpr = (tb_n + 3) >> 2;  // groups of 4 column tiles per tile row
-  const int tg = blockIdx.y * 4 + wave;
-  const int ta = tg / gpr, tb0 = (tg % gpr) * 4;
-  if (ta >= ta_n) return;
-  v4d acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int bb_n = (tb_n + TB - 1) / TB;  // tile blocks per block row
+  const int blk = blockIdx.y * 4 + wave;
+  const int ta0 = (blk / bb_n) * TA, tb0 = (blk % bb_n) * TB;
+  if (ta0 >= ta_n) return;
   const int li = lane & 15, lk = lane >> 4;
-  const int a_col = ta * 16 + li;
-  const bool a_ok = a_col < k1;
-  int b_col[4];
-  bool b_ok[4];
+  const int na = min(TA, ta_n - ta0), nb = min(TB, tb_n - tb0);  // wave-uniform
+  int a_col[TA], b_col[TB];
+  bool a_ok[TA], b_ok[TB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    b_col[t] = (tb0 + t) * 16 + li;
-    b_ok[t] = (tb0 + t) < tb_n && b_col[t] < k2;
+  for (int i = 0; i < TA; ++i) {
+    a_col[i] = (ta0 + i) * 16 + li;
+    a_ok[i] = i < na && a_col[i] < k1;
   }
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    b_col[j] = (tb0 + j) * 16 + li;
+    b_ok[j] = j < nb && b_col[j] < k2;
+  }
+  v4d acc[TA][TB];
+#pragma unroll
+  for (int i = 0; i < TA; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int64_t r = r_begin; r < r_end; r += 4) {
     const int64_t rr = r + lk;
     const bool r_ok = rr < r_end;
-    const double a = (a_ok && r_ok) ? X[rr * ldx + a_col] : 0.0;
+    double a[TA], b[TB];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double b = (b_ok[t] && r_ok) ? Y[rr * ldy + b_col[t]] : 0.0;
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-    }
+    for (int i = 0; i < TA; ++i) a[i] = (a_ok[i] && r_ok) ? X[rr * ldx + a_col[i]] : 0.0;
+#pragma unroll
+    for (int j = 0; j < TB; ++j) b[j] = (b_ok[j] && r_ok) ? Y[rr * ldy + b_col[j]] : 0.0;
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j)
+        if (i < na && j < nb)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
   }
   double* P = part + (size_t)chunk * k1 * k2;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (!((tb0 + t) < tb_n)) continue;
+  for (int i = 0; i < TA; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = ta * 16 + lk + 4 * v;
-      const int j = (tb0 + t) * 16 + li;
-      if (i < k1 && j < k2) P[(size_t)i * k2 + j] = acc[t][v];
+    for (int j = 0; j < TB; ++j) {
+      if (!(i < na && j < nb)) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = (ta0 + i) * 16 + lk + 4 * v;
+        const int gj = (tb0 + j) * 16 + li;
+        if (gi < k1 && gj < k2) P[(size_t)gi * k2 + gj] = acc[i][j][v];
+      }
     }
-  }
 }
 
 __global__ __launch_bounds__(256) void k_gram_reduce(int chunks, int k1, int k2,
@@ -264,10 +281,18 @@ hipError_t launch_gram(hipStream_t st, int64_t n, int k1, int k2, const double* 
   int64_t rpc = (n + chunks - 1) / chunks;
   rpc = (rpc + 3) & ~int64_t(3);
   const int ta_n = (k1 + 15) / 16, tb_n = (k2 + 15) / 16;
-  const int groups = ta_n * ((tb_n + 3) / 4);
-  dim3 grid(chunks, (groups + 3) / 4);
-  hipLaunchKernelGGL(k_gram_partial, grid, dim3(256), 0, st, n, k1, k2, X, ldx, Y, ldy, part,
-                     rpc);
+  // the largest tile block that still gives three or more workgroups per
+  // chunk (the chip holds several per CU), else 2 x 2
+  auto nblk = [&](int ta, int tb) { return ((ta_n + ta - 1) / ta) * ((tb_n + tb - 1) / tb); };
+  const bool big = (nblk(3, 3) + 3) / 4 >= 3;
+  const int blocks = big ? nblk(3, 3) : nblk(2, 2);
+  dim3 grid(chunks, (blocks + 3) / 4);
+  if (big)
+    hipLaunchKernelGGL((k_gram_partial<3, 3>), grid, dim3(256), 0, st, n, k1, k2, X, ldx, Y,
+                       ldy, part, rpc);
+  else
+    hipLaunchKernelGGL((k_gram_partial<2, 2>), grid, dim3(256), 0, st, n, k1, k2, X, ldx, Y,
+                       ldy, part, rpc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gram_reduce, dim3((k1 * k2 + 255) / 256), dim3(256), 0, st, chunks, k1,
