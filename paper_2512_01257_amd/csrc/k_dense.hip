@@ -302,9 +302,10 @@ hipError_t launch_gram(hipStream_t st, int64_t n, int k1, int k2, const double* 
 
 // ============================================================================
 // TSMM Y = X S on v_mfma_f64_16x16x4f64: each wave computes a 16-row strip of
-// Y for four 16-column tiles; A operand lane l reads X[r0 + l%16][a0 + l/16],
+// Y for TB 16-column tiles; A operand lane l reads X[r0 + l%16][a0 + l/16],
 // B operand reads S[a0 + l/16][b0 + l%16].
 // ============================================================================
+template <int TB>
 __global__ __launch_bounds__(256) void k_tsmm(int64_t n, int k, int k2,
                                               const double* __restrict__ X, int ldx,
                                               const double* __restrict__ S, int lds,
@@ -313,32 +314,34 @@ __global__ __launch_bounds__(256) void k_tsmm(int64_t n, int k, int k2,
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
   if (r0 >= n) return;
   const int tb_n = (k2 + 15) >> 4;
-  const int tb0 = blockIdx.y * 4;
+  const int tb0 = blockIdx.y * TB;
+  const int nb = min(TB, tb_n - tb0);  // wave-uniform
   const int li = lane & 15, lk = lane >> 4;
-  v4d acc[4];
+  v4d acc[TB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < TB; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t arow = r0 + li;
   const bool r_ok = arow < n;
-  int bcol[4];
-  bool bok[4];
+  int bcol[TB];
+  bool bok[TB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < TB; ++t) {
     bcol[t] = (tb0 + t) * 16 + li;
-    bok[t] = (tb0 + t) < tb_n && bcol[t] < k2;
+    bok[t] = t < nb && bcol[t] < k2;
   }
   for (int a0 = 0; a0 < k; a0 += 4) {
     const int acol = a0 + lk;
     const bool aok = acol < k;
     const double a = (aok && r_ok) ? X[arow * ldx + acol] : 0.0;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double b = (aok && bok[t]) ? S[(size_t)acol * lds + bcol[t]] : 0.0;
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    for (int t = 0; t < TB; ++t) {
+      if (t >= nb) continue;
+      const double bv = (aok && bok[t]) ? S[(size_t)acol * lds + bcol[t]] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < TB; ++t) {
     if (!bok[t]) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -352,8 +355,10 @@ hipError_t launch_tsmm(hipStream_t st, int64_t n, int k, int k2, const double* X
                        const double* S, int lds, double* Y, int ldy) {
   if (n <= 0 || k2 <= 0) return hipSuccess;
   const int tb_n = (k2 + 15) / 16;
-  dim3 grid((unsigned)((n + 63) / 64), (tb_n + 3) / 4);
-  hipLaunchKernelGGL(k_tsmm, grid, dim3(256), 0, st, n, k, k2, X, ldx, S, lds, Y, ldy);
+  // one wave covers up to six column tiles, so X is read once for k2 <= 96
+  constexpr int TB = 6;
+  dim3 grid((unsigned)((n + 63) / 64), (tb_n + TB - 1) / TB);
+  hipLaunchKernelGGL(k_tsmm<TB>, grid, dim3(256), 0, st, n, k, k2, X, ldx, S, lds, Y, ldy);
   return hipGetLastError();
 }
 
