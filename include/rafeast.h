@@ -243,8 +243,7 @@ const char* rafeast_status_string(rafeast_status s);
  * nodes in order of increasing |Im z|, the order each solve starts with (the
  * filter sum does not depend on it; from the second filter application on,
  * a solve takes the nodes by decreasing COCG iteration count of the one
- * before, and the next solve starts from this order again; this call always
- * reports the starting order).  Dense plans: nnz = n^2 (rafeast_plan_dense)
+ * before, and the next solve starts from this order again).  Dense plans: nnz = n^2 (rafeast_plan_dense)
  * or rows * n (rafeast_plan_gram), and for the covariance form the bound
  * scale ||X||_F^2 in place of ||A||_inf. */
 rafeast_status rafeast_plan_info(rafeast_plan_t plan, double* sig_lo, double* sig_hi,

@@ -1724,9 +1724,8 @@ rafeast_status rafeast_plan_info(rafeast_plan_t P, double* sig_lo, double* sig_h
   if (sig_hi) *sig_hi = P->sig_hi;
   if (anorm_inf) *anorm_inf = P->anorm;
   if (nnz) *nnz = P->nnz;
-  // the plan-time order (a solve reorders its nodes while it runs)
-  if (z) std::memcpy(z, P->zw0.data(), 2 * P->nc * sizeof(double));
-  if (w) std::memcpy(w, P->zw0.data() + 2 * P->nc, 2 * P->nc * sizeof(double));
+  if (z) std::memcpy(z, P->zw.data(), 2 * P->nc * sizeof(double));
+  if (w) std::memcpy(w, P->zw.data() + 2 * P->nc, 2 * P->nc * sizeof(double));
   return RAFEAST_OK;
 }
 
