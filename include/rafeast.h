@@ -240,10 +240,8 @@ const char* rafeast_status_string(rafeast_status s);
 
 /* Gershgorin interval, ||A||_inf, nnz and the quadrature table of a plan.
  * z and w: nullable host arrays of 2*nc doubles (re, im interleaved), the
- * nodes in order of increasing |Im z|, the order each solve starts with (the
- * filter sum does not depend on it; from the second filter application on,
- * a solve takes the nodes by decreasing COCG iteration count of the one
- * before, and the next solve starts from this order again).  Dense plans: nnz = n^2 (rafeast_plan_dense)
+ * nodes in order of increasing |Im z| (the order the solves use; the filter
+ * sum does not depend on it).  Dense plans: nnz = n^2 (rafeast_plan_dense)
  * or rows * n (rafeast_plan_gram), and for the covariance form the bound
  * scale ||X||_F^2 in place of ||A||_inf. */
 rafeast_status rafeast_plan_info(rafeast_plan_t plan, double* sig_lo, double* sig_hi,

@@ -40,8 +40,7 @@ struct rafeast_plan_s {
   int64_t n = 0, nnz = 0;
   int m0 = 0, w = 0, nc = 0, pov = 0;
   double sig_lo = 0, sig_hi = 0, anorm = 0;
-  std::vector<double> zw;  // z_j (re, im) then w_j (re, im), in the order the solves use
-  std::vector<double> zw0;  // the same at plan time (each solve starts from it)
+  std::vector<double> zw;  // z_j (re, im) then w_j (re, im)
   hipStream_t st = nullptr;
   bool own_stream = false;
   int dev = 0, num_cu = 0;
@@ -830,13 +829,11 @@ rafeast_status run_stream(rafeast_plan_s* P, const StreamWork& W, int nz, int k,
 
 // Orders (shift, column) pairs longest-first: the smaller Im z, the more COCG
 // iterations a system needs.
-std::vector<int> make_items(int nz, const double* zs, int k, int g = 0, bool keep_order = false) {
+std::vector<int> make_items(int nz, const double* zs, int k, int g = 0) {
   std::vector<int> js(nz);
   for (int j = 0; j < nz; ++j) js[j] = j;
-  if (!keep_order)
-    std::stable_sort(js.begin(), js.end(), [&](int a, int b) {
-      return std::fabs(zs[2 * a + 1]) < std::fabs(zs[2 * b + 1]);
-    });
+  std::stable_sort(js.begin(), js.end(),
+                   [&](int a, int b) { return std::fabs(zs[2 * a + 1]) < std::fabs(zs[2 * b + 1]); });
   std::vector<int> items;
   items.reserve(3 * (size_t)nz * k);
   for (int j : js)
@@ -885,8 +882,6 @@ bool counted(const rafeast_plan_s* P, const SolveRun& S, int i) {
   return S.theta[i] >= P->prm.lmin && S.theta[i] <= P->prm.lmax && S.mu[i] >= kSpuriousGain;
 }
 
-rafeast_status upload_nodes(rafeast_plan_s* P);
-
 // Start block: Q_init, else the last warm start, else the orthonormalised
 // device sketch.
 rafeast_status solve_begin(rafeast_plan_s* P, const double* Q_init, SolveRun& S) {
@@ -910,10 +905,6 @@ rafeast_status solve_begin(rafeast_plan_s* P, const double* Q_init, SolveRun& S)
   HIPCHK(P, hipMemsetAsync(P->d_stats, 0, 2 * sizeof(int), P->st));
   P->have_filter = false;
   P->tau = std::max(P->prm.tol_solve, P->prm.tol_solve_relaxed);
-  if (P->zw != P->zw0) {  // every solve starts from the plan-time node order
-    P->zw = P->zw0;
-    RCHK(upload_nodes(P));
-  }
   S = SolveRun();
   S.iters.assign(P->nitems, 0);
   return RAFEAST_OK;
@@ -969,55 +960,6 @@ rafeast_status solve_shifted_systems(rafeast_plan_s* P) {
                   P->d_D, nc * m0, P->tau, P->d_iters);
 }
 
-// Uploads the node table P->zw and what the engines derive from its order
-// (the streaming engine's per-column shifts, the resident engine's items).
-rafeast_status upload_nodes(rafeast_plan_s* P) {
-  const int nc = P->nc, m0 = P->m0;
-  HIPCHK(P, hipMemcpyAsync(P->d_zw, P->zw.data(), 4 * nc * sizeof(double), hipMemcpyHostToDevice,
-                           P->st));
-  std::vector<double> zc;
-  std::vector<int> items;
-  if (P->engine == RAFEAST_ENGINE_STREAM) {
-    zc = stream_shifts(nc, P->zw.data(), m0, P->swork.Bp);
-    HIPCHK(P, hipMemcpyAsync(P->swork.zc, zc.data(), zc.size() * sizeof(double),
-                             hipMemcpyHostToDevice, P->st));
-  } else {
-    items = make_items(nc, P->zw.data(), m0, 0, true);
-    HIPCHK(P, hipMemcpyAsync(P->d_items, items.data(), items.size() * sizeof(int),
-                             hipMemcpyHostToDevice, P->st));
-  }
-  HIPCHK(P, hipStreamSynchronize(P->st));
-  return RAFEAST_OK;
-}
-
-// The node order of the next filter application: the nodes by decreasing
-// COCG iteration count of the slowest system in this one (ties keep the
-// current order).  The sum over nodes does not depend on the order; the
-// engines take work in it (the resident engine hands out the slowest systems
-// first, the streaming engine's column groups hold consecutive nodes, so slow
-// nodes share groups and groups of fast nodes go idle early).  Called after
-// the combination has consumed the solves.
-rafeast_status reorder_nodes(rafeast_plan_s* P, const SolveRun& S) {
-  const int nc = P->nc, m0 = P->m0;
-  std::vector<int> cost(nc, 0), ord(nc);
-  for (int j = 0; j < nc; ++j) {
-    ord[j] = j;
-    for (int i = 0; i < m0; ++i) cost[j] = std::max(cost[j], S.iters[(size_t)j * m0 + i]);
-  }
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  bool same = true;
-  for (int j = 0; j < nc; ++j) same = same && ord[j] == j;
-  if (same) return RAFEAST_OK;
-  std::vector<double> zw(P->zw.size());
-  for (int j = 0; j < nc; ++j)
-    for (int h = 0; h < 2; ++h) {
-      zw[2 * j + h] = P->zw[2 * ord[j] + h];
-      zw[2 * nc + 2 * j + h] = P->zw[2 * nc + 2 * ord[j] + h];
-    }
-  P->zw.swap(zw);
-  return upload_nodes(P);
-}
-
 // After the solves (between events ev[2] and ev[3]): combination
 // Q~ = sum_j Re[w_j (z_j I - A)^{-1} Q], CholQR2, timings, counters.
 rafeast_status solve_combine(rafeast_plan_s* P, SolveRun& S) {
@@ -1054,7 +996,6 @@ rafeast_status solve_combine(rafeast_plan_s* P, SolveRun& S) {
                  "solve %.1f ms\n",
                  S.it + 1, S.M, S.maxres, (long long)it_sum, it_max, elapsed(P->ev[2], P->ev[3]));
   ++S.it;
-  RCHK(reorder_nodes(P, S));
   return RAFEAST_OK;
 }
 
@@ -1363,7 +1304,6 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
         zw2[2 * P->nc + 2 * j + h] = P->zw[2 * P->nc + 2 * ord[j] + h];
       }
     P->zw.swap(zw2);
-    P->zw0 = P->zw;
   }
 
   if (D) {
