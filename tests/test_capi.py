@@ -215,3 +215,16 @@ def test_plan_tuning_argument_errors(native):
     cand = (C.c_int32 * 4)()
     ms = (C.c_float * 4)()
     assert L.rafeast_plan_tuning(None, C.byref(ch), C.byref(cnt), cand, ms, 4) == 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # this build runs on one GPU: --gpus N > 1 (or a WORLD_SIZE > 1) exits with
+    # a message before touching a device
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+    env = dict(os.environ, WORLD_SIZE="4")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")], capture_output=True,
+                       text=True, timeout=120, env=env)
+    assert r.returncode == 2 and "one GPU" in r.stderr
