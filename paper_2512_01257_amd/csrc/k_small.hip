@@ -110,18 +110,20 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_inv(int k, double shift_
     if (tid == 0) *flag = 2;
     return;
   }
-  // Four lanes of one wave share row i and split the sum.
-  const int i = tid >> 2, qd = tid & 3;
+  // L lanes of one wave share row i and split the sum (L = 16 for k <= 64,
+  // 8 for k <= 128, else 4: L k <= 1024 threads).
+  const int lg = k <= 64 ? 4 : (k <= 128 ? 3 : 2);
+  const int L = 1 << lg;
+  const int i = tid >> lg, qd = tid & (L - 1);
   if constexpr (kXInLds) {
     for (int j = 0; j < k; ++j) {
       const double ujj = U[packed_index(k, j, j)];
       double part = 0.0;
       if (i < j) {
-        for (int t = i + qd; t < j; t += 4)
+        for (int t = i + qd; t < j; t += L)
           part += X[packed_index(k, i, t)] * U[packed_index(k, t, j)];
       }
-      part += __shfl_xor(part, 1, 64);
-      part += __shfl_xor(part, 2, 64);
+      for (int o = 1; o < L; o <<= 1) part += __shfl_xor(part, o, 64);
       if (i < j && qd == 0) X[packed_index(k, i, j)] = -part / ujj;
       if (tid == kSmallThreads - 1) X[packed_index(k, j, j)] = 1.0 / ujj;
       __syncthreads();
@@ -139,11 +141,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_inv(int k, double shift_
       const double ujj = U[packed_index(k, j, j)];
       double part = 0.0;
       if (i < j) {
-        for (int t = i + qd; t < j; t += 4)
+        for (int t = i + qd; t < j; t += L)
           part += M[(size_t)i * ldm + t] * U[packed_index(k, t, j)];
       }
-      part += __shfl_xor(part, 1, 64);
-      part += __shfl_xor(part, 2, 64);
+      for (int o = 1; o < L; o <<= 1) part += __shfl_xor(part, o, 64);
       if (i < j && qd == 0) M[(size_t)i * ldm + j] = -part / ujj;
       if (tid == kSmallThreads - 1) M[(size_t)j * ldm + j] = 1.0 / ujj;
       __syncthreads();
@@ -236,7 +237,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
       tot += red[1][w];
     }
     __syncthreads();
-    if (k == 1 || off <= 1e-30 * tot) break;
+    // converged once the off-diagonal mass is at the rounding floor: each
+    // of the k (k - 1) off-diagonal entries is then a few units of roundoff
+    // of the diagonal, so off / tot ~ k u^2; 64 k u^2 leaves a margin of 8 u
+    // per entry (u = 2^-53)
+    if (k == 1 || off <= 64.0 * k * 0x1.0p-106 * tot) break;
     for (int r = 0; r < players; ++r) {
       for (int t = tid; t < np; t += kSmallThreads) {
         int p, q;

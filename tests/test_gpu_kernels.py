@@ -105,7 +105,8 @@ def test_cholqr2_rank_deficient(small_plan, torch_dev):
     assert plan.cholqr2(Yd) == 2
 
 
-@pytest.mark.parametrize("k", [1, 2, 7, 64, 65, 128, 148, 192])
+# H and V in LDS up to k = 98, H alone up to 128, both in global memory above
+@pytest.mark.parametrize("k", [1, 2, 7, 33, 64, 65, 98, 99, 128, 129, 148, 192])
 def test_syev_jacobi(small_plan, torch_dev, k):
     torch = torch_dev
     _, plan = small_plan
@@ -126,6 +127,28 @@ def test_syev_jacobi(small_plan, torch_dev, k):
     assert np.all(np.diff(theta) >= 0)
     assert np.abs(Sv.T @ Sv - np.eye(k)).max() < 1e-13 * max(1, k / 16)
     assert np.abs(H @ Sv - Sv * theta[None, :]).max() < 1e-13 * nrm * max(1, k / 16)
+
+
+@pytest.mark.parametrize("k", [64, 84])
+def test_syev_jacobi_nearly_diagonal(small_plan, torch_dev, k):
+    # the reduced matrix of a late FEAST iteration: diagonal up to a small
+    # symmetric perturbation, with a cluster of close diagonal entries
+    torch = torch_dev
+    _, plan = small_plan
+    rng = np.random.default_rng(100 + k)
+    d = np.sort(rng.uniform(0.0, 0.06, k))
+    d[10:14] = d[10] + 1e-9 * np.arange(4)
+    E = 1e-7 * rng.standard_normal((k, k))
+    H = np.diag(d) + E + E.T
+    th = torch.zeros(k, dtype=torch.float64, device="cuda")
+    S = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+    plan.syev(torch.from_numpy(H).cuda(), th, S)
+    theta = th.cpu().numpy()
+    Sv = S.cpu().numpy()
+    nrm = np.linalg.norm(H, 2)
+    np.testing.assert_allclose(theta, np.linalg.eigvalsh(H), atol=1e-14 * nrm * k)
+    assert np.abs(Sv.T @ Sv - np.eye(k)).max() < 1e-14 * k
+    assert np.abs(H @ Sv - Sv * theta[None, :]).max() < 1e-14 * nrm * k
 
 
 @pytest.mark.parametrize("seed", [0, 12345, (1 << 40) + 7])
