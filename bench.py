@@ -814,7 +814,11 @@ def main():
         },
         "plain_feast": None if plain_value is None else {
             "value": round(plain_value, 3), "unit": "eigenpairs/s",
-            "ms_per_step": round(psecs / pk * 1e3, 4), "nc": w["nc_plain"]},
+            "ms_per_step": round(psecs / pk * 1e3, 4), "nc": w["nc_plain"],
+            # each step draws a new random start, so the FEAST iteration count
+            # (and with it the step time) varies between steps
+            "feast_iters_per_step": [o["iters"] for _, o in precs],
+            "cocg_iters_per_step": int(sum(o["cocg_iters"] for _, o in precs) / pk)},
         "speedup_vs_plain": None if plain_value is None else round(value / plain_value, 3),
         "relaxed_phase2": relaxed,
         "plan_ms": round(plan_ms, 2),
