@@ -104,6 +104,15 @@ __device__ __forceinline__ double rcp_nr(double d) {
   x = fma(x, fma(-d, x, 1.0), x);
   return x;
 }
+// 1/sqrt(x) for positive normal x from the hardware estimate refined by two
+// Newton steps y <- y (3 - x y^2) / 2 (each squares the relative error).
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
 __device__ __forceinline__ zd zdiv_fast(zd a, zd b) {
   if (fabs(b.re) >= fabs(b.im)) {
     const double r = b.im * rcp_nr(b.re), inv = rcp_nr(b.re + b.im * r);

@@ -255,13 +255,24 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
         double c = 1.0, s = 0.0;
         if (p < k && q < k) {
           const double apq = H[p * k + q];
-          if (apq != 0.0) {
-            const double tau = (H[q * k + q] - H[p * k + p]) / (2.0 * apq);
+          if (fabs(apq) >= 0x1.0p-1000) {
+            // this phase is one wave's latency per round: reciprocals and
+            // square roots from Newton-refined hardware estimates (a few ulp;
+            // the rotation stays orthogonal to working precision)
+            const double tau = (H[q * k + q] - H[p * k + p]) * rcp_nr(2.0 * apq);
             double tt;
-            if (fabs(tau) > 1e150)
+            if (fabs(tau) > 1e150) {
               tt = 0.5 / tau;
-            else
-              tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            } else {
+              const double w = fma(tau, tau, 1.0);
+              tt = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + w * rsq_nr(w));
+            }
+            c = rsq_nr(fma(tt, tt, 1.0));
+            s = tt * c;
+          } else if (apq != 0.0) {
+            const double tau = (H[q * k + q] - H[p * k + p]) / (2.0 * apq);
+            const double tt = fabs(tau) > 1e150 ? 0.5 / tau
+                              : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
           }
