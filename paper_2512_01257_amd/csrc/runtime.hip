@@ -73,6 +73,11 @@ struct rafeast_plan_s {
   double* d_theta = nullptr; // kmax
   double* d_res = nullptr;   // kmax
   double* d_qn = nullptr;    // kmax
+  // Q = Q~ mtot for the filtered block Q~ of the last iteration: CholQR2's
+  // transforms (m0 x m0 row-major), valid while have_filter; d_mtmp the
+  // buffer of their next product
+  double* d_mtot = nullptr;  // m0^2
+  double* d_mtmp = nullptr;  // m0^2
   double* d_gamma = nullptr; // 2 nc m0
   double* d_info = nullptr;  // 4
   double* d_zw = nullptr;    // 4 nc
@@ -111,10 +116,7 @@ struct rafeast_plan_s {
   std::vector<void*> sbufs;       // device buffers behind swork
   int nitems = 0;
   bool have_start = false;
-  // Q = Q~ mtot for the filtered block Q~ of the last iteration (CholQR2's
-  // transforms, k x k row-major, host); valid while have_filter
-  std::vector<double> mtot;
-  bool have_filter = false;
+  bool have_filter = false;  // d_mtot holds the last filter step's transforms
   // COCG tolerance of the next filter application (tol_solve, or the relaxed
   // tolerance of Phase 2 while it still contracts)
   double tau = 0.0;
@@ -391,7 +393,8 @@ void free_plan(rafeast_plan_s* P) {
                   P->d_res,    P->d_qn,   P->d_gamma, P->d_info,  P->d_zw,   P->d_part,
                   P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
                   P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm,
-                  P->d_k64, P->d_k32, P->d_t64, P->d_t32, P->d_ones64, P->d_ones32};
+                  P->d_k64, P->d_k32, P->d_t64, P->d_t32, P->d_ones64, P->d_ones32,
+                  P->d_mtot, P->d_mtmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : P->sbufs)
@@ -646,7 +649,12 @@ rafeast_status spmm(rafeast_plan_s* P, int k, const double* X, int ldx, double* 
                     double alpha, double beta, const double* X2 = nullptr, int ldx2 = 0,
                     double gamma = 0.0) {
   if (P->dop.kind != 0) {
-    HIPCHK(P, dense_apply_f64(P->dop, P->st, k, X, ldx, Y, ldy, alpha, beta));
+    // the GEMM forms alpha A X; the beta X and gamma X2 terms are added to it
+    HIPCHK(P, dense_apply_f64(P->dop, P->st, k, X, ldx, Y, ldy, alpha, 0.0));
+    if (beta != 0.0) {
+      if (ldx != k || ldy != k) return fail(P, RAFEAST_UNSUPPORTED, "strided dense update");
+      HIPCHK(P, dense_axpy(P->dop, P->st, P->n * (int64_t)k, beta, X, Y));
+    }
     if (X2) {
       if (ldx2 != k || ldy != k) return fail(P, RAFEAST_UNSUPPORTED, "strided dense update");
       HIPCHK(P, dense_axpy(P->dop, P->st, P->n * (int64_t)k, gamma, X2, Y));
@@ -659,42 +667,32 @@ rafeast_status spmm(rafeast_plan_s* P, int k, const double* X, int ldx, double* 
 }
 
 // CholQR2 on Y (n x k, ld) in place through P->d_T; *info as in rafeast_cholqr2.
+// With track (k = m0), the product of the passes' transforms is formed on the
+// device in d_mtot (pass 0 copies M, later passes multiply it on the right).
 rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, int* info,
-                       double* tmp, int ldt, std::vector<double>* mtot = nullptr) {
+                       double* tmp, int ldt, bool track = false) {
   int worst = 0;
   int passes = 2;
-  std::vector<double> hm, prod;
-  if (mtot) {
-    mtot->assign((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) (*mtot)[(size_t)i * k + i] = 1.0;
-    hm.resize((size_t)k * k);
-    prod.resize((size_t)k * k);
-  }
   for (int pass = 0; pass < passes; ++pass) {
     HIPCHK(P, launch_gram(P->st, n, k, k, Y, ldy, Y, ldy, P->d_G, k, P->d_part));
     HIPCHK(P, launch_chol_inv(P->st, k, n, P->d_G, k, P->d_M, k, P->d_flag));
     int flag = 0;
     HIPCHK(P, hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, P->st));
-    if (mtot)
-      HIPCHK(P, hipMemcpyAsync(hm.data(), P->d_M, hm.size() * sizeof(double),
-                               hipMemcpyDeviceToHost, P->st));
     HIPCHK(P, hipStreamSynchronize(P->st));
     if (flag == 2) {
       if (info) *info = 2;
-      return RAFEAST_OK;  // Y keeps the last good pass
+      return RAFEAST_OK;  // Y (and d_mtot) keep the last good pass
     }
     if (flag == 1 && pass == 0) passes = 3;
     worst = std::max(worst, flag);
-    if (mtot) {  // mtot <- mtot * M of this pass (sums over t in increasing order)
-      std::fill(prod.begin(), prod.end(), 0.0);
-      for (int r = 0; r < k; ++r)
-        for (int t = 0; t < k; ++t) {
-          const double a = (*mtot)[(size_t)r * k + t];
-          const double* hr = &hm[(size_t)t * k];
-          double* pr = &prod[(size_t)r * k];
-          for (int c = 0; c < k; ++c) pr[c] += a * hr[c];
-        }
-      mtot->swap(prod);
+    if (track) {
+      if (pass == 0) {
+        HIPCHK(P, hipMemcpyAsync(P->d_mtot, P->d_M, (size_t)k * k * sizeof(double),
+                                 hipMemcpyDeviceToDevice, P->st));
+      } else {
+        HIPCHK(P, launch_tsmm(P->st, k, k, k, P->d_mtot, k, P->d_M, k, P->d_mtmp, k));
+        std::swap(P->d_mtot, P->d_mtmp);
+      }
     }
     HIPCHK(P, launch_tsmm(P->st, n, k, k, Y, ldy, P->d_M, k, tmp, ldt));
     HIPCHK(P, launch_copy_cols(P->st, n, k, tmp, ldt, Y, ldy));
@@ -725,30 +723,23 @@ rafeast_status rayleigh_ritz(rafeast_plan_s* P, std::vector<double>& theta,
                            P->st));
   HIPCHK(P, hipMemcpyAsync(res.data(), P->d_res, m0 * sizeof(double), hipMemcpyDeviceToHost,
                            P->st));
-  std::vector<double> S;
-  if (P->have_filter) {
-    S.resize((size_t)m0 * m0);
-    HIPCHK(P, hipMemcpyAsync(S.data(), P->d_S, S.size() * sizeof(double), hipMemcpyDeviceToHost,
-                             P->st));
-  }
-  HIPCHK(P, hipStreamSynchronize(P->st));
   // filter gain of each Ritz vector q_i = Q~ y_i, y_i = mtot S e_i, of the
   // orthonormal block Q_prev that Q~ filtered: mu_i = 1 / ||y_i|| =
-  // ||rho(A) Q_prev y_i|| / ||Q_prev y_i||; 1 before the first filter step
+  // ||rho(A) Q_prev y_i|| / ||Q_prev y_i||; 1 before the first filter step.
+  // Y = mtot S on the device; its column norms on the host.
+  std::vector<double> Yh;
+  if (P->have_filter) {
+    HIPCHK(P, launch_tsmm(P->st, m0, m0, m0, P->d_mtot, m0, P->d_S, m0, P->d_mtmp, m0));
+    Yh.resize((size_t)m0 * m0);
+    HIPCHK(P, hipMemcpyAsync(Yh.data(), P->d_mtmp, Yh.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, P->st));
+  }
+  HIPCHK(P, hipStreamSynchronize(P->st));
   mu.assign(m0, 1.0);
   if (P->have_filter) {
-    // Y = Mt S row by row (sums over t in increasing order), then column norms
-    const std::vector<double>& Mt = P->mtot;
-    std::vector<double> ss(m0, 0.0), yr(m0);
-    for (int r = 0; r < m0; ++r) {
-      std::fill(yr.begin(), yr.end(), 0.0);
-      for (int t = 0; t < m0; ++t) {
-        const double a = Mt[(size_t)r * m0 + t];
-        const double* sr = &S[(size_t)t * m0];
-        for (int i = 0; i < m0; ++i) yr[i] += a * sr[i];
-      }
-      for (int i = 0; i < m0; ++i) ss[i] += yr[i] * yr[i];
-    }
+    std::vector<double> ss(m0, 0.0);
+    for (int r = 0; r < m0; ++r)
+      for (int i = 0; i < m0; ++i) ss[i] += Yh[(size_t)r * m0 + i] * Yh[(size_t)r * m0 + i];
     for (int i = 0; i < m0; ++i) mu[i] = ss[i] > 0.0 ? 1.0 / std::sqrt(ss[i]) : 0.0;
   }
   return RAFEAST_OK;
@@ -974,7 +965,7 @@ rafeast_status solve_combine(rafeast_plan_s* P, SolveRun& S) {
   HIPCHK(P, hipEventRecord(P->ev[4], P->st));
   std::swap(P->d_Q, P->d_Y);
   int ci = 0;
-  RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld, &P->mtot));
+  RCHK(cholqr2(P, n, m0, P->d_Q, ld, &ci, P->d_T, ld, true));
   P->have_filter = ci != 2;
   HIPCHK(P, hipEventRecord(P->ev[5], P->st));
   HIPCHK(P, hipEventSynchronize(P->ev[5]));
@@ -1550,6 +1541,8 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
   PRCHK(dalloc(P, &P->d_theta, kMaxSmallK, "theta"));
   PRCHK(dalloc(P, &P->d_res, kMaxSmallK, "res"));
   PRCHK(dalloc(P, &P->d_qn, kMaxSmallK, "qn"));
+  PRCHK(dalloc(P, &P->d_mtot, (size_t)P->m0 * P->m0, "mtot"));
+  PRCHK(dalloc(P, &P->d_mtmp, (size_t)P->m0 * P->m0, "mtot product"));
   PRCHK(dalloc(P, &P->d_gamma, 2 * (size_t)P->nc * P->m0, "gamma"));
   PRCHK(dalloc(P, &P->d_info, 4, "info"));
   PRCHK(dalloc(P, &P->d_zw, 4 * P->nc, "zw"));

@@ -100,7 +100,7 @@ def test_dense_products(gpu_lib, name):
     with _plan(gpu_lib, fx, data) as plan:
         plan.spmm(X, Y, alpha=0.5, beta=-2.0)
         got = Y.cpu().numpy()
-    want = 0.5 * (A @ Xh) - 2.0 * Yh
+    want = 0.5 * (A @ Xh) - 2.0 * Xh  # Y = alpha A X + beta X; Y's old values unused
     # both sides round inner products of length m (gamma_m = m u bounds
     # each): m = n with |K| |X| for the kernel; X^T (X V) / (rows - 1) with
     # m = rows + p and |X|^T (|X| |V|) / (rows - 1) for the covariance
@@ -111,7 +111,7 @@ def test_dense_products(gpu_lib, name):
     else:
         m = n
         mag = np.abs(A) @ np.abs(Xh)
-    bound = 2 * m * u * 0.5 * mag + 4 * u * (0.5 * np.abs(A @ Xh) + 2.0 * np.abs(Yh))
+    bound = 2 * m * u * 0.5 * mag + 4 * u * (0.5 * np.abs(A @ Xh) + 2.0 * np.abs(Xh))
     assert np.all(np.abs(got - want) <= bound)
 
 
