@@ -115,6 +115,7 @@ def gram_shapes(reps=5):
     for k in (84, 192):
         X = torch.randn((csr.n, k), dtype=torch.float64, device="cuda")
         G = torch.empty((k, k), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()  # the plan runs on a stream of its own
         plan.gram(X, X, G)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -128,6 +129,7 @@ def gram_shapes(reps=5):
                                  flops=2.0 * csr.n * k * k, rel_diff_vs_torch=err)
         del X, G
     Y = torch.randn((csr.n, 84), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     plan.cholqr2(Y)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -77,6 +77,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing; build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime: load it first so that the library binds
+    # to the same one (a second runtime in the process sees no device)
+    import torch  # noqa: F401
+
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     dp = C.POINTER(C.c_double)
