@@ -290,6 +290,25 @@ rafeast_status rafeast_gram(rafeast_plan_t plan, int64_t n, int32_t k1, int32_t 
                             const double* X, int32_t ldx, const double* Y, int32_t ldy,
                             double* G, int32_t ldg);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the Gram
+ * product of rafeast_gram without a plan and without any allocation.
+ * G = X^T Y (k1 x k2 row-major, ldg >= k2) for device arrays X (n x k1, ldx)
+ * and Y (n x k2, ldy), FP64, enqueued on hip_stream (NULL: the null stream)
+ * of the current device; the call returns after enqueueing and does not
+ * wait.  The row-chunk partial sums go to a fixed scratch array of 2^21
+ * doubles (16 MiB) that the library holds on each device it runs on until
+ * the process ends: k1 * k2 must not exceed 2^21 (INVALID_ARG otherwise,
+ * text in rafeast_last_error(NULL)); it uses as many row chunks as
+ * rafeast_gram when they fit (then the results are identical), fewer
+ * otherwise.  Every call on a device shares that device's scratch, so calls
+ * that overlap on one device (concurrent streams or threads) race; serialise
+ * them.  Errors: INVALID_ARG for null pointers, n < 1, k1 < 1, k2 < 1 or
+ * ld < k; DEVICE for a HIP error. */
+rafeast_status rafeast_gram_noalloc(void* hip_stream, int64_t n, int32_t k1, int32_t k2,
+                                    const double* X, int32_t ldx, const double* Y, int32_t ldy,
+                                    double* G, int32_t ldg);
+
 /* CholQR2 of an n x k block in place (Y <- Y R^{-1}, twice), k <= 192, with
  * column scaling; when the first Cholesky fails, the shifted variant is used
  * and a third pass added.  *info (host, nullable): 0 plain, 1 shifted,

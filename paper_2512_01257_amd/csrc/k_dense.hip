@@ -276,8 +276,15 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int chunks, int k1, int k2,
 
 hipError_t launch_gram(hipStream_t st, int64_t n, int k1, int k2, const double* X, int ldx,
                        const double* Y, int ldy, double* G, int ldg, double* part) {
+  return launch_gram_chunks(st, n, k1, k2, X, ldx, Y, ldy, G, ldg, part, gram_chunks(n));
+}
+
+hipError_t launch_gram_chunks(hipStream_t st, int64_t n, int k1, int k2, const double* X,
+                              int ldx, const double* Y, int ldy, double* G, int ldg, double* part,
+                              int chunks) {
   if (k1 <= 0 || k2 <= 0) return hipSuccess;
-  const int chunks = gram_chunks(n);
+  if (chunks < 1) chunks = 1;
+  if (chunks > gram_chunks(n)) chunks = gram_chunks(n);
   int64_t rpc = (n + chunks - 1) / chunks;
   rpc = (rpc + 3) & ~int64_t(3);
   const int ta_n = (k1 + 15) / 16, tb_n = (k2 + 15) / 16;

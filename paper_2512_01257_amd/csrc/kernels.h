@@ -25,6 +25,11 @@ size_t gram_partial_doubles(int64_t n, int k1, int k2);
 // G = X^T Y; `part` holds gram_partial_doubles(n, k1, k2) doubles.
 hipError_t launch_gram(hipStream_t st, int64_t n, int k1, int k2, const double* X, int ldx,
                        const double* Y, int ldy, double* G, int ldg, double* part);
+// The same with an explicit number of row chunks (clamped to [1, gram_chunks(n)]);
+// `part` holds chunks * k1 * k2 doubles.
+hipError_t launch_gram_chunks(hipStream_t st, int64_t n, int k1, int k2, const double* X,
+                              int ldx, const double* Y, int ldy, double* G, int ldg, double* part,
+                              int chunks);
 // Y = X S, X n x k, S k x k2 (row-major, lds), Y n x k2.  Y must not alias X.
 hipError_t launch_tsmm(hipStream_t st, int64_t n, int k, int k2, const double* X, int ldx,
                        const double* S, int lds, double* Y, int ldy);

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1786,6 +1787,67 @@ rafeast_status rafeast_gram(rafeast_plan_t P, int64_t n, int32_t k1, int32_t k2,
   if (e == hipSuccess) e = hipStreamSynchronize(P->st);
   (void)hipFree(part);
   HIPCHK(P, e);
+  return RAFEAST_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Gram product without allocation.  The row-chunk partial sums live in a
+// file-scope device array of fixed size; each device holds its own copy at
+// its own address, which hipGetSymbolAddress returns once per device (in host
+// code the array's name is not a device address).
+// ----------------------------------------------------------------------------
+constexpr size_t kGramScratchDoubles = size_t(1) << 21;  // 16 MiB per device
+static __device__ __align__(256) double scratch[kGramScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on the current device (resolved on the first
+// call made with that device current).
+hipError_t gram_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+rafeast_status rafeast_gram_noalloc(void* hip_stream, int64_t n, int32_t k1, int32_t k2,
+                                    const double* X, int32_t ldx, const double* Y, int32_t ldy,
+                                    double* G, int32_t ldg) {
+  if (!X || !Y || !G || n < 1 || k1 < 1 || k2 < 1 || ldx < k1 || ldy < k2 || ldg < k2)
+    return fail(nullptr, RAFEAST_INVALID_ARG, "rafeast_gram_noalloc: bad argument");
+  const size_t tile = (size_t)k1 * (size_t)k2;
+  if (tile > kGramScratchDoubles)
+    return fail(nullptr, RAFEAST_INVALID_ARG,
+                "rafeast_gram_noalloc: k1 * k2 = " + std::to_string(tile) +
+                    " exceeds the scratch of " + std::to_string(kGramScratchDoubles) +
+                    " doubles");
+  double* part = nullptr;
+  hipError_t e = gram_scratch(&part);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "rafeast_gram_noalloc: scratch address");
+  // as many row chunks as rafeast_gram uses when they fit, fewer otherwise
+  const int chunks = (int)std::min<size_t>((size_t)gram_chunks(n), kGramScratchDoubles / tile);
+  e = launch_gram_chunks(static_cast<hipStream_t>(hip_stream), n, k1, k2, X, ldx, Y, ldy, G, ldg,
+                         part, chunks);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "rafeast_gram_noalloc: launch");
   return RAFEAST_OK;
 }
 

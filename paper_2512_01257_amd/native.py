@@ -145,6 +145,9 @@ def lib():
     L.rafeast_gram.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int32, P, C.c_int32,
                                P, C.c_int32]
     L.rafeast_gram.restype = C.c_int
+    L.rafeast_gram_noalloc.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int32, P,
+                                       C.c_int32, P, C.c_int32]
+    L.rafeast_gram_noalloc.restype = C.c_int
     L.rafeast_cholqr2.argtypes = [P, C.c_int64, C.c_int32, P, C.c_int32, C.POINTER(C.c_int32)]
     L.rafeast_cholqr2.restype = C.c_int
     L.rafeast_syev.argtypes = [P, C.c_int32, P, P, P]
@@ -190,6 +193,25 @@ def _tptr(t, dtype=None):
     if dtype is not None and t.dtype != dtype:
         raise ValueError(f"expected {dtype}, got {t.dtype}")
     return C.c_void_p(t.data_ptr())
+
+
+def gram_noalloc(X, Y, G, stream=None, n=None, k1=None, k2=None):
+    """G = X^T Y through rafeast_gram_noalloc (no plan, no device allocation),
+    enqueued on `stream` (a torch stream; None: the current stream) without
+    waiting.  X, Y, G: contiguous float64 device tensors (n x k1, n x k2,
+    k1 x k2); n, k1, k2 override the sizes (for host-side argument checks)."""
+    import torch
+
+    st = stream if stream is not None else torch.cuda.current_stream()
+    n = X.shape[0] if n is None else n
+    k1 = X.shape[1] if k1 is None else k1
+    k2 = Y.shape[1] if k2 is None else k2
+    s = lib().rafeast_gram_noalloc(C.c_void_p(st.cuda_stream), n, k1, k2,
+                                   _tptr(X, torch.float64), X.stride(0),
+                                   _tptr(Y, torch.float64), Y.stride(0),
+                                   _tptr(G, torch.float64), G.stride(0))
+    if s != 0:
+        raise RafeastError(s, lib().rafeast_last_error(None).decode())
 
 
 def rcm_order(csr):
