@@ -826,6 +826,15 @@ def main():
         if tj.get("kernel_source_sha") == native.kernel_source_sha("k_cocg.hip"):
             traffic = tj.get("bytes_per_launch")
 
+    onchip = None
+    ofile = os.path.join(ROOT, "profiles", "cocg_resident_knn8000_onchip.txt")
+    if os.path.exists(ofile):
+        with open(ofile) as f:
+            oj = json.load(f)
+        if oj.get("kernel_source_sha") == native.kernel_source_sha("k_cocg.hip"):
+            onchip = {k: oj[k] for k in ("cu_busy_frac_over_step", "l2_read_bytes_per_launch_128B",
+                                         "l2_port_frac_while_busy", "l2_port_frac_over_launch")}
+
     phases = {k: round(v / args.steps, 3) for k, v in ph_ra.items() if k.endswith("_ms")}
     line = {
         "metric": "eigenpairs/s at rel. residual 1e-10, RA-FEAST vs plain FEAST; SpMM HBM GB/s",
@@ -876,6 +885,7 @@ def main():
             "avg_launch_ms": round(avg_launch_s * 1e3, 4),
             "column_iterations_per_launch": round(coliters_per_launch, 1),
             "l2_bytes_per_launch": l2_bytes_per_launch,
+            "onchip_counters": onchip,
             "hbm_measured_frac": None if traffic is None else round(
                 traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4),
             "hbm_streaming_equivalent": {
