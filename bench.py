@@ -342,7 +342,8 @@ def main_learned(args):
             Xs.append(X), Gs.append(G), hs.append(h), rrs.append(rr)
         X, G, h, rr = (torch.cat(t) for t in (Xs, Gs, hs, rrs))
         ns = X.shape[0]
-        W = torch.from_numpy(flatten(init_weights(1))).cuda()
+        W = torch.from_numpy(flatten(init_weights(1, out_scale=0.0))).cuda()
+        pt.pc_normalize(X, W)
         _, loss0 = pt.pc_gradient(X, G, h, rr, W)
         order = minibatch_order(ns, 200, 2)
         pt.pc_train(X, G, h, rr, W, order, batch=64, lr=2e-3)
@@ -362,7 +363,7 @@ def main_learned(args):
         z = plan.info()["z"]
         Xf = torch.from_numpy(features(plan, z, 1e-3, te["u"])).cuda()
         Y = plan.pc_forward(Xf, W).cpu().numpy().astype(np.float64)
-        coef = Y[:, 0::2] + 1j * Y[:, 1::2]
+        coef = (Y[:, 0::2] + 1j * Y[:, 1::2]) / Xf.cpu().numpy()[:, 1:2]  # c = y / Im z^
         B = torch.from_numpy(np.ascontiguousarray(residual_samples(csr.n, nrhs, 23))).cuda()
         out = {}
         for name, cf in (("plain", None), ("learned", coef)):

@@ -84,6 +84,12 @@ enum { RAFEAST_ENGINE_AUTO = 0,
        RAFEAST_ENGINE_STREAM = 2 };  /* all systems in lock step, vectors in HBM, rows
                                         reordered by reverse Cuthill-McKee */
 
+/* rafeast_params.precond: preconditioner of the shifted solves. */
+enum { RAFEAST_PC_NONE = 0,       /* unpreconditioned COCG on the plan's engine */
+       RAFEAST_PC_LEARNED = 1 };  /* FP64 COCG preconditioned by the learned polynomial
+                                     p_j(A) ~ (z_j I - A)^{-1} (weights from
+                                     rafeast_pc_attach); plain COCG is the fallback */
+
 /* rafeast_result.flags */
 enum { RAFEAST_PTR_DEVICE = 1 };  /* lambda/resid/X are device pointers */
 
@@ -132,16 +138,32 @@ typedef struct rafeast_params {
                               not below tol_solve.  Needs rhs_form RESIDUAL, whose solve
                               error scales with the Ritz residual (a literal-form solve
                               error sets a floor near the tolerance) */
+  int32_t precond;         /* RAFEAST_PC_NONE | RAFEAST_PC_LEARNED.  LEARNED (CSR plans
+                              only): in every FEAST iteration the library forms each node's
+                              features (Re z^_j, Im z^_j, theta^_lo, theta^_hi) from the
+                              current Ritz values, evaluates the attached network for the
+                              coefficients of p_j, and solves all (node, column) systems by
+                              FP64 COCG preconditioned with p_j(A), to the true residual
+                              ||b - (z_j I - A) x|| <= tol ||b||.  A system that does not
+                              reach it (iteration budget, breakdown) is solved again by
+                              plain FP64 COCG (counted in rafeast_result.pc_fallbacks) */
 } rafeast_params;
 
 /* Phase-1 diagnostics (Remark 1's post-hoc check of the power-count condition,
- * eq. power-cond): op-Ritz estimates of beta_{m0}, beta_{m0+1}. */
+ * eq. power-cond): op-Ritz estimates of beta_{m0}, beta_{m0+1}, and the
+ * warmstart error bound of Theorem 1 evaluated with them. */
 typedef struct rafeast_ws_info {
   double beta_m0;
   double beta_m0p1;        /* NaN when p == 0 */
   double ratio;            /* (beta_m0p1 / beta_m0)^(2q+1) */
   int32_t op;              /* the RAFEAST_WS_* operator actually used */
   double t_ms;             /* device time of Phase 1 */
+  double r_halko;          /* eq. R-Halko at failure probability delta = 0.01:
+                              C1 sqrt(1 + m0/(p-1)) beta_m0p1 (beta_m0p1/beta_m0)^(2q),
+                              C1 = 1 + (p/2) ln(2 m0 / delta); NaN when p < 2 */
+  double gap;              /* delta_gap = beta_m0 - beta_m0p1 (eq. gap-def) */
+  double proj_bound;       /* r_halko / gap, the bound on ||P - P~||_2 of Theorem 1
+                              (eq. warmstart-error); Remark 1 asks for <= 1/2 */
 } rafeast_ws_info;
 
 typedef struct rafeast_result {
@@ -160,12 +182,17 @@ typedef struct rafeast_result {
   double t_ms[RAFEAST_NPHASE]; /* out: device time per phase (HIP events) */
   double tol_solve_last;   /* out: COCG tolerance of the last filter application
                               (the starting one when none ran) */
+  int64_t cocg_node[64];   /* out: COCG iterations per quadrature node (first nc entries,
+                              in the node order of rafeast_plan_info), summed over columns
+                              and FEAST iterations; preconditioned iterations count once */
+  int32_t pc_fallbacks;    /* out: systems re-solved by plain COCG after the learned
+                              preconditioner missed the tolerance (precond LEARNED) */
 } rafeast_result;
 
 /* Fills *p with defaults: m0 = 0 (must be set), nc = 8, q = 2, p = -1,
  * tol_eig = 1e-10, tol_solve = 1e-6, max_iter = 20, max_cocg = 20000,
  * precision FP32_REFINED, ws_op AUTO, rhs_form RESIDUAL, engine AUTO, seed 0,
- * tol_solve_relaxed 0 (fixed tolerance). */
+ * tol_solve_relaxed 0 (fixed tolerance), precond NONE. */
 void rafeast_params_default(rafeast_params* p);
 
 /* Validates A and the parameters, copies A to the device (FP64 values plus an
@@ -400,14 +427,27 @@ const char* rafeast_batch_last_error(rafeast_batch_t batch);
  * The coefficients come from a network 4 -> 64 -> 64 -> 64 -> 16 (exact
  * GELU on the hidden layers) of the features (Re z^, Im z^, theta^_lo,
  * theta^_hi): the shift and the smallest and largest current Ritz values,
- * mapped like A.  Outputs are (Re c_0, Im c_0, ..., Re c_7, Im c_7).
+ * mapped like A.  The 16 outputs y are the coefficients scaled by the
+ * shift's distance from the real axis: c_k = (y_2k + i y_2k+1) / Im z^ (the
+ * coefficients of a good p grow like 1 / Im z^; scaled they are O(1)).
  * Parameters: rafeast_pc_param_count() floats, per layer W (out x in,
  * row-major) then b; used in BF16 (round to nearest even) with FP32 sums,
  * trained in FP32.  All arrays below are device pointers unless marked host.
  * ------------------------------------------------------------------------- */
 
-/* Number of network parameters (9680). */
+/* Number of network parameters (9688): the 9680 weights and biases, then
+ * the input standardization mu[4], sd[4]: each feature x_f enters the network
+ * as (x_f - mu_f) / sd_f, in FP64 before the BF16 rounding of the inputs
+ * (the mapped features of a window at the end of a wide spectrum differ by
+ * less than a BF16 ulp); mu = 0, sd = 1 is the identity. */
 int32_t rafeast_pc_param_count(void);
+
+/* Sets the input standardization of W (device, rafeast_pc_param_count()
+ * FP32) to the mean and standard deviation of each feature over the ns rows
+ * X (device, ns x 4 FP64); sd = 1 for a feature whose standard deviation is
+ * at most 1e-9 max(1, |mean|) (constant up to rounding).  Call before
+ * rafeast_pc_train, which leaves it unchanged.  Errors: INVALID_ARG. */
+rafeast_status rafeast_pc_normalize(rafeast_plan_t plan, int32_t ns, const double* X, float* W);
 
 /* Training samples from k real residual vectors R (n x k FP64, row-major,
  * ldr) at nz shifts z (host, 2*nz): sample s = j*k + i has features X[s][4],
@@ -419,24 +459,51 @@ rafeast_status rafeast_pc_samples(rafeast_plan_t plan, int32_t nz, const double*
                                   const double* R, int32_t ldr, double theta_lo, double theta_hi,
                                   double* X, double* G, double* h, double* rr);
 
-/* Network outputs Y[s][16] (FP32) of features X[s][4] for s < ns; W: FP32
- * parameters (used in BF16). */
+/* Network outputs Y[s][16] (FP32, the scaled coefficients y; c = y / X[s][1]
+ * as above) of features X[s][4] for s < ns; W: FP32 parameters (used in BF16). */
 rafeast_status rafeast_pc_forward(rafeast_plan_t plan, int32_t ns, const double* X, const float* W,
                                   float* Y);
 
 /* Gradient grad[rafeast_pc_param_count()] (FP32) of the mean loss over the
- * ns samples at parameters W; loss: nullable host, the mean loss. */
+ * ns samples at parameters W (zero for the standardization); loss: nullable
+ * host, the mean loss. */
 rafeast_status rafeast_pc_gradient(rafeast_plan_t plan, int32_t ns, const double* X,
                                    const double* G, const double* h, const double* rr,
                                    const float* W, float* grad, double* loss);
 
-/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on W in place for
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on the weights of W
+ * (not the standardization) in place for
  * `steps` minibatches of `batch` samples; order: host [steps * batch]
  * sample indices (< ns).  loss: nullable host [steps], each minibatch's mean
  * loss before its step. */
 rafeast_status rafeast_pc_train(rafeast_plan_t plan, int32_t ns, const double* X, const double* G,
                                 const double* h, const double* rr, float* W, int32_t steps,
                                 int32_t batch, const int32_t* order, float lr, double* loss);
+
+/* Training samples from the solver's own residuals: the COCG residual
+ * vectors of the plan's shifted systems.  The right-hand sides are the Ritz
+ * residual block R = A Q - Q Theta of the plan's last Rayleigh-Ritz step
+ * (k = m0 columns: the end of the last rafeast_solve, e.g. one run with
+ * max_iter 0 or 1), at the plan's quadrature nodes (in the order of
+ * rafeast_plan_info).  For each of the nsteps counts s = steps[t] >= 0, plain
+ * FP64 COCG runs exactly s iterations on all nc * m0 systems, and every
+ * residual vector r of node j gives samples at that node's shift z_j (as
+ * rafeast_pc_samples, features with theta_lo, theta_hi the smallest and
+ * largest Ritz values of that step): s = 0 gives the m0 real right-hand
+ * sides per node, s > 0 the real and the imaginary part of each complex
+ * residual (2 m0 per node).  X[4], G[8][8] complex, h[8] complex, rr per
+ * sample: caller-owned device buffers with room for
+ * sum_t (steps[t] == 0 ? 1 : 2) * nc * m0 samples; *count (host) receives
+ * the number written.  Errors: INVALID_ARG (null pointers, nsteps < 1, a
+ * negative step, or no Rayleigh-Ritz step yet), UNSUPPORTED for dense plans. */
+rafeast_status rafeast_pc_harvest(rafeast_plan_t plan, int32_t nsteps, const int32_t* steps,
+                                  double* X, double* G, double* h, double* rr, int32_t* count);
+
+/* Attaches network parameters W (device, rafeast_pc_param_count() FP32
+ * values, as trained by rafeast_pc_train) to the plan: the plan copies them
+ * and keeps a BF16 copy for the solves with precond LEARNED.  Errors:
+ * INVALID_ARG for null pointers, UNSUPPORTED for dense plans. */
+rafeast_status rafeast_pc_attach(rafeast_plan_t plan, const float* W);
 
 /* COCG in FP64 for (z_j I - A) X_{j,c} = B_c (nz shifts, k right-hand
  * sides, B n x k FP64 row-major, ldb), preconditioned by p(A) with coef

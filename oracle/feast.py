@@ -266,6 +266,11 @@ def warmstart(A, lmin, lmax, m0, Omega, q, ws_op="auto", bounds=None):
     info = dict(op=name, beta_m0=float(f[order[m0 - 1]]),
                 beta_m0p1=float(f[order[m0]]) if len(f) > m0 else float("nan"),
                 theta=theta, phi=f)
+    p = Omega.shape[1] - m0
+    info["gap"] = info["beta_m0"] - info["beta_m0p1"]
+    info["r_halko"] = (float(r_halko(info["beta_m0"], info["beta_m0p1"], m0, p, q))
+                       if p >= 2 else float("nan"))
+    info["proj_bound"] = info["r_halko"] / info["gap"] if info["gap"] > 0 else float("nan")
     return Q0, info
 
 
@@ -277,6 +282,16 @@ def ra_feast(A, lmin, lmax, m0, nc, Omega, q, tol=1e-10, max_iter=20,
     out["ws_info"] = info
     out["Q0"] = Q0
     return out
+
+
+def r_halko(beta_m0, beta_m0p1, m0: int, p: int, q: int, delta: float = 0.01):
+    """R_Halko of the randomized range-finder lemma (eq. R-Halko):
+    C1(delta) sqrt(1 + m0/(p-1)) beta_{m0+1} (beta_{m0+1}/beta_{m0})^(2q), with
+    C1(delta) = 1 + (p/2) ln(2 m0 / delta).  Theorem 1 bounds the warmstart's
+    projector error by R_Halko / delta_gap, delta_gap = beta_m0 - beta_{m0+1}
+    (eq. gap-def), with probability at least 1 - delta."""
+    c1 = 1.0 + 0.5 * p * np.log(2.0 * m0 / delta)
+    return c1 * np.sqrt(1.0 + m0 / (p - 1.0)) * beta_m0p1 * (beta_m0p1 / beta_m0) ** (2 * q)
 
 
 def default_oversampling(m0: int) -> int:

@@ -16,8 +16,9 @@ them with a polynomial preconditioner p(A) ~ (zI - A)^{-1}:
   The loss of coefficients c is ||(zI - A) p(A) r - r||^2 / ||r||^2
   = (c^H G c - 2 Re(c^H h) + rr) / rr, minimised by c* = G^{-1} h.
 * Coefficient network: features x = (Re z^, Im z^, theta^_lo, theta^_hi) (the
-  mapped shift and the mapped smallest and largest current Ritz values)
-  -> 4 x 64 x 64 x 64 x 16 MLP with exact GELU (x Phi(x)) on the hidden
+  mapped shift and the mapped smallest and largest current Ritz values),
+  standardized as (x - mu) / sd with the training set's mean and standard
+  deviation, -> 4 x 64 x 64 x 64 x 16 MLP with exact GELU (x Phi(x)) on the hidden
   layers -> outputs (Re c_0, Im c_0, ..., Re c_7, Im c_7).
 * Preconditioned COCG: COCG on (zI - A) x = b with the preconditioner p(A):
   rho = r^T p(A) r, the search direction from p(A) r.
@@ -96,10 +97,13 @@ def gelu_grad(x):
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2 * math.pi)
 
 
-def mlp_forward(params, X):
+def mlp_forward(params, X, norm=None):
     """Outputs Y (N x 16) of features X (N x 4); params = [(W, b)] with W
-    (out x in).  Returns (Y, cache) with the pre-activations for backward."""
+    (out x in); norm = (mu, sd): the network sees (X - mu) / sd (None: X).
+    Returns (Y, cache) with the pre-activations for backward."""
     H = np.asarray(X, dtype=np.float64)
+    if norm is not None:
+        H = (H - np.asarray(norm[0], dtype=np.float64)) / np.asarray(norm[1], dtype=np.float64)
     cache = []
     for l, (W, b) in enumerate(params):
         Zp = H @ np.asarray(W, dtype=np.float64).T + np.asarray(b, dtype=np.float64)
@@ -122,27 +126,31 @@ def mlp_backward(params, cache, dY):
     return grads
 
 
-def coeffs(Y):
-    """Complex coefficients (N x 8) from network outputs (N x 16)."""
+def coeffs(Y, X):
+    """Complex coefficients (N x 8) from network outputs Y (N x 16) of
+    features X (N x 4): c_k = (y_2k + i y_2k+1) / Im z^, the outputs being the
+    coefficients scaled by the shift's distance from the real axis."""
     Y = np.asarray(Y, dtype=np.float64)
-    return Y[:, 0::2] + 1j * Y[:, 1::2]
+    X = np.asarray(X, dtype=np.float64)
+    return (Y[:, 0::2] + 1j * Y[:, 1::2]) / X[:, 1:2]
 
 
-def batch_loss(params, X, G, h, rr):
+def batch_loss(params, X, G, h, rr, norm=None):
     """Mean loss over samples: X (N x 4), G (N x 8 x 8), h (N x 8), rr (N)."""
-    C = coeffs(mlp_forward(params, X)[0])
+    C = coeffs(mlp_forward(params, X, norm)[0], X)
     return float(np.mean([quad_loss(C[s], G[s], h[s], rr[s]) for s in range(len(rr))]))
 
 
-def batch_grad(params, X, G, h, rr):
+def batch_grad(params, X, G, h, rr, norm=None):
     """Gradients of batch_loss: dL/dRe c = 2 Re(Gc - h)/rr, dL/dIm c =
-    2 Im(Gc - h)/rr per sample, averaged, then back through the network."""
-    Y, cache = mlp_forward(params, X)
-    C = coeffs(Y)
+    2 Im(Gc - h)/rr per sample, times dc/dy = 1 / Im z^, averaged, then back
+    through the network."""
+    Y, cache = mlp_forward(params, X, norm)
+    C = coeffs(Y, X)
     N = len(rr)
     dY = np.zeros_like(Y)
     for s in range(N):
-        g = 2.0 * (G[s] @ C[s] - h[s]) / rr[s]
+        g = 2.0 * (G[s] @ C[s] - h[s]) / rr[s] / float(X[s][1])
         dY[s, 0::2] = g.real / N
         dY[s, 1::2] = g.imag / N
     return mlp_backward(params, cache, dY)

@@ -36,6 +36,11 @@ constexpr int kW3 = kB2 + kMlpH, kB3 = kW3 + kMlpH * kMlpH;
 constexpr int kW4 = kB3 + kMlpH, kB4 = kW4 + kMlpOut * kMlpH;
 constexpr int kNPar = kB4 + kMlpOut;
 static_assert(kNPar == 9680, "parameter count");
+// After the trained weights: the input standardization x' = (x - mu) / sd
+// (mu[4], sd[4]), fixed from the training features, never rounded to BF16
+// and never changed by training.
+constexpr int kMu = kNPar, kSd = kNPar + kMlpIn;
+constexpr int kNTot = kNPar + 2 * kMlpIn;
 
 __device__ __forceinline__ float bf16_round(float x) {
   // round to nearest even on the upper 16 bits (finite inputs)
@@ -158,7 +163,7 @@ hipError_t launch_pc_gram_assemble(hipStream_t st, int64_t n, int kc, const doub
 // network
 __global__ void k_to_bf16(int n, const float* __restrict__ w, float* __restrict__ wb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) wb[i] = bf16_round(w[i]);
+  if (i < n) wb[i] = i < kNPar ? bf16_round(w[i]) : w[i];  // the standardization stays FP32
 }
 
 // Forward pass of one sample in one wave; weights wb (BF16 values held in
@@ -174,7 +179,8 @@ __device__ __forceinline__ Fwd mlp_fwd_wave(const float* __restrict__ wb, const 
                                             float (*act)[kMlpH]) {
   const int lane = threadIdx.x & 63;
   Fwd f;
-  if (lane < kMlpIn) act[0][lane] = bf16_round((float)x[lane]);
+  if (lane < kMlpIn)
+    act[0][lane] = bf16_round((float)((x[lane] - (double)wb[kMu + lane]) / (double)wb[kSd + lane]));
   wave_sync();
   float s = wb[kB1 + lane];
   for (int i = 0; i < kMlpIn; ++i) s += wb[kW1 + lane * kMlpIn + i] * act[0][i];
@@ -206,9 +212,9 @@ constexpr int kMlpWaves = 4;
 __global__ __launch_bounds__(256) void k_mlp_forward(int ns, const double* __restrict__ X,
                                                      const float* __restrict__ wb_g,
                                                      float* __restrict__ Y) {
-  __shared__ float wb[kNPar];
+  __shared__ float wb[kNTot];
   __shared__ float act[kMlpWaves][4][kMlpH];
-  for (int i = threadIdx.x; i < kNPar; i += blockDim.x) wb[i] = wb_g[i];
+  for (int i = threadIdx.x; i < kNTot; i += blockDim.x) wb[i] = wb_g[i];
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int s = blockIdx.x * kMlpWaves + wv; s < ns; s += gridDim.x * kMlpWaves) {
@@ -226,10 +232,10 @@ __global__ __launch_bounds__(256) void k_mlp_backward(
     int nb, const int* __restrict__ idx, const double* __restrict__ X,
     const double* __restrict__ G, const double* __restrict__ h, const double* __restrict__ rr,
     const float* __restrict__ wb_g, float* __restrict__ part, double* __restrict__ lpart) {
-  __shared__ float wb[kNPar];
+  __shared__ float wb[kNTot];
   __shared__ float act[kMlpWaves][4][kMlpH];
   __shared__ float dlt[kMlpWaves][kMlpH];
-  for (int i = threadIdx.x; i < kNPar; i += blockDim.x) wb[i] = wb_g[i];
+  for (int i = threadIdx.x; i < kNTot; i += blockDim.x) wb[i] = wb_g[i];
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gw = blockIdx.x * kMlpWaves + wv, nw = gridDim.x * kMlpWaves;
@@ -242,8 +248,11 @@ __global__ __launch_bounds__(256) void k_mlp_backward(
   for (int t = gw; t < nb; t += nw) {
     const int s = idx[t];
     const Fwd f = mlp_fwd_wave(wb, X + (size_t)s * 4, act[wv]);
+    // coefficients c = y / Im z^ (the network predicts c scaled by the
+    // shift's distance from the real axis, an O(1) quantity)
+    const double cs = 1.0 / X[(size_t)s * 4 + 1];
     // loss and dL/dy: lanes k < 8 form (G c - h)_k
-    dlt[wv][lane] = lane < kMlpOut ? f.y : 0.0f;
+    dlt[wv][lane] = lane < kMlpOut ? (float)(f.y * cs) : 0.0f;
     wave_sync();
     const double* Gs = G + (size_t)s * 128;
     const double* hs = h + (size_t)s * 16;
@@ -270,7 +279,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(
     // dL/dy (mean over the minibatch)
     float d4 = 0.0f;
     if (lane < 8) {
-      const double sc = 2.0 / rrs;
+      const double sc = 2.0 / rrs * cs;  // dL/dy = dL/dc / Im z^
       dlt[wv][2 * lane] = (float)((gre - hs[2 * lane]) * sc) * inv;
       dlt[wv][2 * lane + 1] = (float)((gim - hs[2 * lane + 1]) * sc) * inv;
     }
@@ -328,6 +337,8 @@ __global__ void k_mlp_reduce(int nwaves, const float* __restrict__ part, float* 
     float s = 0.0f;
     for (int w = 0; w < nwaves; ++w) s += part[(size_t)w * kNPar + i];
     grad[i] = s;
+  } else if (i < kNTot) {
+    grad[i] = 0.0f;  // the standardization is not trained
   }
   if (i == 0 && loss) {
     double l = 0.0;
@@ -352,7 +363,29 @@ __global__ void k_adam(int n, float* __restrict__ w, float* __restrict__ m, floa
   wb[i] = bf16_round(wi);
 }
 
-int mlp_param_count() { return kNPar; }
+// dst (n x 2k real, row-major) <- the real parts of columns c0..c0+k of the
+// complex block src (n x ld), then their imaginary parts.
+__global__ void k_split_complex(int64_t n, int ld, int c0, int k,
+                                const cpx<double>* __restrict__ src, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * k) return;
+  const int64_t r = e / k;
+  const int i = (int)(e % k);
+  const cpx<double> v = src[r * ld + c0 + i];
+  dst[r * 2 * k + i] = v.re;
+  dst[r * 2 * k + k + i] = v.im;
+}
+
+hipError_t launch_split_complex(hipStream_t st, int64_t n, int ld, int c0, int k,
+                                const cpx<double>* src, double* dst) {
+  const int64_t total = n * k;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_complex, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n,
+                     ld, c0, k, src, dst);
+  return hipGetLastError();
+}
+
+int mlp_param_count() { return kNTot; }
 int mlp_backward_waves(int nb) {
   int w = (nb + 3) / 4;  // about four samples per wave
   if (w > 1024) w = 1024;
@@ -361,7 +394,7 @@ int mlp_backward_waves(int nb) {
 }
 
 hipError_t launch_mlp_bf16(hipStream_t st, const float* w, float* wb) {
-  hipLaunchKernelGGL(k_to_bf16, dim3((kNPar + 255) / 256), dim3(256), 0, st, kNPar, w, wb);
+  hipLaunchKernelGGL(k_to_bf16, dim3((kNTot + 255) / 256), dim3(256), 0, st, kNTot, w, wb);
   return hipGetLastError();
 }
 
@@ -381,7 +414,7 @@ hipError_t launch_mlp_grad(hipStream_t st, int nb, const int* idx, const double*
                      idx, X, G, h, rr, wb, part, lpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((kNPar + 255) / 256), dim3(256), 0, st, waves, part, grad,
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kNTot + 255) / 256), dim3(256), 0, st, waves, part, grad,
                      lpart, nb, loss);
   return hipGetLastError();
 }

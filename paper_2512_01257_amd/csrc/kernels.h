@@ -306,6 +306,10 @@ hipError_t launch_pc_gram_assemble(hipStream_t st, int64_t n, int kc, const doub
                                    const double* zs, double a, double b, double th_lo,
                                    double th_hi, double* part, int nchunks, double* X, double* G,
                                    double* h, double* rr);
+// dst (n x 2k real, row-major) <- Re, then Im, of columns c0..c0+k of the
+// complex FP64 block src (n x ld).
+hipError_t launch_split_complex(hipStream_t st, int64_t n, int ld, int c0, int k,
+                                const cpx<double>* src, double* dst);
 int mlp_param_count();
 int mlp_backward_waves(int nb);
 // wb <- BF16 values (held in FP32) of the FP32 parameters w

@@ -122,6 +122,17 @@ struct rafeast_plan_s {
   // tolerance of Phase 2 while it still contracts)
   double tau = 0.0;
   int ws_used = RAFEAST_WS_NONE;
+  // learned preconditioner inside the solve (precond LEARNED): network
+  // parameters (FP32 and their BF16 values), per-node features and outputs,
+  // and the FP64 solution block the preconditioned solves write
+  float* d_pcW = nullptr;
+  float* d_pcWb = nullptr;
+  double* d_pcX = nullptr;   // nc x 4
+  float* d_pcY = nullptr;    // nc x 16
+  void* d_D64 = nullptr;     // n x (nc m0) complex FP64
+  bool pc_ready = false;
+  // Ritz values of the last Rayleigh-Ritz step (training-sample harvest)
+  std::vector<double> last_theta;
   std::string err;
   hipEvent_t ev[8] = {};
 };
@@ -286,6 +297,10 @@ rafeast_status validate_params(const rafeast_params* p, int64_t n, std::string& 
     msg = "unknown engine";
     return RAFEAST_INVALID_ARG;
   }
+  if (p->precond != RAFEAST_PC_NONE && p->precond != RAFEAST_PC_LEARNED) {
+    msg = "unknown precond";
+    return RAFEAST_INVALID_ARG;
+  }
   return RAFEAST_OK;
 }
 
@@ -388,6 +403,7 @@ rafeast_status dalloc(rafeast_plan_s* P, T** p, size_t count, const char* what) 
 
 void free_plan(rafeast_plan_s* P) {
   if (!P) return;
+  if (P->d_D64 == P->d_D) P->d_D64 = nullptr;  // the FP64 plan's own solve block
   void* ptrs[] = {P->d_rowptr, P->d_col,  P->d_val,   P->d_sbase, P->d_perm, P->d_wtab, P->d_v32,
                   P->d_e64,   P->d_Q,    P->d_W,     P->d_R,     P->d_T,    P->d_Y,
                   P->d_G,      P->d_M,    P->d_S,     P->d_Ssel,  P->d_jw,   P->d_theta,
@@ -395,7 +411,7 @@ void free_plan(rafeast_plan_s* P) {
                   P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
                   P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm,
                   P->d_k64, P->d_k32, P->d_t64, P->d_t32, P->d_ones64, P->d_ones32,
-                  P->d_mtot, P->d_mtmp};
+                  P->d_mtot, P->d_mtmp, P->d_pcW, P->d_pcWb, P->d_pcX, P->d_pcY, P->d_D64};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : P->sbufs)
@@ -852,6 +868,115 @@ int resolve_ws_op(const rafeast_plan_s* P) {
 }
 
 // ----------------------------------------------------------------------------
+// learned polynomial preconditioner: device buffers, spectral map, solver
+// ----------------------------------------------------------------------------
+namespace {
+struct DevBuf {  // device allocations released together
+  std::vector<void*> ptrs;
+  ~DevBuf() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  template <typename T>
+  hipError_t get(T** p, size_t count) {
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, (count ? count : 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(q);
+    *p = (T*)q;
+    return e;
+  }
+};
+
+void spectral_map(const rafeast_plan_s* P, double& a, double& b) {
+  a = 2.0 / (P->sig_hi - P->sig_lo);
+  b = -(P->sig_hi + P->sig_lo) / (P->sig_hi - P->sig_lo);
+}
+
+// FP64 COCG on the nz * k systems (z_j I - A) X[:, j k + i] = B[:, i] in lock
+// step (X n x nz k complex, row-major), preconditioned by p_j(A) with
+// coefficients coef (host [nz][8] complex) or plain (coef null).  iters,
+// resid: nullable host [nz k].
+rafeast_status pc_solve_run(rafeast_plan_s* P, int nz, const double* z, int k, const double* B,
+                            int ldb, const double* coef, void* Xout, double tol, int* iters,
+                            double* resid, int maxit = -1, void* r_out = nullptr) {
+  const int64_t n = P->n;
+  const int Bc = nz * k;
+  DevBuf buf;
+  PcSolve S;
+  S.n = n;
+  S.rowptr = P->d_rowptr;
+  S.col = P->d_col;
+  S.val = P->d_val;
+  spectral_map(P, S.a, S.b);
+  S.Bc = Bc;
+  S.B = B;
+  S.ldb = ldb;
+  S.kb = k;
+  S.tol = tol;
+  S.maxit = maxit >= 0 ? maxit : P->prm.max_cocg;
+  S.num_cu = P->num_cu;
+  S.progress = verbose_log();
+  const size_t blk = (size_t)n * Bc;
+  S.x = (cpx<double>*)Xout;
+  HIPCHK(P, buf.get(&S.r, blk));
+  HIPCHK(P, buf.get(&S.p0, blk));
+  HIPCHK(P, buf.get(&S.p1, blk));
+  HIPCHK(P, buf.get(&S.w, blk));
+  if (coef) {
+    HIPCHK(P, buf.get(&S.u, blk));
+    HIPCHK(P, buf.get(&S.t0, blk));
+    HIPCHK(P, buf.get(&S.t1, blk));
+    HIPCHK(P, buf.get(&S.t2, blk));
+  }
+  double *zc = nullptr, *cf = nullptr;
+  HIPCHK(P, buf.get(&S.part, (size_t)pc_blocks(n, P->num_cu) * Bc * 3));
+  HIPCHK(P, buf.get(&S.counts, 2));
+  HIPCHK(P, buf.get(&zc, 2 * (size_t)Bc));
+  HIPCHK(P, buf.get(&S.cols.active, Bc));
+  HIPCHK(P, buf.get(&S.cols.it, Bc));
+  HIPCHK(P, buf.get(&S.cols.pending, Bc));
+  HIPCHK(P, buf.get(&S.cols.bn2, Bc));
+  HIPCHK(P, buf.get(&S.cols.res, Bc));
+  HIPCHK(P, buf.get(&S.cols.rho, 2 * (size_t)Bc));
+  HIPCHK(P, buf.get(&S.cols.rhon, 2 * (size_t)Bc));
+  HIPCHK(P, buf.get(&S.cols.alpha, 2 * (size_t)Bc));
+  HIPCHK(P, buf.get(&S.cols.beta, 2 * (size_t)Bc));
+  std::vector<double> hz(2 * (size_t)Bc), hc;
+  for (int c = 0; c < Bc; ++c) {
+    hz[2 * c] = z[2 * (c / k)];
+    hz[2 * c + 1] = z[2 * (c / k) + 1];
+  }
+  HIPCHK(P, hipMemcpyAsync(zc, hz.data(), hz.size() * sizeof(double), hipMemcpyHostToDevice,
+                           P->st));
+  S.zc = zc;
+  if (coef) {  // [8][Bc] complex from the per-shift [nz][8] complex
+    hc.resize(16 * (size_t)Bc);
+    for (int t = 0; t < 8; ++t)
+      for (int c = 0; c < Bc; ++c) {
+        hc[(size_t)t * 2 * Bc + 2 * c] = coef[(c / k) * 16 + 2 * t];
+        hc[(size_t)t * 2 * Bc + 2 * c + 1] = coef[(c / k) * 16 + 2 * t + 1];
+      }
+    HIPCHK(P, buf.get(&cf, hc.size()));
+    HIPCHK(P, hipMemcpyAsync(cf, hc.data(), hc.size() * sizeof(double), hipMemcpyHostToDevice,
+                             P->st));
+    S.coef = cf;
+  }
+  HIPCHK(P, run_pc_cocg(P->st, S));
+  if (r_out)
+    HIPCHK(P, hipMemcpyAsync(r_out, S.r, blk * sizeof(cpx<double>), hipMemcpyDeviceToDevice,
+                             P->st));
+  std::vector<int> hit(Bc);
+  std::vector<double> hres(Bc);
+  HIPCHK(P, hipMemcpyAsync(hit.data(), S.cols.it, Bc * sizeof(int), hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipMemcpyAsync(hres.data(), S.cols.res, Bc * sizeof(double), hipMemcpyDeviceToHost,
+                           P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  if (iters) std::memcpy(iters, hit.data(), Bc * sizeof(int));
+  if (resid) std::memcpy(resid, hres.data(), Bc * sizeof(double));
+  return RAFEAST_OK;
+}
+}  // namespace
+
+// ----------------------------------------------------------------------------
 // Phase 2 in steps (one plan, or several in lock step for the batching form)
 // ----------------------------------------------------------------------------
 struct SolveRun {
@@ -863,6 +988,9 @@ struct SolveRun {
   double prev_maxres = 0.0;  // largest counted residual of the previous test (0: none)
   int64_t cocg_sum = 0;
   int cocg_max = 0;
+  std::vector<int64_t> cocg_node;  // per quadrature node, summed over columns and iterations
+  int pc_fallbacks = 0;
+  bool pc_solved = false;          // the last solves ran preconditioned (iters filled on host)
   bool breakdown = false, done = false;
   double t_ph[RAFEAST_NPHASE] = {0, 0, 0, 0, 0};
 };
@@ -897,8 +1025,11 @@ rafeast_status solve_begin(rafeast_plan_s* P, const double* Q_init, SolveRun& S)
   HIPCHK(P, hipMemsetAsync(P->d_stats, 0, 2 * sizeof(int), P->st));
   P->have_filter = false;
   P->tau = std::max(P->prm.tol_solve, P->prm.tol_solve_relaxed);
+  if (P->prm.precond == RAFEAST_PC_LEARNED && !P->pc_ready)
+    return fail(P, RAFEAST_INVALID_ARG, "precond LEARNED needs rafeast_pc_attach first");
   S = SolveRun();
   S.iters.assign(P->nitems, 0);
+  S.cocg_node.assign(P->nc, 0);
   return RAFEAST_OK;
 }
 
@@ -907,6 +1038,7 @@ rafeast_status solve_test(rafeast_plan_s* P, SolveRun& S) {
   const int m0 = P->m0;
   HIPCHK(P, hipEventRecord(P->ev[0], P->st));
   RCHK(rayleigh_ritz(P, S.theta, S.rs, S.mu));
+  P->last_theta = S.theta;
   HIPCHK(P, hipEventRecord(P->ev[1], P->st));
   HIPCHK(P, hipEventSynchronize(P->ev[1]));
   S.t_ph[RAFEAST_PH_RR] += elapsed(P->ev[0], P->ev[1]);
@@ -941,10 +1073,84 @@ rafeast_status solve_test(rafeast_plan_s* P, SolveRun& S) {
   return RAFEAST_OK;
 }
 
+// The shifted solves with the learned preconditioner (precond LEARNED): the
+// features of each node from the current Ritz values, the network's
+// coefficients, FP64 preconditioned COCG on all (node, column) systems into
+// d_D64, and plain FP64 COCG for every system that missed the tolerance by
+// true residual.  Fills S.iters (preconditioned plus fallback iterations).
+rafeast_status solve_learned(rafeast_plan_s* P, SolveRun& S) {
+  const int m0 = P->m0, nc = P->nc, ld = P->ld;
+  const int64_t n = P->n;
+  const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
+  const double* B = residual_form ? P->d_R : P->d_Q;
+  double a = 0.0, b = 0.0;
+  spectral_map(P, a, b);
+  const double th_lo = a * S.theta.front() + b, th_hi = a * S.theta.back() + b;
+  std::vector<double> feat(4 * (size_t)nc);
+  for (int j = 0; j < nc; ++j) {
+    feat[4 * j + 0] = a * P->zw[2 * j] + b;
+    feat[4 * j + 1] = a * P->zw[2 * j + 1];
+    feat[4 * j + 2] = th_lo;
+    feat[4 * j + 3] = th_hi;
+  }
+  std::vector<float> out(16 * (size_t)nc);
+  HIPCHK(P, hipMemcpyAsync(P->d_pcX, feat.data(), feat.size() * sizeof(double),
+                           hipMemcpyHostToDevice, P->st));
+  HIPCHK(P, launch_mlp_forward(P->st, nc, P->d_pcX, P->d_pcWb, P->d_pcY));
+  HIPCHK(P, hipMemcpyAsync(out.data(), P->d_pcY, out.size() * sizeof(float),
+                           hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  // the network predicts the coefficients scaled by Im z^: c = y / Im z^
+  std::vector<double> coef(16 * (size_t)nc);
+  for (size_t t = 0; t < coef.size(); ++t) coef[t] = (double)out[t] / feat[4 * (t / 16) + 1];
+  const int Bc = nc * m0;
+  std::vector<double> res(Bc);
+  RCHK(pc_solve_run(P, nc, P->zw.data(), m0, B, ld, coef.data(), P->d_D64, P->tau, S.iters.data(),
+                    res.data()));
+  // judge by true residual; the systems that missed the tolerance are solved
+  // again by plain FP64 COCG, all misses of one node in one lock-step solve
+  DevBuf fb;
+  for (int j = 0; j < nc; ++j) {
+    std::vector<int> miss;
+    for (int i = 0; i < m0; ++i)
+      if (!(res[(size_t)j * m0 + i] <= P->tau)) miss.push_back(i);
+    if (miss.empty()) continue;
+    const int kf = (int)miss.size();
+    double* Bf = nullptr;
+    cpx<double>* Xf = nullptr;
+    HIPCHK(P, fb.get(&Bf, (size_t)n * kf));
+    HIPCHK(P, fb.get(&Xf, (size_t)n * kf));
+    for (int t = 0; t < kf; ++t)
+      HIPCHK(P, hipMemcpy2DAsync(Bf + t, (size_t)kf * sizeof(double), B + miss[t],
+                                 (size_t)ld * sizeof(double), sizeof(double), (size_t)n,
+                                 hipMemcpyDeviceToDevice, P->st));
+    std::vector<int> it(kf);
+    std::vector<double> r1(kf);
+    RCHK(pc_solve_run(P, 1, P->zw.data() + 2 * j, kf, Bf, kf, nullptr, Xf, P->tau, it.data(),
+                      r1.data()));
+    for (int t = 0; t < kf; ++t) {
+      const int c = j * m0 + miss[t];
+      HIPCHK(P, hipMemcpy2DAsync((cpx<double>*)P->d_D64 + c, (size_t)Bc * sizeof(cpx<double>),
+                                 Xf + t, (size_t)kf * sizeof(cpx<double>), sizeof(cpx<double>),
+                                 (size_t)n, hipMemcpyDeviceToDevice, P->st));
+      S.iters[c] += it[t];
+    }
+    HIPCHK(P, hipStreamSynchronize(P->st));
+    S.pc_fallbacks += kf;
+    if (verbose_log())
+      std::fprintf(stderr, "rafeast: node %d: %d systems solved again without the preconditioner\n",
+                   j, kf);
+  }
+  S.pc_solved = true;
+  return RAFEAST_OK;
+}
+
 // The shifted solves of one plan, for all (node, column) pairs.
-rafeast_status solve_shifted_systems(rafeast_plan_s* P) {
+rafeast_status solve_shifted_systems(rafeast_plan_s* P, SolveRun& S) {
   const int m0 = P->m0, nc = P->nc, ld = P->ld;
   const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
+  S.pc_solved = false;
+  if (P->prm.precond == RAFEAST_PC_LEARNED) return solve_learned(P, S);
   if (P->engine == RAFEAST_ENGINE_STREAM)
     return run_stream(P, P->swork, nc, m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D, nc * m0,
                       P->tau, P->d_iters);
@@ -958,11 +1164,13 @@ rafeast_status solve_combine(rafeast_plan_s* P, SolveRun& S) {
   const int64_t n = P->n;
   const int m0 = P->m0, nc = P->nc, ld = P->ld;
   const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
-  HIPCHK(P, hipMemcpyAsync(S.iters.data(), P->d_iters, P->nitems * sizeof(int),
-                           hipMemcpyDeviceToHost, P->st));
+  if (!S.pc_solved)
+    HIPCHK(P, hipMemcpyAsync(S.iters.data(), P->d_iters, P->nitems * sizeof(int),
+                             hipMemcpyDeviceToHost, P->st));
   HIPCHK(P, launch_gamma(P->st, nc, m0, P->d_zw, P->d_theta, P->d_gamma));
   HIPCHK(P, launch_combine(P->st, n, nc, m0, P->d_gamma, P->d_zw, residual_form, P->d_Q, ld,
-                           P->d_D, nc * m0, P->fp32, P->d_Y, ld));
+                           S.pc_solved ? P->d_D64 : P->d_D, nc * m0,
+                           S.pc_solved ? false : P->fp32, P->d_Y, ld));
   HIPCHK(P, hipEventRecord(P->ev[4], P->st));
   std::swap(P->d_Q, P->d_Y);
   int ci = 0;
@@ -976,9 +1184,11 @@ rafeast_status solve_combine(rafeast_plan_s* P, SolveRun& S) {
   S.t_ph[RAFEAST_PH_ORTH] += elapsed(P->ev[4], P->ev[5]);
   int64_t it_sum = 0;
   int it_max = 0;
-  for (int v : S.iters) {
+  for (size_t c = 0; c < S.iters.size(); ++c) {
+    const int v = S.iters[c];
     it_sum += v;
     it_max = std::max(it_max, v);
+    S.cocg_node[c / m0] += v;
   }
   S.cocg_sum += it_sum;
   S.cocg_max = std::max(S.cocg_max, it_max);
@@ -1042,6 +1252,8 @@ rafeast_status solve_finish(rafeast_plan_s* P, SolveRun& S, rafeast_result* res)
   res->max_resid = S.maxres;
   res->tol_solve_last = P->tau;
   for (int i = 0; i < RAFEAST_NPHASE; ++i) res->t_ms[i] = S.t_ph[i];
+  for (int j = 0; j < 64; ++j) res->cocg_node[j] = j < (int)S.cocg_node.size() ? S.cocg_node[j] : 0;
+  res->pc_fallbacks = S.pc_fallbacks;
   if (stats[1] > 0 && status != RAFEAST_OK)
     P->err = std::to_string(stats[1]) + " COCG systems broke down";
   return status;
@@ -1190,6 +1402,8 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
   const int64_t n = A ? A->n : D->n;
   s = validate_params(prm, n, msg);
   if (s != RAFEAST_OK) return fail(nullptr, s, msg);
+  if (D && prm->precond == RAFEAST_PC_LEARNED)
+    return fail(nullptr, RAFEAST_UNSUPPORTED, "the learned preconditioner takes CSR plans");
   int pov = prm->p;
   if (pov < 0) pov = prm->m0 <= 50 ? 10 : std::min(20, (prm->m0 + 1) / 2);
   int w = (int)std::min<int64_t>((int64_t)prm->m0 + pov, n);
@@ -1554,6 +1768,19 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     hipError_t e = hipMalloc(&P->d_D, (size_t)n * P->nc * P->m0 * cs);
     if (e != hipSuccess) return bail(hip_fail(P, e, "solve block"));
   }
+  if (prm->precond == RAFEAST_PC_LEARNED) {
+    const int npar = mlp_param_count();
+    PRCHK(dalloc(P, &P->d_pcW, (size_t)npar, "network parameters"));
+    PRCHK(dalloc(P, &P->d_pcWb, (size_t)npar, "network BF16 parameters"));
+    PRCHK(dalloc(P, &P->d_pcX, 4 * (size_t)P->nc, "network features"));
+    PRCHK(dalloc(P, &P->d_pcY, 16 * (size_t)P->nc, "network outputs"));
+    if (!fp32) {
+      P->d_D64 = P->d_D;  // the plan's solve block is FP64 already
+    } else {
+      hipError_t e = hipMalloc(&P->d_D64, (size_t)n * P->nc * P->m0 * 2 * sizeof(double));
+      if (e != hipSuccess) return bail(hip_fail(P, e, "FP64 solve block"));
+    }
+  }
   P->nitems = P->nc * P->m0;
   PRCHK(dalloc(P, &P->d_items, 3 * (size_t)P->nitems, "items"));
   PRCHK(dalloc(P, &P->d_counter, 1, "counter"));
@@ -1747,6 +1974,21 @@ rafeast_status rafeast_warmstart(rafeast_plan_t P, const double* omega, double* 
     info->ratio = std::pow(bm1 / bm0, 2.0 * P->prm.q + 1.0);
     info->op = op;
     info->t_ms = elapsed(P->ev[0], P->ev[1]);
+    // Theorem 1 with the Rayleigh-Ritz estimates of beta_m0 and beta_m0+1
+    // (eq. R-Halko with C1(delta) = 1 + (p/2) ln(2 m0 / delta), delta = 0.01)
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    const int q = P->prm.q, pov = P->w - m0;
+    info->gap = bm0 - bm1;
+    if (pov >= 2 && std::isfinite(bm1)) {
+      const double delta = 0.01;
+      const double c1 = 1.0 + 0.5 * pov * std::log(2.0 * m0 / delta);
+      info->r_halko =
+          c1 * std::sqrt(1.0 + (double)m0 / (pov - 1)) * bm1 * std::pow(bm1 / bm0, 2.0 * q);
+      info->proj_bound = info->gap > 0.0 ? info->r_halko / info->gap : nan;
+    } else {
+      info->r_halko = nan;
+      info->proj_bound = nan;
+    }
   }
   return RAFEAST_OK;
 }
@@ -1759,7 +2001,7 @@ rafeast_status rafeast_solve(rafeast_plan_t P, const double* Q_init, rafeast_res
     RCHK(solve_test(P, S));
     if (S.done) break;
     HIPCHK(P, hipEventRecord(P->ev[2], P->st));
-    RCHK(solve_shifted_systems(P));
+    RCHK(solve_shifted_systems(P, S));
     HIPCHK(P, hipEventRecord(P->ev[3], P->st));
     RCHK(solve_combine(P, S));
   }
@@ -2087,6 +2329,11 @@ rafeast_status rafeast_plan_batch(int32_t count, const rafeast_csr* A, const raf
   if (!out) return batch_fail(nullptr, RAFEAST_INVALID_ARG, "null output");
   *out = nullptr;
   if (count < 1 || !A || !prm) return batch_fail(nullptr, RAFEAST_INVALID_ARG, "need count >= 1 and arrays");
+  for (int g = 0; g < count; ++g)
+    if (prm[g].precond != RAFEAST_PC_NONE)
+      return batch_fail(nullptr, RAFEAST_UNSUPPORTED,
+                        "the batching form runs unpreconditioned COCG (member " +
+                            std::to_string(g) + " asks for precond LEARNED)");
   for (int g = 1; g < count; ++g)
     if (prm[g].precision != prm[0].precision || prm[g].tol_solve != prm[0].tol_solve ||
         prm[g].max_cocg != prm[0].max_cocg)
@@ -2238,7 +2485,7 @@ rafeast_status rafeast_batch_solve(rafeast_batch_t B, const double* const* Q_ini
       std::atomic<size_t> next{0};
       auto worker = [&]() {
         for (size_t t = next++; t < todo.size(); t = next++)
-          sst[todo[t]] = solve_shifted_systems(B->plans[todo[t]]);
+          sst[todo[t]] = solve_shifted_systems(B->plans[todo[t]], S[todo[t]]);
       };
       const size_t nthr = std::min<size_t>(todo.size(), kBatchWorkers);
       std::vector<std::thread> pool;
@@ -2303,27 +2550,6 @@ const char* rafeast_batch_last_error(rafeast_batch_t B) {
 // ---------------------------------------------------------------------------
 // learned polynomial preconditioner
 // ---------------------------------------------------------------------------
-namespace {
-struct DevBuf {  // device allocations released together
-  std::vector<void*> ptrs;
-  ~DevBuf() {
-    for (void* q : ptrs) (void)hipFree(q);
-  }
-  template <typename T>
-  hipError_t get(T** p, size_t count) {
-    void* q = nullptr;
-    const hipError_t e = hipMalloc(&q, (count ? count : 1) * sizeof(T));
-    if (e == hipSuccess) ptrs.push_back(q);
-    *p = (T*)q;
-    return e;
-  }
-};
-
-void spectral_map(const rafeast_plan_s* P, double& a, double& b) {
-  a = 2.0 / (P->sig_hi - P->sig_lo);
-  b = -(P->sig_hi + P->sig_lo) / (P->sig_hi - P->sig_lo);
-}
-}  // namespace
 
 extern "C" {
 
@@ -2435,6 +2661,100 @@ rafeast_status rafeast_pc_train(rafeast_plan_t P, int32_t ns, const double* X, c
   return RAFEAST_OK;
 }
 
+rafeast_status rafeast_pc_harvest(rafeast_plan_t P, int32_t nsteps, const int32_t* steps,
+                                  double* X, double* G, double* h, double* rr, int32_t* count) {
+  if (P && P->dop.kind != 0)
+    return fail(P, RAFEAST_UNSUPPORTED, "the learned preconditioner takes CSR plans");
+  if (!P || !X || !G || !h || !rr || !count || nsteps < 1 || !steps) return RAFEAST_INVALID_ARG;
+  for (int t = 0; t < nsteps; ++t)
+    if (steps[t] < 0) return fail(P, RAFEAST_INVALID_ARG, "negative COCG step count");
+  if ((int)P->last_theta.size() != P->m0)
+    return fail(P, RAFEAST_INVALID_ARG, "no Rayleigh-Ritz step yet (run rafeast_solve first)");
+  P->err.clear();
+  *count = 0;
+  const int64_t n = P->n;
+  const int m0 = P->m0, nc = P->nc, Bc = nc * m0;
+  const double th_lo = P->last_theta.front(), th_hi = P->last_theta.back();
+  DevBuf buf;
+  cpx<double>* xs = nullptr;
+  cpx<double>* rs = nullptr;
+  double* split = nullptr;
+  int64_t s0 = 0;  // samples written
+  for (int t = 0; t < nsteps; ++t) {
+    if (steps[t] == 0) {  // the right-hand sides themselves (real)
+      for (int j = 0; j < nc; ++j) {
+        RCHK(rafeast_pc_samples(P, 1, P->zw.data() + 2 * j, m0, P->d_R, P->ld, th_lo, th_hi,
+                                X + 4 * s0, G + 128 * s0, h + 16 * s0, rr + s0));
+        s0 += m0;
+      }
+      continue;
+    }
+    if (!xs) {
+      HIPCHK(P, buf.get(&xs, (size_t)n * Bc));
+      HIPCHK(P, buf.get(&rs, (size_t)n * Bc));
+      HIPCHK(P, buf.get(&split, (size_t)n * 2 * m0));
+    }
+    // exactly steps[t] plain FP64 COCG iterations (a tolerance no residual meets)
+    RCHK(pc_solve_run(P, nc, P->zw.data(), m0, P->d_R, P->ld, nullptr, xs, 1e-300, nullptr,
+                      nullptr, steps[t], rs));
+    for (int j = 0; j < nc; ++j) {
+      HIPCHK(P, launch_split_complex(P->st, n, Bc, j * m0, m0, rs, split));
+      RCHK(rafeast_pc_samples(P, 1, P->zw.data() + 2 * j, 2 * m0, split, 2 * m0, th_lo, th_hi,
+                              X + 4 * s0, G + 128 * s0, h + 16 * s0, rr + s0));
+      s0 += 2 * m0;
+    }
+  }
+  *count = (int32_t)s0;
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_pc_normalize(rafeast_plan_t P, int32_t ns, const double* X, float* W) {
+  if (!P || !X || !W || ns < 1) return RAFEAST_INVALID_ARG;
+  P->err.clear();
+  std::vector<double> hx(4 * (size_t)ns);
+  HIPCHK(P, hipMemcpyAsync(hx.data(), X, hx.size() * sizeof(double), hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  float ms[8];
+  for (int f = 0; f < 4; ++f) {
+    double mean = 0.0;
+    for (int s = 0; s < ns; ++s) mean += hx[4 * (size_t)s + f];
+    mean /= ns;
+    double var = 0.0;
+    for (int s = 0; s < ns; ++s) {
+      const double d = hx[4 * (size_t)s + f] - mean;
+      var += d * d;
+    }
+    const double sd = std::sqrt(var / ns);
+    ms[f] = (float)mean;
+    // a spread at the rounding level of the feature is a constant feature
+    const bool varies = std::isfinite(sd) && sd > 1e-9 * std::max(1.0, std::fabs(mean));
+    ms[4 + f] = varies ? (float)sd : 1.0f;
+  }
+  const int npar = mlp_param_count();
+  HIPCHK(P, hipMemcpyAsync(W + (npar - 8), ms, sizeof(ms), hipMemcpyHostToDevice, P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_pc_attach(rafeast_plan_t P, const float* W) {
+  if (P && P->dop.kind != 0)
+    return fail(P, RAFEAST_UNSUPPORTED, "the learned preconditioner takes CSR plans");
+  if (!P || !W) return RAFEAST_INVALID_ARG;
+  P->err.clear();
+  const int npar = mlp_param_count();
+  if (!P->d_pcW) {  // plans made with precond NONE get the buffers on first attach
+    HIPCHK(P, hipMalloc(&P->d_pcW, npar * sizeof(float)));
+    HIPCHK(P, hipMalloc(&P->d_pcWb, npar * sizeof(float)));
+    HIPCHK(P, hipMalloc(&P->d_pcX, 4 * (size_t)P->nc * sizeof(double)));
+    HIPCHK(P, hipMalloc(&P->d_pcY, 16 * (size_t)P->nc * sizeof(float)));
+  }
+  HIPCHK(P, hipMemcpyAsync(P->d_pcW, W, npar * sizeof(float), hipMemcpyDeviceToDevice, P->st));
+  HIPCHK(P, launch_mlp_bf16(P->st, P->d_pcW, P->d_pcWb));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  P->pc_ready = true;
+  return RAFEAST_OK;
+}
+
 rafeast_status rafeast_pc_solve(rafeast_plan_t P, int32_t nz, const double* z, int32_t k,
                                 const double* B, int32_t ldb, const double* coef, void* Xout,
                                 double tol, int32_t* iters, double* resid) {
@@ -2443,78 +2763,7 @@ rafeast_status rafeast_pc_solve(rafeast_plan_t P, int32_t nz, const double* z, i
   if (!P || !z || !B || !Xout || nz < 1 || k < 1 || ldb < k || !(tol > 0.0) || !(tol < 1.0))
     return RAFEAST_INVALID_ARG;
   P->err.clear();
-  const int64_t n = P->n;
-  const int Bc = nz * k;
-  DevBuf buf;
-  PcSolve S;
-  S.n = n;
-  S.rowptr = P->d_rowptr;
-  S.col = P->d_col;
-  S.val = P->d_val;
-  spectral_map(P, S.a, S.b);
-  S.Bc = Bc;
-  S.B = B;
-  S.ldb = ldb;
-  S.kb = k;
-  S.tol = tol;
-  S.maxit = P->prm.max_cocg;
-  S.num_cu = P->num_cu;
-  S.progress = verbose_log();
-  const size_t blk = (size_t)n * Bc;
-  S.x = (cpx<double>*)Xout;
-  HIPCHK(P, buf.get(&S.r, blk));
-  HIPCHK(P, buf.get(&S.p0, blk));
-  HIPCHK(P, buf.get(&S.p1, blk));
-  HIPCHK(P, buf.get(&S.w, blk));
-  if (coef) {
-    HIPCHK(P, buf.get(&S.u, blk));
-    HIPCHK(P, buf.get(&S.t0, blk));
-    HIPCHK(P, buf.get(&S.t1, blk));
-    HIPCHK(P, buf.get(&S.t2, blk));
-  }
-  double *zc = nullptr, *cf = nullptr;
-  HIPCHK(P, buf.get(&S.part, (size_t)pc_blocks(n, P->num_cu) * Bc * 3));
-  HIPCHK(P, buf.get(&S.counts, 2));
-  HIPCHK(P, buf.get(&zc, 2 * (size_t)Bc));
-  HIPCHK(P, buf.get(&S.cols.active, Bc));
-  HIPCHK(P, buf.get(&S.cols.it, Bc));
-  HIPCHK(P, buf.get(&S.cols.pending, Bc));
-  HIPCHK(P, buf.get(&S.cols.bn2, Bc));
-  HIPCHK(P, buf.get(&S.cols.res, Bc));
-  HIPCHK(P, buf.get(&S.cols.rho, 2 * (size_t)Bc));
-  HIPCHK(P, buf.get(&S.cols.rhon, 2 * (size_t)Bc));
-  HIPCHK(P, buf.get(&S.cols.alpha, 2 * (size_t)Bc));
-  HIPCHK(P, buf.get(&S.cols.beta, 2 * (size_t)Bc));
-  std::vector<double> hz(2 * (size_t)Bc), hc;
-  for (int c = 0; c < Bc; ++c) {
-    hz[2 * c] = z[2 * (c / k)];
-    hz[2 * c + 1] = z[2 * (c / k) + 1];
-  }
-  HIPCHK(P, hipMemcpyAsync(zc, hz.data(), hz.size() * sizeof(double), hipMemcpyHostToDevice,
-                           P->st));
-  S.zc = zc;
-  if (coef) {  // [8][Bc] complex from the per-shift [nz][8] complex
-    hc.resize(16 * (size_t)Bc);
-    for (int t = 0; t < 8; ++t)
-      for (int c = 0; c < Bc; ++c) {
-        hc[(size_t)t * 2 * Bc + 2 * c] = coef[(c / k) * 16 + 2 * t];
-        hc[(size_t)t * 2 * Bc + 2 * c + 1] = coef[(c / k) * 16 + 2 * t + 1];
-      }
-    HIPCHK(P, buf.get(&cf, hc.size()));
-    HIPCHK(P, hipMemcpyAsync(cf, hc.data(), hc.size() * sizeof(double), hipMemcpyHostToDevice,
-                             P->st));
-    S.coef = cf;
-  }
-  HIPCHK(P, run_pc_cocg(P->st, S));
-  std::vector<int> hit(Bc);
-  std::vector<double> hres(Bc);
-  HIPCHK(P, hipMemcpyAsync(hit.data(), S.cols.it, Bc * sizeof(int), hipMemcpyDeviceToHost, P->st));
-  HIPCHK(P, hipMemcpyAsync(hres.data(), S.cols.res, Bc * sizeof(double), hipMemcpyDeviceToHost,
-                           P->st));
-  HIPCHK(P, hipStreamSynchronize(P->st));
-  if (iters) std::memcpy(iters, hit.data(), Bc * sizeof(int));
-  if (resid) std::memcpy(resid, hres.data(), Bc * sizeof(double));
-  return RAFEAST_OK;
+  return pc_solve_run(P, nz, z, k, B, ldb, coef, Xout, tol, iters, resid);
 }
 
 }  // extern "C"

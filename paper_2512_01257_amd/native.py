@@ -28,6 +28,7 @@ PRECISION = {"fp64": 0, "fp32": 1}
 WS_OP = {"auto": 0, "literal": 1, "flip": 2, "fold": 3, "none": 4}
 RHS_FORM = {"residual": 0, "literal": 1}
 ENGINE = {"auto": 0, "resident": 1, "stream": 2}
+PRECOND = {"none": 0, "learned": 1}
 NPHASE = 5
 PHASES = ("rr", "solve", "combine", "orth", "total")
 
@@ -44,12 +45,14 @@ class Params(C.Structure):
                 ("tol_eig", C.c_double), ("tol_solve", C.c_double), ("max_iter", C.c_int32),
                 ("max_cocg", C.c_int32), ("precision", C.c_int32), ("ws_op", C.c_int32),
                 ("rhs_form", C.c_int32), ("engine", C.c_int32), ("seed", C.c_uint64),
-                ("hip_stream", C.c_void_p), ("tol_solve_relaxed", C.c_double)]
+                ("hip_stream", C.c_void_p), ("tol_solve_relaxed", C.c_double),
+                ("precond", C.c_int32)]
 
 
 class WsInfo(C.Structure):
     _fields_ = [("beta_m0", C.c_double), ("beta_m0p1", C.c_double), ("ratio", C.c_double),
-                ("op", C.c_int32), ("t_ms", C.c_double)]
+                ("op", C.c_int32), ("t_ms", C.c_double), ("r_halko", C.c_double),
+                ("gap", C.c_double), ("proj_bound", C.c_double)]
 
 
 class Result(C.Structure):
@@ -57,7 +60,8 @@ class Result(C.Structure):
                 ("X", C.c_void_p), ("M", C.c_int32), ("iters", C.c_int32),
                 ("cocg_iters", C.c_int64), ("cocg_max", C.c_int32), ("refinements", C.c_int32),
                 ("max_resid", C.c_double), ("t_ms", C.c_double * NPHASE),
-                ("tol_solve_last", C.c_double)]
+                ("tol_solve_last", C.c_double), ("cocg_node", C.c_int64 * 64),
+                ("pc_fallbacks", C.c_int32)]
 
 
 _lib = None
@@ -127,6 +131,13 @@ def lib():
     L.rafeast_pc_solve.argtypes = [P, C.c_int32, dp, C.c_int32, P, C.c_int32, dp, P, C.c_double,
                                    C.POINTER(C.c_int32), dp]
     L.rafeast_pc_solve.restype = C.c_int
+    L.rafeast_pc_harvest.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), P, P, P, P,
+                                     C.POINTER(C.c_int32)]
+    L.rafeast_pc_harvest.restype = C.c_int
+    L.rafeast_pc_attach.argtypes = [P, P]
+    L.rafeast_pc_attach.restype = C.c_int
+    L.rafeast_pc_normalize.argtypes = [P, C.c_int32, P, P]
+    L.rafeast_pc_normalize.restype = C.c_int
     L.rafeast_plan_batch.argtypes = [C.c_int32, C.POINTER(Csr), C.POINTER(Params), C.POINTER(P)]
     L.rafeast_plan_batch.restype = C.c_int
     L.rafeast_batch_plan.argtypes = [P, C.c_int32]
@@ -241,7 +252,7 @@ def _csr_struct(csr):
 
 
 def _params(lmin, lmax, m0, nc, q, p, tol_eig, tol_solve, max_iter, max_cocg, precision,
-            ws_op, rhs_form, engine, seed, stream, tol_solve_relaxed=0.0):
+            ws_op, rhs_form, engine, seed, stream, tol_solve_relaxed=0.0, precond="none"):
     prm = default_params()
     prm.lmin, prm.lmax, prm.m0, prm.nc, prm.q, prm.p = lmin, lmax, m0, nc, q, p
     prm.tol_eig, prm.tol_solve, prm.max_iter, prm.max_cocg = tol_eig, tol_solve, max_iter, max_cocg
@@ -252,6 +263,7 @@ def _params(lmin, lmax, m0, nc, q, p, tol_eig, tol_solve, max_iter, max_cocg, pr
     prm.seed = seed
     prm.hip_stream = stream
     prm.tol_solve_relaxed = tol_solve_relaxed
+    prm.precond = PRECOND[precond]
     return prm
 
 
@@ -266,11 +278,13 @@ class Plan:
 
     def __init__(self, csr, lmin, lmax, m0, nc=8, q=2, p=-1, tol_eig=1e-10, tol_solve=1e-6,
                  max_iter=20, max_cocg=20000, precision="fp32", ws_op="auto",
-                 rhs_form="residual", engine="auto", seed=0, stream=None, tol_solve_relaxed=0.0):
+                 rhs_form="residual", engine="auto", seed=0, stream=None, tol_solve_relaxed=0.0,
+                 precond="none"):
         L = lib()
         A, keep = _csr_struct(csr)
         prm = _params(lmin, lmax, m0, nc, q, p, tol_eig, tol_solve, max_iter, max_cocg,
-                      precision, ws_op, rhs_form, engine, seed, stream, tol_solve_relaxed)
+                      precision, ws_op, rhs_form, engine, seed, stream, tol_solve_relaxed,
+                      precond)
         h = C.c_void_p()
         st = L.rafeast_plan(C.byref(A), C.byref(prm), C.byref(h))
         if st != 0:
@@ -285,7 +299,7 @@ class Plan:
         prm = _params(lmin, lmax, m0, opts["nc"], opts["q"], opts["p"], opts["tol_eig"],
                       opts["tol_solve"], opts["max_iter"], opts["max_cocg"], opts["precision"],
                       opts["ws_op"], opts["rhs_form"], opts["engine"], opts["seed"], stream,
-                      opts["tol_solve_relaxed"])
+                      opts["tol_solve_relaxed"], opts["precond"])
         h = C.c_void_p()
         st = make(C.byref(prm), C.byref(h))
         if st != 0:
@@ -389,6 +403,39 @@ class Plan:
                                              _tptr(X), _tptr(G), _tptr(h), _tptr(rr)))
         return X, G, h, rr
 
+    def pc_harvest(self, steps=(0, 32, 128)):
+        """rafeast_pc_harvest: (X, G, h, rr) device tensors of the training
+        samples from the COCG residuals of the plan's own shifted systems
+        after each count of plain COCG iterations in steps (right-hand sides:
+        the residual block of the plan's last Rayleigh-Ritz step)."""
+        import torch
+
+        st = np.ascontiguousarray(steps, dtype=np.int32)
+        cap = int(sum(1 if s == 0 else 2 for s in st)) * self.nc * self.m0
+        X = torch.empty((cap, 4), dtype=torch.float64, device="cuda")
+        G = torch.empty((cap, 8, 8, 2), dtype=torch.float64, device="cuda")
+        h = torch.empty((cap, 8, 2), dtype=torch.float64, device="cuda")
+        rr = torch.empty(cap, dtype=torch.float64, device="cuda")
+        cnt = C.c_int32()
+        self._check(lib().rafeast_pc_harvest(self._h, len(st),
+                                             st.ctypes.data_as(C.POINTER(C.c_int32)), _tptr(X),
+                                             _tptr(G), _tptr(h), _tptr(rr), C.byref(cnt)))
+        k = cnt.value
+        return X[:k], G[:k], h[:k], rr[:k]
+
+    def pc_normalize(self, X, W):
+        """rafeast_pc_normalize: W's input standardization from features X."""
+        import torch
+
+        self._check(lib().rafeast_pc_normalize(self._h, X.shape[0], _tptr(X, torch.float64),
+                                               _tptr(W, torch.float32)))
+
+    def pc_attach(self, W):
+        """rafeast_pc_attach: the plan copies the FP32 network parameters W."""
+        import torch
+
+        self._check(lib().rafeast_pc_attach(self._h, _tptr(W, torch.float32)))
+
     def pc_forward(self, X, W):
         import torch
 
@@ -462,7 +509,8 @@ class Plan:
         inf = WsInfo()
         self._check(lib().rafeast_warmstart(self._h, _dptr(om), _dptr(q0), C.byref(inf)))
         out = dict(beta_m0=inf.beta_m0, beta_m0p1=inf.beta_m0p1, ratio=inf.ratio,
-                   op={v: k for k, v in WS_OP.items()}[inf.op], t_ms=inf.t_ms)
+                   op={v: k for k, v in WS_OP.items()}[inf.op], t_ms=inf.t_ms,
+                   r_halko=inf.r_halko, gap=inf.gap, proj_bound=inf.proj_bound)
         if want_q0:
             out["Q0"] = q0
         return out
@@ -489,6 +537,7 @@ class Plan:
                     X=X[:, :M].copy() if X is not None else None, M=M, iters=r.iters,
                     cocg_iters=r.cocg_iters, cocg_max=r.cocg_max, refinements=r.refinements,
                     max_resid=r.max_resid, tol_solve_last=r.tol_solve_last,
+                    cocg_node=list(r.cocg_node[: self.nc]), pc_fallbacks=r.pc_fallbacks,
                     t_ms={k: r.t_ms[i] for i, k in enumerate(PHASES)})
 
     def solve_device(self, lam, resid, X=None, Q_init=None):
@@ -509,6 +558,7 @@ class Plan:
         return dict(status=STATUS[st], M=r.M, iters=r.iters, cocg_iters=r.cocg_iters,
                     cocg_max=r.cocg_max, refinements=r.refinements, max_resid=r.max_resid,
                     tol_solve_last=r.tol_solve_last,
+                    cocg_node=list(r.cocg_node[: self.nc]), pc_fallbacks=r.pc_fallbacks,
                     t_ms={k: r.t_ms[i] for i, k in enumerate(PHASES)})
 
     # ------------------------------------------------ step-level (device) ---
@@ -566,7 +616,7 @@ class Plan:
 
 _PLAN_DEFAULTS = dict(nc=8, q=2, p=-1, tol_eig=1e-10, tol_solve=1e-6, max_iter=20,
                       max_cocg=20000, precision="fp32", ws_op="auto", rhs_form="residual",
-                      engine="auto", seed=0, tol_solve_relaxed=0.0)
+                      engine="auto", seed=0, tol_solve_relaxed=0.0, precond="none")
 
 
 class Batch:

@@ -122,6 +122,34 @@ def test_invalid_params_rejected(native):
     assert _plan_status(native, csr, tol_solve_relaxed=math.nan) == "INVALID_ARG"
 
 
+def test_precond_validated_before_the_device(native):
+    import ctypes as C
+
+    csr = grid_laplacian((6, 6), 0.01)
+    L = native.lib()
+    A, keep = native._csr_struct(csr)
+    prm = native._params(0.0, 0.5, 8, 4, 1, -1, 1e-10, 1e-6, 20, 20000, "fp32", "auto",
+                         "residual", "auto", 0, None)
+    prm.precond = 2
+    h = C.c_void_p()
+    assert L.rafeast_plan(C.byref(A), C.byref(prm), C.byref(h)) == 1
+    assert b"precond" in L.rafeast_last_error(None)
+    # dense plans and the batching form refuse the learned preconditioner
+    prm.precond = native.PRECOND["learned"]
+    prm.m0 = 2
+    K = np.eye(4) * 2.0
+    assert native.STATUS[L.rafeast_plan_dense(4, K.ctypes.data_as(C.POINTER(C.c_double)), 4,
+                                              C.byref(prm), C.byref(h))] == "UNSUPPORTED"
+    prm.m0 = 8
+    As = (native.Csr * 1)(A)
+    assert native.STATUS[L.rafeast_plan_batch(1, As, (native.Params * 1)(prm),
+                                              C.byref(h))] == "UNSUPPORTED"
+    assert b"precond" in L.rafeast_batch_last_error(None)
+    # step-level learned calls refuse null plans and buffers
+    assert L.rafeast_pc_harvest(None, 0, None, None, None, None, None, None) == 1
+    assert L.rafeast_pc_attach(None, None) == 1
+
+
 def test_dense_plans_validated_before_the_device(native):
     import ctypes as C
 

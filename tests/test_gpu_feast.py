@@ -67,6 +67,9 @@ def test_warmstart_parity(gpu_lib, op):
     assert sin_theta(ws["Q0"], Q0).max() < 1e-9
     assert abs(ws["beta_m0"] - info["beta_m0"]) <= 1e-10 * abs(info["beta_m0"])
     assert abs(ws["beta_m0p1"] - info["beta_m0p1"]) <= 1e-10 * abs(info["beta_m0p1"])
+    # Theorem 1's bound from the same estimates (eq. R-Halko, delta = 0.01)
+    for key in ("gap", "r_halko", "proj_bound"):
+        assert abs(ws[key] - info[key]) <= 1e-8 * abs(info[key]), key
 
 
 def test_device_sketch_path(gpu_lib):
@@ -84,6 +87,10 @@ def test_device_sketch_path(gpu_lib):
     assert sin_theta(ws["Q0"], Q0).max() < 1e-9
     assert out["status"] == "OK" and out["M"] == 10
     np.testing.assert_allclose(out["lam"], lam[:10], atol=1e-10 * lmax)
+    # per-node COCG counts add up to the total, and the node nearest the real
+    # axis (first in the plan's order) needs the most iterations
+    assert len(out["cocg_node"]) == 4 and sum(out["cocg_node"]) == out["cocg_iters"]
+    assert out["cocg_node"][0] == max(out["cocg_node"]) and out["pc_fallbacks"] == 0
 
 
 # The literal form stores (zI - A)^{-1} q itself, so its rounding sets the

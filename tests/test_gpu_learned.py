@@ -8,7 +8,8 @@ import pytest
 from oracle import learned as Lr
 from oracle.spectrum import gershgorin
 from workloads import grid_laplacian, knn_laplacian
-from workloads.learned import flatten, init_weights, minibatch_order, residual_samples, unflatten
+from workloads.learned import (flatten, init_weights, minibatch_order, normalization,
+                               residual_samples, unflatten)
 
 pytestmark = pytest.mark.gpu
 
@@ -77,21 +78,31 @@ def test_network_forward_and_gradient_bf16(gpu_lib, torch_dev):
     csr = knn_laplacian(600, 2, 8, seed=4, weighted=True, shift=1e-3)
     A = csr.to_scipy()
     params = init_weights(21)
-    W = torch.from_numpy(flatten(params)).cuda()
     P64 = [(w.astype(np.float64), b.astype(np.float64)) for w, b in params]
     with _plan(gpu_lib, csr) as plan:
         dev, host = _training_set(torch, plan, A, csr.n)
+        # the input standardization the library sets from the features
+        W = torch.from_numpy(flatten(params)).cuda()
+        plan.pc_normalize(dev[0], W)
+        mu, sd = normalization(W.cpu().numpy())
         Y = plan.pc_forward(dev[0], W).cpu().numpy().astype(np.float64)
         g, loss = plan.pc_gradient(*dev, W)
-    Yr = Lr.mlp_forward(P64, host[0])[0]
+    np.testing.assert_allclose(mu, host[0].mean(axis=0), rtol=1e-6, atol=1e-7)
+    ref_sd = host[0].std(axis=0)
+    ref_sd[ref_sd <= 1e-9 * np.maximum(1.0, np.abs(host[0].mean(axis=0)))] = 1.0
+    np.testing.assert_allclose(sd, ref_sd, rtol=1e-6)
+    norm = (mu, sd)
+    Yr = Lr.mlp_forward(P64, host[0], norm)[0]
     assert np.linalg.norm(Y - Yr) <= 2e-2 * np.linalg.norm(Yr)
-    ref = Lr.batch_grad(P64, *host)
+    ref = Lr.batch_grad(P64, *host, norm=norm)
     gr = np.concatenate([np.concatenate([dw.ravel(), db]) for dw, db in ref])
     gg = g.cpu().numpy().astype(np.float64)
+    assert np.all(gg[len(gr):] == 0.0)  # the standardization is not trained
+    gg = gg[: len(gr)]
     assert np.linalg.norm(gg - gr) <= 2e-2 * np.linalg.norm(gr)
     for l, (dw, db) in enumerate(unflatten(gg)):  # layer by layer too
         assert np.linalg.norm(dw - ref[l][0]) <= 5e-2 * np.linalg.norm(ref[l][0]), l
-    lr = Lr.batch_loss(P64, *host)
+    lr = Lr.batch_loss(P64, *host, norm=norm)
     assert abs(loss - lr) <= 2e-2 * abs(lr)
 
 

@@ -175,8 +175,7 @@ def test_theorem1_statistics_top_window():
     beta = np.sort((spec - lmin) / (lmax - lmin))[::-1]
     b_m0, b_m1 = beta[m0 - 1], beta[m0]
     gap = b_m0 - b_m1
-    C1 = 1 + 0.5 * p * np.log(2 * m0 / delta)
-    R = C1 * np.sqrt(1 + m0 / (p - 1)) * b_m1 * (b_m1 / b_m0) ** (2 * q)
+    R = F.r_halko(b_m0, b_m1, m0, p, q, delta)
     fails = 0
     for seed in range(40):
         Q0, _ = F.warmstart(A, lmin, lmax, m0, gaussian(n, m0 + p, seed), q, "literal")
@@ -184,6 +183,33 @@ def test_theorem1_statistics_top_window():
         dist = np.linalg.norm(Q0o @ Q0o.T - U[:, :m0] @ U[:, :m0].T, 2)
         fails += dist > R / gap
     assert fails / 40 <= delta
+
+
+def test_r_halko_hand_value():
+    # m0 = 10, p = 10, q = 1, delta = 0.1, beta_m0 = 0.9, beta_m0+1 = 0.3:
+    # C1 = 1 + 5 ln 200 = 27.491586832740182, sqrt(1 + 10/9) = sqrt(19)/3
+    # = 1.4529663145135578, 0.3 (1/3)^2 = 1/30; product 1.3314783200165317
+    assert F.r_halko(0.9, 0.3, 10, 10, 1, 0.1) == pytest.approx(1.3314783200165317, rel=1e-14)
+    # q = 0 drops the power factor (x 9); a larger delta lowers C1
+    assert F.r_halko(0.9, 0.3, 10, 10, 0, 0.1) == pytest.approx(11.983304880148786, rel=1e-14)
+    assert F.r_halko(0.9, 0.3, 10, 10, 1, 0.5) < F.r_halko(0.9, 0.3, 10, 10, 1, 0.1)
+
+
+def test_warmstart_reports_theorem1_bound():
+    # the warmstart's own estimates satisfy Theorem 1 on a top window: the
+    # projector error is below r_halko / gap (and Remark 1's 1/2 here)
+    rng = np.random.default_rng(5)
+    n, m0, p, q = 200, 8, 10, 2
+    spec = np.concatenate([np.linspace(1.0, 0.95, m0), rng.uniform(0.0, 0.1, n - m0)])
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = sp.csr_matrix(U @ np.diag(spec) @ U.T)
+    Q0, info = F.warmstart(A, 0.0, 1.0, m0, gaussian(n, m0 + p, 1), q, "literal")
+    assert info["gap"] == pytest.approx(info["beta_m0"] - info["beta_m0p1"])
+    assert info["proj_bound"] == pytest.approx(info["r_halko"] / info["gap"])
+    Qo = F.orth(Q0)
+    dist = np.linalg.norm(Qo @ Qo.T - U[:, :m0] @ U[:, :m0].T, 2)
+    assert dist <= info["proj_bound"]
+    assert info["proj_bound"] < 0.5
 
 
 def test_theorem2_perturbed_iteration_floor():

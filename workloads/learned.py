@@ -11,24 +11,34 @@ import numpy as np
 MLP_SIZES = (4, 64, 64, 64, 16)
 
 
-def init_weights(seed: int, sizes=MLP_SIZES):
+def init_weights(seed: int, sizes=MLP_SIZES, out_scale: float = 0.1):
     """[(W_l, b_l)]: W_l (out x in) ~ N(0, 1/in) (float32), b_l = 0, except
-    the last layer, scaled by 1/10 so the untrained outputs start small."""
+    the last layer, scaled by out_scale so the untrained outputs start small
+    (0: they start at zero, the choice for training a preconditioner)."""
     rng = np.random.default_rng(seed)
     out = []
     for l in range(len(sizes) - 1):
         fan_in, fan_out = sizes[l], sizes[l + 1]
         W = rng.standard_normal((fan_out, fan_in)) / np.sqrt(fan_in)
         if l == len(sizes) - 2:
-            W = W / 10.0
+            W = W * out_scale
         out.append((W.astype(np.float32), np.zeros(fan_out, dtype=np.float32)))
     return out
 
 
-def flatten(params) -> np.ndarray:
-    """All weights and biases in layer order (W row-major, then b), float32."""
-    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(
-        np.float32)
+def flatten(params, norm=None) -> np.ndarray:
+    """All weights and biases in layer order (W row-major, then b), then the
+    input standardization mu[4], sd[4] (default 0 and 1), float32."""
+    mu, sd = norm if norm is not None else (np.zeros(4), np.ones(4))
+    parts = [np.concatenate([W.ravel(), b.ravel()]) for W, b in params] + [mu, sd]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def normalization(flat, sizes=MLP_SIZES):
+    """(mu, sd) stored after the weights of a flat parameter vector."""
+    o = parameter_count(sizes)
+    return (np.asarray(flat[o:o + sizes[0]], dtype=np.float64),
+            np.asarray(flat[o + sizes[0]:o + 2 * sizes[0]], dtype=np.float64))
 
 
 def unflatten(flat, sizes=MLP_SIZES):
@@ -44,6 +54,7 @@ def unflatten(flat, sizes=MLP_SIZES):
 
 
 def parameter_count(sizes=MLP_SIZES) -> int:
+    """Trained weights and biases (the standardization is not counted)."""
     return sum(sizes[l + 1] * sizes[l] + sizes[l + 1] for l in range(len(sizes) - 1))
 
 
