@@ -423,10 +423,13 @@ def main_grid64(args):
 
     csr = grid_laplacian((64, 64, 64), 0.01)
     lmin, lmax = 0.493673151133, 0.506687779116
+    ms = args.engine == "multishift"
+    prec = "fp64" if ms else args.precision
     t0 = time.perf_counter()
-    with native.Plan(csr, lmin, lmax, 64, nc=8, q=2, p=20, precision="fp32", tol_solve=1e-6,
+    with native.Plan(csr, lmin, lmax, 64, nc=8, q=2, p=20, precision=prec, tol_solve=1e-6,
                      tol_solve_relaxed=args.relaxed if args.relaxed_phase2 else 0.0,
-                     tol_eig=1e-10, max_iter=args.max_iter, max_cocg=args.max_cocg) as plan:
+                     tol_eig=1e-10, max_iter=args.max_iter, max_cocg=args.max_cocg,
+                     engine="multishift" if ms else "auto") as plan:
         plan_ms = (time.perf_counter() - t0) * 1e3
         t0 = time.perf_counter()
         ws = plan.warmstart(omega=gaussian(csr.n, 84, 0))
@@ -449,11 +452,15 @@ def main_grid64(args):
         "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(secs * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64+f64", "data": "synthetic",
+        "dtype": "f64+c128" if ms else ("c64+f64" if prec == "fp32" else "c128"),
+        "data": "synthetic",
         "config": {"workload": "Dirichlet 7-point 64^3 grid + 0.01 I, window [0.493673151133, "
                                "0.506687779116] (39 eigenvalues), m0=64, N_c=8, q=2, p=20, "
-                               "complex-FP32 COCG + FP64 reliable updates, tol 1e-6",
-                   "engine": "stream", "max_iter": args.max_iter, "max_cocg": args.max_cocg,
+                               + ("multi-shift FP64 COCG (one real seed CG per right-hand side)"
+                                  if ms else "complex-FP32 COCG + FP64 reliable updates"
+                                  if prec == "fp32" else "complex-FP64 COCG") + ", tol 1e-6",
+                   "engine": "multishift" if ms else "stream", "precision": prec,
+                   "max_iter": args.max_iter, "max_cocg": args.max_cocg,
                    "tol_solve_relaxed": args.relaxed if args.relaxed_phase2 else 0.0},
         "status": out["status"], "M": out["M"], "feast_iters": out["iters"],
         "cocg_iters": out["cocg_iters"], "cocg_max": out["cocg_max"],
@@ -667,6 +674,8 @@ def main():
     ap.add_argument("--relaxed-phase2", action="store_true",
                     help="grid64, batch32, rgg (RA configurations only): relaxed Phase-2 solves "
                          "starting at --relaxed")
+    ap.add_argument("--engine", choices=("auto", "multishift"), default="auto",
+                    help="grid64: COCG engine (multishift: FP64 multi-shift engine)")
     ap.add_argument("--max-iter", type=int, default=20, help="grid64: FEAST iteration cap")
     ap.add_argument("--max-cocg", type=int, default=20000, help="grid64: COCG iteration cap")
     ap.add_argument("--gram-only", action="store_true",

@@ -81,8 +81,19 @@ enum { RAFEAST_RHS_RESIDUAL = 0,  /* solve against Ritz residuals r_i and use
  * stopping test. */
 enum { RAFEAST_ENGINE_AUTO = 0,
        RAFEAST_ENGINE_RESIDENT = 1,  /* one workgroup per system, vectors in LDS/registers */
-       RAFEAST_ENGINE_STREAM = 2 };  /* all systems in lock step, vectors in HBM, rows
+       RAFEAST_ENGINE_STREAM = 2,    /* all systems in lock step, vectors in HBM, rows
                                         reordered by reverse Cuthill-McKee */
+       RAFEAST_ENGINE_MULTISHIFT = 3 };/* precision FP64 and CSR plans only: the nc shifted
+                                        systems of each right-hand side share one Krylov
+                                        space, K(z_j I - A, b) = K(A, b); one real CG on
+                                        the positive definite seed A - s I (s below the
+                                        Gershgorin interval) drives them all, each with its
+                                        own complex search direction and iterate, stopped
+                                        at its own residual (|r_k| / |pi_k|, the shifted
+                                        residual collinear with the seed's).  One real
+                                        SpMV of the m0 columns per iteration instead of
+                                        nc complex ones; vectors in HBM in the streaming
+                                        engine's row order.  Never chosen by AUTO */
 
 /* rafeast_params.precond: preconditioner of the shifted solves. */
 enum { RAFEAST_PC_NONE = 0,       /* unpreconditioned COCG on the plan's engine */
@@ -274,8 +285,8 @@ const char* rafeast_status_string(rafeast_status s);
 rafeast_status rafeast_plan_info(rafeast_plan_t plan, double* sig_lo, double* sig_hi,
                                  double* anorm_inf, int64_t* nnz, double* z, double* w);
 
-/* The COCG engine the plan resolved (RAFEAST_ENGINE_RESIDENT or _STREAM);
- * 0 for a NULL plan. */
+/* The COCG engine the plan resolved (RAFEAST_ENGINE_RESIDENT, _STREAM or
+ * _MULTISHIFT); 0 for a NULL plan. */
 int32_t rafeast_plan_engine(rafeast_plan_t plan);
 
 /* The launch shape rafeast_plan chose by measurement (autotuning; the

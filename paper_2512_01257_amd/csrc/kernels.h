@@ -289,6 +289,64 @@ size_t stream_partial_doubles(int n, int Bp, int num_cu);
 hipError_t run_stream_cocg(hipStream_t st, const StreamMatrix& A, const StreamWork& W,
                            const StreamLaunch& L, bool fp32);
 
+// ---- multi-shift COCG engine (FP64) ------------------------------------------
+// The nz shifted systems of each column c < k share the right-hand side
+// b_c: (z_j I - A) d_{j,c} = b_c.  One CG on the real SPD seed A - s I
+// (s below the spectrum) drives all of them; every shifted system keeps its
+// own search direction and iterate (complex FP64) and stops at its own
+// residual.  Blocks are n x kp (kp = 64 ceil(k / 64)) in the streaming
+// engine's row order (A: its StreamMatrix, FP64 values).
+struct MsCols {                  // per column kp entries; per (j, c) nz x kp entries
+  double* rr = nullptr;          // seed r^T r
+  double* bn = nullptr;          // |b|
+  double* alpha = nullptr;
+  double* alpha_prev = nullptr;
+  double* beta_prev = nullptr;
+  double* scale = nullptr;       // pending rescale of the seed's r and p (1: none)
+  int* colive = nullptr;         // some shift of the column still iterates
+  cpx<double>* pi = nullptr;     // pi_k of each shift
+  cpx<double>* pi_prev = nullptr;
+  cpx<double>* pi_next = nullptr;
+  cpx<double>* ipi = nullptr;    // 1 / pi_k
+  cpx<double>* as = nullptr;     // alpha^s_k
+  cpx<double>* bs = nullptr;     // beta^s_{k-1}
+  int* live = nullptr;           // the shifted system still iterates
+  int* its = nullptr;            // its iterations
+  double* est = nullptr;         // its estimated relative residual |r_k| / (|pi_k| |b|)
+};
+struct MsWork {
+  int kp = 0, nz = 0, nb = 0, num_cu = 0;  // nz: the most shifts this workspace holds
+  double* r = nullptr;           // n x kp seed blocks
+  double* p = nullptr;
+  double* w = nullptr;
+  cpx<double>* X = nullptr;      // nz blocks n x kp: shifted iterates
+  cpx<double>* P = nullptr;      // nz blocks n x kp: shifted search directions
+  double* part = nullptr;        // nb x kp partial sums
+  cpx<double>* sig = nullptr;    // [nz] sigma_j = s - z_j
+  int* count = nullptr;          // [1] live systems
+  MsCols cols;
+};
+struct MsLaunch {
+  const double* B = nullptr;     // n x k right-hand sides (FP64, caller row order), ldb
+  int ldb = 0;
+  int k = 0;
+  int nz = 0;
+  const double* z = nullptr;     // host [2 nz] shifts (re, im)
+  double seed = 0.0;             // s: A - s I is positive definite
+  void* D = nullptr;             // n x (nz k) complex FP64 outputs (caller row order), ldd;
+  int ldd = 0;                   //   column j k + c is d_{j,c}
+  double tol = 1e-6;
+  int maxit = 20000;
+  int chunk = 8;                 // iterations between host reads of the live count
+  int* iters = nullptr;          // nullable device [nz k]
+  double* resid = nullptr;       // nullable device [nz k]: true relative residuals
+};                               //   |b_c - (z_j I - A) d| / |b_c| in FP64
+int ms_cpl(int k);
+int ms_padded(int k);
+int ms_blocks(int n, int num_cu);
+// Runs to completion; synchronises st once per chunk of iterations.
+hipError_t run_mshift(hipStream_t st, const StreamMatrix& A, const MsWork& W, const MsLaunch& L);
+
 }  // namespace rafeast
 
 namespace rafeast {

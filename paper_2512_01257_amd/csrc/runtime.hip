@@ -107,6 +107,7 @@ struct rafeast_plan_s {
   int* d_sperm = nullptr;
   StreamMatrix smat;
   StreamWork swork;               // sized for the nc * m0 systems of a solve
+  MsWork mswork;                  // multi-shift engine: sized for nc shifts x m0 columns
   DenseOp dop;                    // dense operator (kind 0: A is the CSR matrix)
   double* d_k64 = nullptr;        // its device matrices and scratch
   float* d_k32 = nullptr;
@@ -293,8 +294,12 @@ rafeast_status validate_params(const rafeast_params* p, int64_t n, std::string& 
     msg = "unknown rhs_form";
     return RAFEAST_INVALID_ARG;
   }
-  if (p->engine < RAFEAST_ENGINE_AUTO || p->engine > RAFEAST_ENGINE_STREAM) {
+  if (p->engine < RAFEAST_ENGINE_AUTO || p->engine > RAFEAST_ENGINE_MULTISHIFT) {
     msg = "unknown engine";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->engine == RAFEAST_ENGINE_MULTISHIFT && p->precision != RAFEAST_FP64) {
+    msg = "the multi-shift engine runs in FP64 (precision RAFEAST_FP64)";
     return RAFEAST_INVALID_ARG;
   }
   if (p->precond != RAFEAST_PC_NONE && p->precond != RAFEAST_PC_LEARNED) {
@@ -647,6 +652,59 @@ rafeast_status alloc_stream_work(rafeast_plan_s* P, int Bp, StreamWork& W,
   return RAFEAST_OK;
 }
 
+// Device buffers of a multi-shift workspace for nz shifts and k columns.
+rafeast_status alloc_ms_work(rafeast_plan_s* P, int nz, int k, MsWork& W,
+                             std::vector<void*>& bufs) {
+  const int64_t n = P->n;
+  auto get = [&](void** ptr, size_t bytes, const char* what) -> rafeast_status {
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+      *ptr = nullptr;
+      return hip_fail(P, e, what);
+    }
+    bufs.push_back(*ptr);
+    return RAFEAST_OK;
+  };
+  W = MsWork{};
+  W.kp = ms_padded(k);
+  W.nz = nz;
+  W.num_cu = P->num_cu;
+  W.nb = ms_blocks((int)n, P->num_cu);
+  const size_t blk = (size_t)n * W.kp, cs = (size_t)nz * W.kp;
+  RCHK(get((void**)&W.r, blk * sizeof(double), "multi-shift r"));
+  RCHK(get((void**)&W.p, blk * sizeof(double), "multi-shift p"));
+  RCHK(get((void**)&W.w, blk * sizeof(double), "multi-shift w"));
+  RCHK(get((void**)&W.X, nz * blk * sizeof(cpx<double>), "multi-shift x"));
+  RCHK(get((void**)&W.P, nz * blk * sizeof(cpx<double>), "multi-shift p^s"));
+  RCHK(get((void**)&W.part, (size_t)W.nb * W.kp * sizeof(double), "multi-shift partials"));
+  RCHK(get((void**)&W.sig, nz * sizeof(cpx<double>), "multi-shift sigma"));
+  RCHK(get((void**)&W.count, sizeof(int), "multi-shift count"));
+  MsCols& c = W.cols;
+  RCHK(get((void**)&c.rr, W.kp * sizeof(double), "ms rr"));
+  RCHK(get((void**)&c.bn, W.kp * sizeof(double), "ms bn"));
+  RCHK(get((void**)&c.alpha, W.kp * sizeof(double), "ms alpha"));
+  RCHK(get((void**)&c.alpha_prev, W.kp * sizeof(double), "ms alpha_prev"));
+  RCHK(get((void**)&c.beta_prev, W.kp * sizeof(double), "ms beta_prev"));
+  RCHK(get((void**)&c.scale, W.kp * sizeof(double), "ms scale"));
+  RCHK(get((void**)&c.colive, W.kp * sizeof(int), "ms colive"));
+  RCHK(get((void**)&c.pi, cs * sizeof(cpx<double>), "ms pi"));
+  RCHK(get((void**)&c.pi_prev, cs * sizeof(cpx<double>), "ms pi_prev"));
+  RCHK(get((void**)&c.pi_next, cs * sizeof(cpx<double>), "ms pi_next"));
+  RCHK(get((void**)&c.ipi, cs * sizeof(cpx<double>), "ms 1/pi"));
+  RCHK(get((void**)&c.as, cs * sizeof(cpx<double>), "ms alpha^s"));
+  RCHK(get((void**)&c.bs, cs * sizeof(cpx<double>), "ms beta^s"));
+  RCHK(get((void**)&c.live, cs * sizeof(int), "ms live"));
+  RCHK(get((void**)&c.its, cs * sizeof(int), "ms its"));
+  RCHK(get((void**)&c.est, cs * sizeof(double), "ms est"));
+  return RAFEAST_OK;
+}
+
+// The multi-shift seed: A - s I is positive definite for s below the
+// Gershgorin interval.
+double ms_seed(const rafeast_plan_s* P) {
+  return P->sig_lo - 1e-3 * std::max(P->sig_hi - P->sig_lo, 1e-300);
+}
+
 // Shift of each streaming column: column c = j * k + i takes z_j; padding
 // columns repeat z_0.
 std::vector<double> stream_shifts(int nz, const double* z, int k, int Bp) {
@@ -832,6 +890,27 @@ rafeast_status run_stream(rafeast_plan_s* P, const StreamWork& W, int nz, int k,
   L.resid = d_resid;
   L.stats = P->d_stats;
   HIPCHK(P, run_stream_cocg(P->st, P->smat, W, L, P->fp32));
+  return RAFEAST_OK;
+}
+
+// Multi-shift engine: the nz shifts of every column c < k in one seed CG.
+rafeast_status run_ms(rafeast_plan_s* P, const MsWork& W, int nz, const double* z, int k,
+                      const double* B, int ldb, void* D, int ldd, double tol, int* d_iters,
+                      double* d_resid = nullptr) {
+  MsLaunch L;
+  L.B = B;
+  L.ldb = ldb;
+  L.k = k;
+  L.nz = nz;
+  L.z = z;
+  L.seed = ms_seed(P);
+  L.D = D;
+  L.ldd = ldd;
+  L.tol = tol;
+  L.maxit = P->prm.max_cocg;
+  L.iters = d_iters;
+  L.resid = d_resid;
+  HIPCHK(P, run_mshift(P->st, P->smat, W, L));
   return RAFEAST_OK;
 }
 
@@ -1151,6 +1230,9 @@ rafeast_status solve_shifted_systems(rafeast_plan_s* P, SolveRun& S) {
   const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
   S.pc_solved = false;
   if (P->prm.precond == RAFEAST_PC_LEARNED) return solve_learned(P, S);
+  if (P->engine == RAFEAST_ENGINE_MULTISHIFT)
+    return run_ms(P, P->mswork, nc, P->zw.data(), m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D,
+                  nc * m0, P->tau, P->d_iters);
   if (P->engine == RAFEAST_ENGINE_STREAM)
     return run_stream(P, P->swork, nc, m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D, nc * m0,
                       P->tau, P->d_iters);
@@ -1412,8 +1494,10 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
                 "m0 + p = " + std::to_string(w) + " exceeds the small-matrix limit 192");
   const bool fp32 = prm->precision == RAFEAST_FP32_REFINED;
   int engine = prm->engine;
-  if (D && engine == RAFEAST_ENGINE_RESIDENT)
+  if (D && (engine == RAFEAST_ENGINE_RESIDENT || engine == RAFEAST_ENGINE_MULTISHIFT))
     return fail(nullptr, RAFEAST_UNSUPPORTED, "dense operators run on the streaming engine");
+  if (engine == RAFEAST_ENGINE_MULTISHIFT && prm->m0 > 192)
+    return fail(nullptr, RAFEAST_UNSUPPORTED, "the multi-shift engine takes m0 <= 192");
   if (D) engine = RAFEAST_ENGINE_STREAM;
   if (engine == RAFEAST_ENGINE_RESIDENT && n > cocg_resident_max_n(fp32))
     return fail(nullptr, RAFEAST_UNSUPPORTED,
@@ -1426,7 +1510,8 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     // the streaming engine is the fallback of AUTO, so its limits apply to both
     const int ncols = prm->nc * prm->m0;
     const int gw = 64 * stream_cpl(prm->m0, ncols, fp32);
-    if (engine != RAFEAST_ENGINE_RESIDENT && (ncols + gw - 1) / gw > kStreamMaxGroups)
+    if ((engine == RAFEAST_ENGINE_AUTO || engine == RAFEAST_ENGINE_STREAM) &&
+        (ncols + gw - 1) / gw > kStreamMaxGroups)
       return fail(nullptr, RAFEAST_UNSUPPORTED,
                   "nc * m0 exceeds the streaming engine's column limit");
   }
@@ -1586,7 +1671,7 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
       PCHK(hipMemcpy(P->d_col, cl.data(), nnz * sizeof(int), hipMemcpyHostToDevice));
       PCHK(hipMemcpy(P->d_val, A->values, nnz * sizeof(double), hipMemcpyHostToDevice));
     }
-    if (engine != RAFEAST_ENGINE_STREAM) {
+    if (engine != RAFEAST_ENGINE_STREAM && engine != RAFEAST_ENGINE_MULTISHIFT) {
     // SELL-64 of the resident engine: rows sorted by decreasing length (ties
     // by index), slices of 64 slots, widths padded to a multiple of 4
     const int nsl = (int)((n + 63) / 64);
@@ -1693,7 +1778,7 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
       P->sell.wave_rpt = rpt;
     }
     }
-    if (engine == RAFEAST_ENGINE_STREAM) {
+    if (engine == RAFEAST_ENGINE_STREAM || engine == RAFEAST_ENGINE_MULTISHIFT) {
       // CSR of the streaming engine in reverse Cuthill-McKee order, so that
       // the rows a workgroup gathers sit close to its own
       const std::vector<int> perm = rcm_order(n, rp, cl);
@@ -1792,6 +1877,8 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     P->xhi_slots = cocg_resident_xhi_slots((int)n, P->num_cu);
     hipError_t e = hipMalloc(&P->d_xhi, P->xhi_slots * 2 * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(P, e, "solution scratch"));
+  } else if (P->engine == RAFEAST_ENGINE_MULTISHIFT) {
+    PRCHK(alloc_ms_work(P, P->nc, P->m0, P->mswork, P->sbufs));
   } else {
     const int Bp = stream_padded_columns(P->m0, P->nc * P->m0, fp32);
     PRCHK(alloc_stream_work(P, Bp, P->swork, P->sbufs));
@@ -2152,7 +2239,20 @@ rafeast_status rafeast_shifted_solve(rafeast_plan_t P, int32_t nz, const double*
   if (e != hipSuccess) {
     s = hip_fail(P, e, "shifted_solve setup");
   } else {
-    if (P->engine == RAFEAST_ENGINE_STREAM) {
+    if (P->engine == RAFEAST_ENGINE_MULTISHIFT) {
+      std::vector<void*> bufs;
+      MsWork W;
+      if (k > 192)
+        s = fail(P, RAFEAST_UNSUPPORTED, "the multi-shift engine takes k <= 192");
+      else
+        s = alloc_ms_work(P, nz, k, W, bufs);
+      if (s == RAFEAST_OK) s = run_ms(P, W, nz, z, k, B, ldb, X, nz * k, tol, d_it, d_rs);
+      if (s == RAFEAST_OK) {
+        e = hipStreamSynchronize(P->st);
+        if (e != hipSuccess) s = hip_fail(P, e, "shifted_solve");
+      }
+      for (void* b : bufs) (void)hipFree(b);
+    } else if (P->engine == RAFEAST_ENGINE_STREAM) {
       // a workspace of this call's width, released below
       const int gw = 64 * stream_cpl(k, nitems, P->fp32);
       const int Bp = stream_padded_columns(k, nitems, P->fp32);
