@@ -425,6 +425,13 @@ def main_grid64(args):
     lmin, lmax = 0.493673151133, 0.506687779116
     ms = args.engine == "multishift"
     prec = "fp64" if ms else args.precision
+    if args.copy_probe:
+        import torch
+
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
     t0 = time.perf_counter()
     with native.Plan(csr, lmin, lmax, 64, nc=8, q=2, p=20, precision=prec, tol_solve=1e-6,
                      tol_solve_relaxed=args.relaxed if args.relaxed_phase2 else 0.0,

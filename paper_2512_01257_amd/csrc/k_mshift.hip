@@ -25,6 +25,12 @@
 // stopped.  The seed's r, p and the pi's are rescaled together when |r_k|
 // falls below 1e-100 |b| (the shifted quantities depend on their ratios).
 //
+// Combining mode (the filter step of FEAST): only the weighted sum
+// sum_j Re(g_j d_j) of the solutions is needed, so the engine accumulates it
+// into one real block as the iterates advance and never stores them: per
+// iteration a shift then moves its direction only (32 B per row and column
+// instead of 64).
+//
 // Layout: engine rows in the streaming engine's reverse Cuthill-McKee order,
 // blocks n x kp row-major (kp = 64 CPL, column c of lane c / CPL); the seed
 // r, p, w are real, the shifted p^s and x^s complex, one n x kp block per
@@ -82,12 +88,26 @@ __device__ __forceinline__ void put_partial(const double (&acc)[CPL], double* __
   }
 }
 
-// Fixed-order sum of column c's partials over nb workgroups.
+constexpr int kFT = 256;  // threads of a finaliser workgroup (one per column)
+
+// Fixed-order sum of column c's partials over nb workgroups by the kFT
+// threads of the calling workgroup (strided partial sums, then a tree); every
+// thread must call it and receives the total.
 __device__ __forceinline__ double col_total(const double* __restrict__ part, int nb, int kp,
                                             int c) {
+  __shared__ double sh[kFT];
+  const int t = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(size_t)b * kp + c];
-  return s;
+  for (int b = t; b < nb; b += kFT) s += part[(size_t)b * kp + c];
+  sh[t] = s;
+  __syncthreads();
+  for (int o = kFT / 2; o > 0; o >>= 1) {
+    if (t < o) sh[t] += sh[t + o];
+    __syncthreads();
+  }
+  const double tot = sh[0];
+  __syncthreads();
+  return tot;
 }
 
 __device__ __forceinline__ zd zinv(zd a) { return zdiv(zd{1.0, 0.0}, a); }
@@ -103,6 +123,7 @@ __global__ __launch_bounds__(kMT) void k_ms_init(int n, int k, int kp, int nz,
                                                  double* __restrict__ r, double* __restrict__ p,
                                                  cpx<double>* __restrict__ X,
                                                  cpx<double>* __restrict__ Ps,
+                                                 double* __restrict__ y,
                                                  double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
   double acc[CPL];
@@ -120,8 +141,9 @@ __global__ __launch_bounds__(kMT) void k_ms_init(int n, int k, int kp, int nz,
       const size_t o = (size_t)row * kp + c;
       r[o] = v;
       p[o] = 0.0;
+      if (y) y[o] = 0.0;
       for (int j = 0; j < nz; ++j) {
-        X[j * blk + o] = cpx<double>{0.0, 0.0};
+        if (!y) X[j * blk + o] = cpx<double>{0.0, 0.0};
         Ps[j * blk + o] = cpx<double>{0.0, 0.0};
       }
       acc[q] += v * v;
@@ -132,11 +154,13 @@ __global__ __launch_bounds__(kMT) void k_ms_init(int n, int k, int kp, int nz,
 
 // Column state after the start: |b|, r^T r, the seed scalars and every
 // shift's pi; a system with b = 0 is done at once (x = 0).
-__global__ void k_ms_fin0(int k, int kp, int nz, int nb, const double* __restrict__ part,
-                          MsCols cols, int* __restrict__ count) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= kp) return;
-  const double rr = c < k ? col_total(part, nb, kp, c) : 0.0;
+__global__ __launch_bounds__(kFT) void k_ms_fin0(int k, int kp, int nz, int nb,
+                                                 const double* __restrict__ part, MsCols cols,
+                                                 int* __restrict__ count) {
+  const int c = blockIdx.x;
+  const double tot = col_total(part, nb, kp, c);
+  if (threadIdx.x != 0) return;
+  const double rr = c < k ? tot : 0.0;
   cols.rr[c] = rr;
   cols.bn[c] = sqrt(rr);
   cols.alpha[c] = 0.0;
@@ -258,13 +282,19 @@ __global__ __launch_bounds__(kMT) void k_ms_spmv(int n, int kp, const int* __res
 
 // alpha_k of every live column, then for each live shift pi_{k+1},
 // alpha^s_k = alpha_k pi_k / pi_{k+1} and 1 / pi_k for the update kernel.
-__global__ void k_ms_fin_alpha(int kp, int nz, int nb, const double* __restrict__ part,
-                               const cpx<double>* __restrict__ sig, MsCols cols) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= kp) return;
-  cols.scale[c] = 1.0;  // a rescale has been applied by the direction update
-  if (!cols.colive[c]) return;
+__global__ __launch_bounds__(kFT) void k_ms_fin_alpha(int kp, int k, int nz, int nb,
+                                                      const double* __restrict__ part,
+                                                      const cpx<double>* __restrict__ sig,
+                                                      const double* __restrict__ g,
+                                                      MsCols cols) {
+  const int c = blockIdx.x;
+  if (!cols.colive[c]) {  // uniform over the workgroup
+    if (threadIdx.x == 0) cols.scale[c] = 1.0;
+    return;
+  }
   const double pw = col_total(part, nb, kp, c);
+  if (threadIdx.x != 0) return;
+  cols.scale[c] = 1.0;  // a rescale has been applied by the direction update
   const double alpha = pw != 0.0 ? cols.rr[c] / pw : 0.0;
   cols.alpha[c] = alpha;
   const double cc = cols.beta_prev[c] * alpha / cols.alpha_prev[c];
@@ -280,6 +310,11 @@ __global__ void k_ms_fin_alpha(int kp, int nz, int nb, const double* __restrict_
     cols.as[e] = cpx<double>{alpha * q.re, alpha * q.im};
     const zd ip = zinv(pk);
     cols.ipi[e] = cpx<double>{ip.re, ip.im};
+    if (g) {  // combining mode: the weight of this step's update of x^s
+      const zd gw = zmul(zd{g[2 * (j * k + c)], g[2 * (j * k + c) + 1]},
+                         zd{alpha * q.re, alpha * q.im});
+      cols.gas[e] = cpx<double>{gw.re, gw.im};
+    }
   }
 }
 
@@ -333,16 +368,203 @@ __global__ __launch_bounds__(kMT) void k_ms_update(int n, int kp, int nz, MsCols
   put_partial<CPL>(acc, part, kp);
 }
 
+// The same update with the per-shift scalars of this lane's columns held in
+// registers (NZ >= nz shifts, NZ * CPL <= 8) and every live shift's loads of
+// a row issued before any of its arithmetic, so that a wave keeps 2 NZ CPL
+// loads in flight instead of two.
+template <int CPL, int NZ>
+__global__ __launch_bounds__(kMT) void k_ms_update_r(int n, int kp, int nz, MsCols cols,
+                                                     double* __restrict__ r,
+                                                     const double* __restrict__ w,
+                                                     cpx<double>* __restrict__ X,
+                                                     cpx<double>* __restrict__ Ps,
+                                                     double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int cl = lane * CPL;
+  double alpha[CPL];
+  bool on[CPL], lv[CPL][NZ];
+  zd ip[CPL][NZ], bs[CPL][NZ], as[CPL][NZ];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    on[q] = cols.colive[cl + q] != 0;
+    alpha[q] = cols.alpha[cl + q];
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      const int e = j * kp + cl + q;
+      lv[q][j] = j < nz && cols.live[e] != 0;
+      ip[q][j] = lv[q][j] ? zd{cols.ipi[e].re, cols.ipi[e].im} : zd{0.0, 0.0};
+      bs[q][j] = lv[q][j] ? zd{cols.bs[e].re, cols.bs[e].im} : zd{0.0, 0.0};
+      as[q][j] = lv[q][j] ? zd{cols.as[e].re, cols.as[e].im} : zd{0.0, 0.0};
+    }
+  }
+  double acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = 0.0;
+  const Rows rw = my_rows(n);
+  const size_t blk = (size_t)n * kp;
+  for (int t = 0; t < rw.count; ++t) {
+    const size_t o = (size_t)(rw.first + rw.stride * t) * kp + cl;
+    double ro[CPL];
+    cpx<double> po[CPL][NZ], xo[CPL][NZ];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      ro[q] = on[q] ? r[o + q] : 0.0;
+#pragma unroll
+      for (int j = 0; j < NZ; ++j)
+        if (lv[q][j]) {
+          po[q][j] = Ps[j * blk + o + q];
+          xo[q][j] = X[j * blk + o + q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      if (!on[q]) continue;
+      const double rn = ro[q] - alpha[q] * w[o + q];
+      r[o + q] = rn;
+      acc[q] += rn * rn;
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) {
+        if (!lv[q][j]) continue;
+        const zd b = bs[q][j], a = as[q][j];
+        const double pr = ro[q] * ip[q][j].re + (b.re * po[q][j].re - b.im * po[q][j].im);
+        const double pi = ro[q] * ip[q][j].im + (b.re * po[q][j].im + b.im * po[q][j].re);
+        Ps[j * blk + o + q] = cpx<double>{pr, pi};
+        X[j * blk + o + q] =
+            cpx<double>{xo[q][j].re + (a.re * pr - a.im * pi), xo[q][j].im + (a.re * pi + a.im * pr)};
+      }
+    }
+  }
+  put_partial<CPL>(acc, part, kp);
+}
+
+// Combining mode of the update: the shifted directions as in k_ms_update_r,
+// and instead of every shift's iterate the one real block
+// y += sum_j Re(g_{j,c} alpha^s_k p^s_k) (the weighted sum of the iterates).
+template <int CPL, int NZ>
+__global__ __launch_bounds__(kMT) void k_ms_update_y(int n, int kp, int nz, MsCols cols,
+                                                     double* __restrict__ r,
+                                                     const double* __restrict__ w,
+                                                     double* __restrict__ y,
+                                                     cpx<double>* __restrict__ Ps,
+                                                     double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int cl = lane * CPL;
+  double alpha[CPL];
+  bool on[CPL], lv[CPL][NZ];
+  zd ip[CPL][NZ], bs[CPL][NZ], ga[CPL][NZ];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    on[q] = cols.colive[cl + q] != 0;
+    alpha[q] = cols.alpha[cl + q];
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      const int e = j * kp + cl + q;
+      lv[q][j] = j < nz && cols.live[e] != 0;
+      ip[q][j] = lv[q][j] ? zd{cols.ipi[e].re, cols.ipi[e].im} : zd{0.0, 0.0};
+      bs[q][j] = lv[q][j] ? zd{cols.bs[e].re, cols.bs[e].im} : zd{0.0, 0.0};
+      ga[q][j] = lv[q][j] ? zd{cols.gas[e].re, cols.gas[e].im} : zd{0.0, 0.0};
+    }
+  }
+  double acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = 0.0;
+  const Rows rw = my_rows(n);
+  const size_t blk = (size_t)n * kp;
+  for (int t = 0; t < rw.count; ++t) {
+    const size_t o = (size_t)(rw.first + rw.stride * t) * kp + cl;
+    double ro[CPL], yo[CPL];
+    cpx<double> po[CPL][NZ];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      ro[q] = on[q] ? r[o + q] : 0.0;
+      yo[q] = on[q] ? y[o + q] : 0.0;
+#pragma unroll
+      for (int j = 0; j < NZ; ++j)
+        if (lv[q][j]) po[q][j] = Ps[j * blk + o + q];
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      if (!on[q]) continue;
+      const double rn = ro[q] - alpha[q] * w[o + q];
+      r[o + q] = rn;
+      acc[q] += rn * rn;
+      double yv = yo[q];
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) {
+        if (!lv[q][j]) continue;
+        const zd b = bs[q][j];
+        const double pr = ro[q] * ip[q][j].re + (b.re * po[q][j].re - b.im * po[q][j].im);
+        const double pi = ro[q] * ip[q][j].im + (b.re * po[q][j].im + b.im * po[q][j].re);
+        Ps[j * blk + o + q] = cpx<double>{pr, pi};
+        yv += ga[q][j].re * pr - ga[q][j].im * pi;
+      }
+      y[o + q] = yv;
+    }
+  }
+  put_partial<CPL>(acc, part, kp);
+}
+
+// Combining mode, generic shift count: as k_ms_update with y in place of the
+// iterates.
+template <int CPL>
+__global__ __launch_bounds__(kMT) void k_ms_update_yg(int n, int kp, int nz, MsCols cols,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ w,
+                                                      double* __restrict__ y,
+                                                      cpx<double>* __restrict__ Ps,
+                                                      double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int cl = lane * CPL;
+  double alpha[CPL];
+  bool on[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    on[q] = cols.colive[cl + q] != 0;
+    alpha[q] = cols.alpha[cl + q];
+  }
+  double acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = 0.0;
+  const Rows rw = my_rows(n);
+  const size_t blk = (size_t)n * kp;
+  for (int t = 0; t < rw.count; ++t) {
+    const size_t o = (size_t)(rw.first + rw.stride * t) * kp + cl;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      if (!on[q]) continue;
+      const double ro = r[o + q];
+      const double rn = ro - alpha[q] * w[o + q];
+      r[o + q] = rn;
+      acc[q] += rn * rn;
+      double yv = y[o + q];
+      for (int j = 0; j < nz; ++j) {
+        const int e = j * kp + cl + q;
+        if (!cols.live[e]) continue;
+        const cpx<double> ip = cols.ipi[e], b = cols.bs[e], ga = cols.gas[e];
+        const cpx<double> po = Ps[j * blk + o + q];
+        const double pr = ro * ip.re + (b.re * po.re - b.im * po.im);
+        const double pi = ro * ip.im + (b.re * po.im + b.im * po.re);
+        Ps[j * blk + o + q] = cpx<double>{pr, pi};
+        yv += ga.re * pr - ga.im * pi;
+      }
+      y[o + q] = yv;
+    }
+  }
+  put_partial<CPL>(acc, part, kp);
+}
+
 // beta_k, beta^s_k = beta_k (pi_k / pi_{k+1})^2, the pi shift, the
 // convergence test |r_{k+1}| / |pi_{k+1}| <= tol |b| (or the iteration cap),
 // the live counts, and the rescale of a column whose seed residual has
 // fallen below 1e-100 |b|.
-__global__ void k_ms_fin_beta(int kp, int nz, int nb, const double* __restrict__ part, double tol,
-                              int maxit, MsCols cols, int* __restrict__ count) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= kp) return;
-  if (!cols.colive[c]) return;
+__global__ __launch_bounds__(kFT) void k_ms_fin_beta(int kp, int nz, int nb,
+                                                     const double* __restrict__ part, double tol,
+                                                     int maxit, MsCols cols,
+                                                     int* __restrict__ count) {
+  const int c = blockIdx.x;
+  if (!cols.colive[c]) return;  // uniform over the workgroup
   const double rn = col_total(part, nb, kp, c);
+  if (threadIdx.x != 0) return;
   const double rr = cols.rr[c];
   const double beta = rr > 0.0 ? rn / rr : 0.0;
   const double bn = cols.bn[c];
@@ -442,11 +664,13 @@ __global__ __launch_bounds__(kMT) void k_ms_true(int n, int k, int kp,
 }
 
 // resid[j k + c] = sqrt(sum of the partials) / |b_c| (0 for b_c = 0).
-__global__ void k_ms_fin_true(int k, int kp, int j, int nb, const double* __restrict__ part,
-                              const double* __restrict__ bn, double* __restrict__ resid) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= k) return;
+__global__ __launch_bounds__(kFT) void k_ms_fin_true(int k, int kp, int j, int nb,
+                                                     const double* __restrict__ part,
+                                                     const double* __restrict__ bn,
+                                                     double* __restrict__ resid) {
+  const int c = blockIdx.x;
   const double s2 = col_total(part, nb, kp, c);
+  if (threadIdx.x != 0 || c >= k) return;
   resid[(size_t)j * k + c] = bn[c] > 0.0 ? sqrt(s2) / bn[c] : 0.0;
 }
 
@@ -470,6 +694,40 @@ __global__ __launch_bounds__(kMT) void k_ms_out(int n, int k, int kp, int nz,
         const cpx<double> x = X[j * blk + (size_t)row * kp + c];
         D[dst + (size_t)j * k + c] = cpx<double>{-x.re, -x.im};
       }
+    }
+  }
+}
+
+// Combining mode output: Qt[perm[row]][c] = gq_c Qin[perm[row]][c] - y[row][c]
+// (d = -x, so the weighted sum of the solutions is -y) with
+// gq_c = sum_j Re(g_{j,c}) (the residual form's q term; Qin null: 0).
+template <int CPL>
+__global__ __launch_bounds__(kMT) void k_ms_out_y(int n, int k, int kp, int nz,
+                                                  const int* __restrict__ perm,
+                                                  const double* __restrict__ y,
+                                                  const double* __restrict__ g,
+                                                  const double* __restrict__ Qin, int ldqin,
+                                                  double* __restrict__ Qt, int ldq) {
+  const int lane = threadIdx.x & 63;
+  double gq[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = lane * CPL + q;
+    double s = 0.0;
+    if (c < k && Qin)
+      for (int j = 0; j < nz; ++j) s += g[2 * (j * k + c)];
+    gq[q] = s;
+  }
+  const Rows rw = my_rows(n);
+  for (int t = 0; t < rw.count; ++t) {
+    const int row = rw.first + rw.stride * t;
+    const size_t dst = (size_t)perm[row];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int c = lane * CPL + q;
+      if (c >= k) continue;
+      const double qv = Qin ? gq[q] * Qin[dst * ldqin + c] : 0.0;
+      Qt[dst * ldq + c] = qv - y[(size_t)row * kp + c];
     }
   }
 }
@@ -499,7 +757,7 @@ template <int CPL>
 hipError_t run_ms_t(hipStream_t st, const StreamMatrix& A, const MsWork& W, const MsLaunch& L) {
   const int n = A.n, k = L.k, kp = W.kp, nz = L.nz;
   const int nb = W.nb;
-  const dim3 grid(nb), blk(kMT), fg((kp + 63) / 64), fb(64);
+  const dim3 grid(nb), blk(kMT), fg(kp), fb(kFT);
 #define MCHK(expr)                   \
   do {                               \
     hipError_t _e = (expr);          \
@@ -515,8 +773,10 @@ hipError_t run_ms_t(hipStream_t st, const StreamMatrix& A, const MsWork& W, cons
   for (int j = 0; j < nz; ++j) sg[j] = cpx<double>{L.seed - L.z[2 * j], -L.z[2 * j + 1]};
   MCHK(hipMemcpyAsync(W.sig, sg.data(), nz * sizeof(cpx<double>), hipMemcpyHostToDevice, st));
   MCHK(hipMemsetAsync(W.count, 0, sizeof(int), st));
+  const bool comb = L.g != nullptr;
+  double* yb = comb ? W.y : nullptr;
   MLAUNCH((k_ms_init<CPL>), grid, blk, 0, st, n, k, kp, nz, A.perm, L.B, L.ldb, W.r, W.p, W.X,
-          W.P, W.part);
+          W.P, yb, W.part);
   MLAUNCH(k_ms_fin0, fg, fb, 0, st, k, kp, nz, nb, W.part, W.cols, W.count);
   int live = 0;
   MCHK(hipMemcpyAsync(&live, W.count, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -525,14 +785,49 @@ hipError_t run_ms_t(hipStream_t st, const StreamMatrix& A, const MsWork& W, cons
     MLAUNCH((k_ms_pupd<CPL>), grid, blk, 0, st, n, kp, W.cols, W.r, W.p);
     MLAUNCH((k_ms_spmv<CPL>), grid, blk, 0, st, n, kp, A.rowptr, A.col, A.val64, L.seed,
             W.cols.colive, W.p, W.w, W.part);
-    MLAUNCH(k_ms_fin_alpha, fg, fb, 0, st, kp, nz, nb, W.part, W.sig, W.cols);
-    MLAUNCH((k_ms_update<CPL>), grid, blk, 0, st, n, kp, nz, W.cols, W.r, W.w, W.X, W.P, W.part);
+    MLAUNCH(k_ms_fin_alpha, fg, fb, 0, st, kp, k, nz, nb, W.part, W.sig, L.g, W.cols);
+    if (comb) {
+      if (nz * CPL <= 2)
+        MLAUNCH((k_ms_update_y<CPL, (2 / CPL > 0 ? 2 / CPL : 1)>), grid, blk, 0, st, n, kp, nz,
+                W.cols, W.r, W.w, yb, W.P, W.part);
+      else if (nz * CPL <= 4)
+        MLAUNCH((k_ms_update_y<CPL, (4 / CPL > 0 ? 4 / CPL : 1)>), grid, blk, 0, st, n, kp, nz,
+                W.cols, W.r, W.w, yb, W.P, W.part);
+      else if (nz * CPL <= 8)
+        MLAUNCH((k_ms_update_y<CPL, (8 / CPL > 0 ? 8 / CPL : 1)>), grid, blk, 0, st, n, kp, nz,
+                W.cols, W.r, W.w, yb, W.P, W.part);
+      else
+        MLAUNCH((k_ms_update_yg<CPL>), grid, blk, 0, st, n, kp, nz, W.cols, W.r, W.w, yb, W.P,
+                W.part);
+    } else if (nz * CPL <= 1)
+      MLAUNCH((k_ms_update_r<CPL, 1>), grid, blk, 0, st, n, kp, nz, W.cols, W.r, W.w, W.X, W.P,
+              W.part);
+    else if (nz * CPL <= 2)
+      MLAUNCH((k_ms_update_r<CPL, (2 / CPL > 0 ? 2 / CPL : 1)>), grid, blk, 0, st, n, kp, nz,
+              W.cols, W.r, W.w, W.X, W.P, W.part);
+    else if (nz * CPL <= 4)
+      MLAUNCH((k_ms_update_r<CPL, (4 / CPL > 0 ? 4 / CPL : 1)>), grid, blk, 0, st, n, kp, nz,
+              W.cols, W.r, W.w, W.X, W.P, W.part);
+    else if (nz * CPL <= 8)
+      MLAUNCH((k_ms_update_r<CPL, (8 / CPL > 0 ? 8 / CPL : 1)>), grid, blk, 0, st, n, kp, nz,
+              W.cols, W.r, W.w, W.X, W.P, W.part);
+    else
+      MLAUNCH((k_ms_update<CPL>), grid, blk, 0, st, n, kp, nz, W.cols, W.r, W.w, W.X, W.P,
+              W.part);
     MCHK(hipMemsetAsync(W.count, 0, sizeof(int), st));
     MLAUNCH(k_ms_fin_beta, fg, fb, 0, st, kp, nz, nb, W.part, L.tol, L.maxit, W.cols, W.count);
     if ((it + 1) % L.chunk == 0 || it + 1 == L.maxit) {
       MCHK(hipMemcpyAsync(&live, W.count, sizeof(int), hipMemcpyDeviceToHost, st));
       MCHK(hipStreamSynchronize(st));
     }
+  }
+  if (comb) {
+    MLAUNCH((k_ms_out_y<CPL>), grid, blk, 0, st, n, k, kp, nz, A.perm, yb, L.g, L.Qin, L.ldqin,
+            L.Qt, L.ldq);
+    if (L.iters)
+      MLAUNCH(k_ms_report, dim3((nz * k + 255) / 256), dim3(256), 0, st, k, kp, nz, W.cols,
+              L.iters, (double*)nullptr);
+    return hipSuccess;
   }
   MLAUNCH((k_ms_out<CPL>), grid, blk, 0, st, n, k, kp, nz, A.perm, W.X,
           static_cast<cpx<double>*>(L.D), L.ldd);
@@ -557,6 +852,9 @@ hipError_t run_ms_t(hipStream_t st, const StreamMatrix& A, const MsWork& W, cons
 hipError_t run_mshift(hipStream_t st, const StreamMatrix& A, const MsWork& W, const MsLaunch& L) {
   if (L.k < 1 || L.nz < 1 || L.k > W.kp || W.kp != ms_padded(L.k) || L.nz > W.nz || !A.val64 ||
       W.nb != ms_blocks(A.n, W.num_cu) || L.chunk < 1)
+    return hipErrorInvalidValue;
+  if (L.g ? (!W.y || !W.cols.gas || !L.Qt || L.ldq < L.k || (L.Qin && L.ldqin < L.k))
+          : (!W.X || !L.D || L.ldd < L.nz * L.k))
     return hipErrorInvalidValue;
   switch (ms_cpl(L.k)) {
     case 1: return run_ms_t<1>(st, A, W, L);

@@ -313,6 +313,7 @@ struct MsCols {                  // per column kp entries; per (j, c) nz x kp en
   int* live = nullptr;           // the shifted system still iterates
   int* its = nullptr;            // its iterations
   double* est = nullptr;         // its estimated relative residual |r_k| / (|pi_k| |b|)
+  cpx<double>* gas = nullptr;    // combining mode: g_{j,c} alpha^s_k
 };
 struct MsWork {
   int kp = 0, nz = 0, nb = 0, num_cu = 0;  // nz: the most shifts this workspace holds
@@ -322,6 +323,8 @@ struct MsWork {
   cpx<double>* X = nullptr;      // nz blocks n x kp: shifted iterates
   cpx<double>* P = nullptr;      // nz blocks n x kp: shifted search directions
   double* part = nullptr;        // nb x kp partial sums
+  double* y = nullptr;           // nullable n x kp: the filtered block accumulated in the
+                                 //   combining mode (then X is not used)
   cpx<double>* sig = nullptr;    // [nz] sigma_j = s - z_j
   int* count = nullptr;          // [1] live systems
   MsCols cols;
@@ -340,7 +343,17 @@ struct MsLaunch {
   int chunk = 8;                 // iterations between host reads of the live count
   int* iters = nullptr;          // nullable device [nz k]
   double* resid = nullptr;       // nullable device [nz k]: true relative residuals
-};                               //   |b_c - (z_j I - A) d| / |b_c| in FP64
+                                 //   |b_c - (z_j I - A) d| / |b_c| in FP64
+  // Combining mode (g non-null): the solutions are not stored; the engine
+  // accumulates Qt[:, c] = gq_c Qin[:, c] + sum_j Re(g_{j,c} d_{j,c}) with
+  // gq_c = sum_j Re(g_{j,c}) (0 when Qin is null) into Qt (caller row order,
+  // ldq), the filter combination of one FEAST iteration; D, resid unused.
+  const double* g = nullptr;     // device [2 nz k]: complex g_{j,c} at j k + c
+  const double* Qin = nullptr;   // nullable device n x k (ldqin)
+  int ldqin = 0;
+  double* Qt = nullptr;
+  int ldq = 0;
+};
 int ms_cpl(int k);
 int ms_padded(int k);
 int ms_blocks(int n, int num_cu);

@@ -108,6 +108,7 @@ struct rafeast_plan_s {
   StreamMatrix smat;
   StreamWork swork;               // sized for the nc * m0 systems of a solve
   MsWork mswork;                  // multi-shift engine: sized for nc shifts x m0 columns
+  double* d_wrep = nullptr;       // its literal-form weights: w_j for every column (2 nc m0)
   DenseOp dop;                    // dense operator (kind 0: A is the CSR matrix)
   double* d_k64 = nullptr;        // its device matrices and scratch
   float* d_k32 = nullptr;
@@ -416,7 +417,8 @@ void free_plan(rafeast_plan_s* P) {
                   P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
                   P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm,
                   P->d_k64, P->d_k32, P->d_t64, P->d_t32, P->d_ones64, P->d_ones32,
-                  P->d_mtot, P->d_mtmp, P->d_pcW, P->d_pcWb, P->d_pcX, P->d_pcY, P->d_D64};
+                  P->d_mtot, P->d_mtmp, P->d_pcW, P->d_pcWb, P->d_pcX, P->d_pcY, P->d_D64,
+                  P->d_wrep};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : P->sbufs)
@@ -652,9 +654,11 @@ rafeast_status alloc_stream_work(rafeast_plan_s* P, int Bp, StreamWork& W,
   return RAFEAST_OK;
 }
 
-// Device buffers of a multi-shift workspace for nz shifts and k columns.
+// Device buffers of a multi-shift workspace for nz shifts and k columns: the
+// shifted iterates, or (combining mode, the FEAST filter step) the block they
+// are accumulated into.
 rafeast_status alloc_ms_work(rafeast_plan_s* P, int nz, int k, MsWork& W,
-                             std::vector<void*>& bufs) {
+                             std::vector<void*>& bufs, bool combining = false) {
   const int64_t n = P->n;
   auto get = [&](void** ptr, size_t bytes, const char* what) -> rafeast_status {
     hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
@@ -674,7 +678,10 @@ rafeast_status alloc_ms_work(rafeast_plan_s* P, int nz, int k, MsWork& W,
   RCHK(get((void**)&W.r, blk * sizeof(double), "multi-shift r"));
   RCHK(get((void**)&W.p, blk * sizeof(double), "multi-shift p"));
   RCHK(get((void**)&W.w, blk * sizeof(double), "multi-shift w"));
-  RCHK(get((void**)&W.X, nz * blk * sizeof(cpx<double>), "multi-shift x"));
+  if (combining)
+    RCHK(get((void**)&W.y, blk * sizeof(double), "multi-shift filtered block"));
+  else
+    RCHK(get((void**)&W.X, nz * blk * sizeof(cpx<double>), "multi-shift x"));
   RCHK(get((void**)&W.P, nz * blk * sizeof(cpx<double>), "multi-shift p^s"));
   RCHK(get((void**)&W.part, (size_t)W.nb * W.kp * sizeof(double), "multi-shift partials"));
   RCHK(get((void**)&W.sig, nz * sizeof(cpx<double>), "multi-shift sigma"));
@@ -696,6 +703,7 @@ rafeast_status alloc_ms_work(rafeast_plan_s* P, int nz, int k, MsWork& W,
   RCHK(get((void**)&c.live, cs * sizeof(int), "ms live"));
   RCHK(get((void**)&c.its, cs * sizeof(int), "ms its"));
   RCHK(get((void**)&c.est, cs * sizeof(double), "ms est"));
+  if (combining) RCHK(get((void**)&c.gas, cs * sizeof(cpx<double>), "ms g alpha^s"));
   return RAFEAST_OK;
 }
 
@@ -893,6 +901,30 @@ rafeast_status run_stream(rafeast_plan_s* P, const StreamWork& W, int nz, int k,
   return RAFEAST_OK;
 }
 
+// Multi-shift engine in combining mode for one FEAST filter step: the
+// weights g (gamma_{j,i} of the residual form, w_j of the literal form) on
+// the device, the filtered block written to P->d_Y.
+rafeast_status run_ms_combine(rafeast_plan_s* P, const double* B, const double* g,
+                              const double* Qin) {
+  MsLaunch L;
+  L.B = B;
+  L.ldb = P->ld;
+  L.k = P->m0;
+  L.nz = P->nc;
+  L.z = P->zw.data();
+  L.seed = ms_seed(P);
+  L.tol = P->tau;
+  L.maxit = P->prm.max_cocg;
+  L.iters = P->d_iters;
+  L.g = g;
+  L.Qin = Qin;
+  L.ldqin = P->ld;
+  L.Qt = P->d_Y;
+  L.ldq = P->ld;
+  HIPCHK(P, run_mshift(P->st, P->smat, P->mswork, L));
+  return RAFEAST_OK;
+}
+
 // Multi-shift engine: the nz shifts of every column c < k in one seed CG.
 rafeast_status run_ms(rafeast_plan_s* P, const MsWork& W, int nz, const double* z, int k,
                       const double* B, int ldb, void* D, int ldd, double tol, int* d_iters,
@@ -1070,6 +1102,7 @@ struct SolveRun {
   std::vector<int64_t> cocg_node;  // per quadrature node, summed over columns and iterations
   int pc_fallbacks = 0;
   bool pc_solved = false;          // the last solves ran preconditioned (iters filled on host)
+  bool combined = false;           // the solves wrote the filtered block themselves (d_Y)
   bool breakdown = false, done = false;
   double t_ph[RAFEAST_NPHASE] = {0, 0, 0, 0, 0};
 };
@@ -1229,10 +1262,17 @@ rafeast_status solve_shifted_systems(rafeast_plan_s* P, SolveRun& S) {
   const int m0 = P->m0, nc = P->nc, ld = P->ld;
   const bool residual_form = P->prm.rhs_form == RAFEAST_RHS_RESIDUAL;
   S.pc_solved = false;
+  S.combined = false;
   if (P->prm.precond == RAFEAST_PC_LEARNED) return solve_learned(P, S);
-  if (P->engine == RAFEAST_ENGINE_MULTISHIFT)
-    return run_ms(P, P->mswork, nc, P->zw.data(), m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D,
-                  nc * m0, P->tau, P->d_iters);
+  if (P->engine == RAFEAST_ENGINE_MULTISHIFT) {
+    // the filter combination happens inside the engine: weights first
+    if (residual_form)
+      HIPCHK(P, launch_gamma(P->st, nc, m0, P->d_zw, P->d_theta, P->d_gamma));
+    RCHK(run_ms_combine(P, residual_form ? P->d_R : P->d_Q,
+                        residual_form ? P->d_gamma : P->d_wrep, residual_form ? P->d_Q : nullptr));
+    S.combined = true;
+    return RAFEAST_OK;
+  }
   if (P->engine == RAFEAST_ENGINE_STREAM)
     return run_stream(P, P->swork, nc, m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D, nc * m0,
                       P->tau, P->d_iters);
@@ -1249,10 +1289,12 @@ rafeast_status solve_combine(rafeast_plan_s* P, SolveRun& S) {
   if (!S.pc_solved)
     HIPCHK(P, hipMemcpyAsync(S.iters.data(), P->d_iters, P->nitems * sizeof(int),
                              hipMemcpyDeviceToHost, P->st));
-  HIPCHK(P, launch_gamma(P->st, nc, m0, P->d_zw, P->d_theta, P->d_gamma));
-  HIPCHK(P, launch_combine(P->st, n, nc, m0, P->d_gamma, P->d_zw, residual_form, P->d_Q, ld,
-                           S.pc_solved ? P->d_D64 : P->d_D, nc * m0,
-                           S.pc_solved ? false : P->fp32, P->d_Y, ld));
+  if (!S.combined) {
+    HIPCHK(P, launch_gamma(P->st, nc, m0, P->d_zw, P->d_theta, P->d_gamma));
+    HIPCHK(P, launch_combine(P->st, n, nc, m0, P->d_gamma, P->d_zw, residual_form, P->d_Q, ld,
+                             S.pc_solved ? P->d_D64 : P->d_D, nc * m0,
+                             S.pc_solved ? false : P->fp32, P->d_Y, ld));
+  }
   HIPCHK(P, hipEventRecord(P->ev[4], P->st));
   std::swap(P->d_Q, P->d_Y);
   int ci = 0;
@@ -1849,7 +1891,9 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
   P->part_doubles = std::max(gram_partial_doubles(n, w, w), (size_t)2 * w * gram_chunks(n));
   PRCHK(dalloc(P, &P->d_part, P->part_doubles, "partials"));
   const size_t cs = fp32 ? 2 * sizeof(float) : 2 * sizeof(double);
-  {
+  // the solutions of one filter step (the multi-shift engine combines them
+  // as it goes and needs no such block unless the learned solver runs)
+  if (P->engine != RAFEAST_ENGINE_MULTISHIFT || prm->precond == RAFEAST_PC_LEARNED) {
     hipError_t e = hipMalloc(&P->d_D, (size_t)n * P->nc * P->m0 * cs);
     if (e != hipSuccess) return bail(hip_fail(P, e, "solve block"));
   }
@@ -1878,7 +1922,17 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     hipError_t e = hipMalloc(&P->d_xhi, P->xhi_slots * 2 * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(P, e, "solution scratch"));
   } else if (P->engine == RAFEAST_ENGINE_MULTISHIFT) {
-    PRCHK(alloc_ms_work(P, P->nc, P->m0, P->mswork, P->sbufs));
+    PRCHK(alloc_ms_work(P, P->nc, P->m0, P->mswork, P->sbufs, true));
+    if (prm->rhs_form == RAFEAST_RHS_LITERAL) {  // literal form: g_{j,c} = w_j
+      std::vector<double> wr(2 * (size_t)P->nc * P->m0);
+      for (int j = 0; j < P->nc; ++j)
+        for (int c = 0; c < P->m0; ++c) {
+          wr[2 * ((size_t)j * P->m0 + c)] = P->zw[2 * P->nc + 2 * j];
+          wr[2 * ((size_t)j * P->m0 + c) + 1] = P->zw[2 * P->nc + 2 * j + 1];
+        }
+      PRCHK(dalloc(P, &P->d_wrep, wr.size(), "repeated weights"));
+      PCHK(hipMemcpy(P->d_wrep, wr.data(), wr.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
   } else {
     const int Bp = stream_padded_columns(P->m0, P->nc * P->m0, fp32);
     PRCHK(alloc_stream_work(P, Bp, P->swork, P->sbufs));
