@@ -65,11 +65,10 @@ def test_stream_column_groups(gpu_lib, torch_dev, precision, k):
     assert its.max() > 10
 
 
-# About four minutes on one MI355X (four rounds of 512 FP32 COCG solves with
-# up to 20000 iterations each), so it runs only when asked for.
+# The precision form as specified (complex-FP32 COCG with FP64 reliable
+# updates, fixed 1e-6 tolerance): about two and a half minutes on one MI355X
+# (four rounds of 512 FP32 COCG solves of up to 20000 iterations each).
 @pytest.mark.slow
-@pytest.mark.skipif(os.environ.get("RAFEAST_SLOW_TESTS", "0") in ("", "0"),
-                    reason="set RAFEAST_SLOW_TESTS=1 to run the 64^3 precision-form solve")
 def test_grid3d_64_interior_window(gpu_lib):
     dims, shift = (64, 64, 64), 0.01
     csr = grid_laplacian(dims, shift)
@@ -108,6 +107,26 @@ def test_grid3d_64_interior_window_relaxed(gpu_lib):
         assert plan.engine == "stream"
         om = gaussian(csr.n, m0 + p, 0)
         ws = plan.warmstart(omega=om)
+        out = plan.solve()
+    assert ws["op"] == "fold"
+    assert out["status"] == "OK"
+    check_against(out, A, vals, V, lmin, lmax, 1e-10, gap)
+
+
+# The same window with the FP64 multi-shift engine at the fixed 1e-6
+# tolerance (about half a minute).
+def test_grid3d_64_interior_window_multishift(gpu_lib):
+    dims, shift = (64, 64, 64), 0.01
+    csr = grid_laplacian(dims, shift)
+    A = csr.to_scipy()
+    lmin, lmax = 0.493673151133, 0.506687779116
+    vals, V = window_basis(dims, shift, lmin, lmax)
+    allv, _ = grid_eigs(dims, shift)
+    gap = gap_out(allv, lmin, lmax)
+    with gpu_lib.Plan(csr, lmin, lmax, 64, nc=8, q=2, p=20, precision="fp64",
+                      engine="multishift", tol_solve=1e-6, tol_eig=1e-10) as plan:
+        assert plan.engine == "multishift"
+        ws = plan.warmstart(omega=gaussian(csr.n, 84, 0))
         out = plan.solve()
     assert ws["op"] == "fold"
     assert out["status"] == "OK"
