@@ -87,11 +87,19 @@ def _samples(count=12, seed=3):
     return np.array(X), np.array(G), np.array(h), np.array(rr)
 
 
-def test_network_gradient_against_finite_differences():
+@pytest.mark.parametrize("standardize", [False, True])
+def test_network_gradient_against_finite_differences(standardize):
     params = [(W.astype(np.float64), b.astype(np.float64) + 0.01) for W, b in init_weights(7)]
     assert sum(W.size + b.size for W, b in params) == parameter_count() == 9680
     X, G, h, rr = _samples()
-    grads = Lr.batch_grad(params, X, G, h, rr)
+    # the input standardization of the training features (a fixed affine map
+    # of the inputs: the gradient with respect to the weights goes through it)
+    norm = None
+    if standardize:  # constant features (the Ritz values here) keep sd = 1
+        mu, sd = X.mean(axis=0), X.std(axis=0)
+        sd[sd <= 1e-9 * np.maximum(1.0, np.abs(mu))] = 1.0
+        norm = (mu, sd)
+    grads = Lr.batch_grad(params, X, G, h, rr, norm=norm)
     rng = np.random.default_rng(4)
     for l in range(len(params)):
         for which in (0, 1):
@@ -100,13 +108,32 @@ def test_network_gradient_against_finite_differences():
             old = P[idx]
             eps = 1e-6 * max(1.0, abs(old))
             P[idx] = old + eps
-            lp = Lr.batch_loss(params, X, G, h, rr)
+            lp = Lr.batch_loss(params, X, G, h, rr, norm=norm)
             P[idx] = old - eps
-            lm = Lr.batch_loss(params, X, G, h, rr)
+            lm = Lr.batch_loss(params, X, G, h, rr, norm=norm)
             P[idx] = old
             fd = (lp - lm) / (2 * eps)
             an = grads[l][which][idx]
             assert abs(an - fd) <= 1e-6 * max(abs(fd), 1e-6), (l, which, an, fd)
+
+
+def test_network_outputs_are_scaled_coefficients():
+    # c_k = (y_2k + i y_2k+1) / Im z^: a network whose outputs equal
+    # Im z^ times the optimal coefficients reaches the per-sample optimum
+    X, G, h, rr = _samples(count=3)
+    Y = np.zeros((3, 16))
+    for s in range(3):
+        c = Lr.c_star(G[s], h[s]) * X[s, 1]
+        Y[s, 0::2], Y[s, 1::2] = c.real, c.imag
+    C = Lr.coeffs(Y, X)
+    for s in range(3):
+        np.testing.assert_allclose(C[s], Lr.c_star(G[s], h[s]), rtol=1e-12)
+        assert Lr.quad_loss(C[s], G[s], h[s], rr[s]) <= Lr.quad_loss(0 * C[s], G[s], h[s], rr[s])
+    # and the standardization is (x - mu) / sd before the first layer
+    params = [(W.astype(np.float64), b.astype(np.float64)) for W, b in init_weights(2)]
+    mu, sd = X.mean(axis=0), np.array([0.5, 2.0, 4.0, 8.0])
+    np.testing.assert_allclose(Lr.mlp_forward(params, X, (mu, sd))[0],
+                               Lr.mlp_forward(params, (X - mu) / sd)[0], rtol=1e-14)
 
 
 def test_preconditioned_cocg_against_direct_solve():
