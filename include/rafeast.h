@@ -273,8 +273,9 @@ void rafeast_destroy(rafeast_plan_t plan);
  * plan is NULL).  Valid until the next call on the same plan. */
 const char* rafeast_last_error(rafeast_plan_t plan);
 
-/* Static name of a status code. */
-const char* rafeast_status_string(rafeast_status s);
+/* Static name of a status code.  Takes any int: a value that is not one of
+ * the rafeast_status codes gives "UNKNOWN". */
+const char* rafeast_status_string(int s);
 
 /* Gershgorin interval, ||A||_inf, nnz and the quadrature table of a plan.
  * z and w: nullable host arrays of 2*nc doubles (re, im interleaved), the

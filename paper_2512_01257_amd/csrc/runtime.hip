@@ -1411,7 +1411,9 @@ void rafeast_params_default(rafeast_params* p) {
   p->hip_stream = nullptr;
 }
 
-const char* rafeast_status_string(rafeast_status s) {
+const char* rafeast_status_string(int s) {
+  // switched on as int: a C caller may pass any value, and an enum object
+  // holding one outside the enumerators is undefined in C++
   switch (s) {
     case RAFEAST_OK: return "OK";
     case RAFEAST_INVALID_ARG: return "INVALID_ARG";

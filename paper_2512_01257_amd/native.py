@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librafeast.so")
+# RAFEAST_LIB selects another build of the library (the sanitizer build of
+# the CPU tests); by default the in-tree one
+LIB_PATH = os.environ.get("RAFEAST_LIB") or os.path.join(_HERE, "librafeast.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "rafeast.h")
 
 STATUS = {
