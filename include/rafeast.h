@@ -369,7 +369,12 @@ rafeast_status rafeast_syev(rafeast_plan_t plan, int32_t k, const double* H, dou
  * iters: nullable host [nz*k] COCG iterations per system.  resid: nullable
  * host [nz*k], ||B_c - (z_j I - A) x|| / ||B_c|| of the FP64 solution (the
  * stopping test is resid <= tol, tol relative).  Zero right-hand sides give
- * zero solutions. */
+ * zero solutions.  A system whose COCG breaks down (p^T (z_j I - A) p = 0, or
+ * a non-finite step) restarts from its true residual; after the fourth
+ * breakdown it stops with its last FP64 solution and residual (resid > tol
+ * tells the caller; the status stays OK).  The multi-shift engine takes
+ * shifts off the real axis only (INVALID_ARG for Im z_j == 0): it divides by
+ * the seed's residual polynomial at z_j, which has real roots. */
 rafeast_status rafeast_shifted_solve(rafeast_plan_t plan, int32_t nz, const double* z, int32_t k,
                                      const double* B, int32_t ldb, void* X, double tol,
                                      int32_t* iters, double* resid);

@@ -1,6 +1,6 @@
 """Builds a variant of librafeast.so whose host code is instrumented with
 AddressSanitizer and UndefinedBehaviorSanitizer (device code is compiled as
-usual) under _build/sanitize/.  The CPU tests of the ABI's validation paths
+usual), by default under _build/sanitize/.  The CPU tests of the ABI's validation paths
 and of the RCM ordering run against it (RAFEAST_LIB selects it, the
 sanitizer runtime is preloaded); no GPU run uses it.
 """
@@ -28,8 +28,9 @@ def asan_runtime() -> str:
     raise RuntimeError("libclang_rt.asan-x86_64.so not found")
 
 
-def build(jobs: int = 8) -> str:
-    return _b.build(jobs, OUTDIR, LIB, COMPILE, LINK)
+def build(jobs: int = 8, outdir: str = OUTDIR) -> str:
+    """Objects and librafeast.so in outdir; returns the library's path."""
+    return _b.build(jobs, outdir, os.path.join(outdir, "librafeast.so"), COMPILE, LINK)
 
 
 if __name__ == "__main__":

@@ -2298,7 +2298,13 @@ rafeast_status rafeast_shifted_solve(rafeast_plan_t P, int32_t nz, const double*
     if (P->engine == RAFEAST_ENGINE_MULTISHIFT) {
       std::vector<void*> bufs;
       MsWork W;
-      if (k > 192)
+      // pi_k = R_k(z_j - s) can vanish for a real z_j inside the seed's
+      // spectrum: the engine takes shifts off the real axis only
+      bool real_shift = false;
+      for (int j = 0; j < nz; ++j) real_shift = real_shift || !(z[2 * j + 1] != 0.0);
+      if (real_shift)
+        s = fail(P, RAFEAST_INVALID_ARG, "the multi-shift engine takes shifts with Im z != 0");
+      else if (k > 192)
         s = fail(P, RAFEAST_UNSUPPORTED, "the multi-shift engine takes k <= 192");
       else
         s = alloc_ms_work(P, nz, k, W, bufs);

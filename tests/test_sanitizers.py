@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_abi_and_rcm_clean_under_asan_ubsan(tmp_path):
     from paper_2512_01257_amd import build_sanitize as bs
 
-    lib = bs.build()
+    lib = bs.build(outdir=str(tmp_path))
     env = dict(os.environ)
     env.update(
         LD_PRELOAD=bs.asan_runtime(),
