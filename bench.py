@@ -141,6 +141,47 @@ def gram_shapes(reps=5):
     return out
 
 
+def gemm_shapes(reps=6):
+    """The matrix-core GEMM behind the dense operators of the statistical
+    workloads (rafeast_gemm), on the products of the stats workload at their
+    full width: the kernel matrix's K P (8192 x 8192 times 1024 columns) and
+    the covariance's X V (1024 x 65536 data, 512 columns; the inner dimension
+    split in chunks) and X^T T, in FP32 and FP64.  Wall-clock per call
+    (includes the call's workspace allocation and its synchronisation); the
+    kernels' own durations come from rocprofv3."""
+    import torch
+
+    from paper_2512_01257_amd import native
+
+    peak = {"fp32": 157.3, "fp64": 78.6}
+    out = {}
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        for name, acol, M, N, K in (("kernel_KP", True, 8192, 1024, 8192),
+                                    ("cov_XV", True, 1024, 512, 65536),
+                                    ("cov_XtT", False, 65536, 512, 1024)):
+            A = torch.randn((K, M) if acol else (M, K), dtype=dt, device="cuda")
+            B = torch.randn((K, N), dtype=dt, device="cuda")
+            Cm = torch.zeros((M, N), dtype=dt, device="cuda")
+            native.gemm(A, B, Cm, a_cols=acol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                native.gemm(A, B, Cm, a_cols=acol)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            ref = (A.T if acol else A).double() @ B.double()
+            err = float((Cm.double() - ref).abs().max() / ref.abs().max())
+            tf = 2.0 * M * N * K / ms / 1e9
+            out[f"{name}_{prec}"] = dict(M=M, N=N, K=K, wall_ms=round(ms, 3),
+                                         tflops_wall=round(tf, 1),
+                                         frac_of_peak_wall=round(tf / peak[prec], 3),
+                                         rel_diff_vs_fp64=err)
+            print(f"gemm {name} {prec}: {ms:.3f} ms", flush=True)
+            del A, B, Cm, ref
+            torch.cuda.empty_cache()
+    return out
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo), or the platform string."""
     try:
@@ -761,6 +802,8 @@ def main():
     ap.add_argument("--max-cocg", type=int, default=20000, help="grid64: COCG iteration cap")
     ap.add_argument("--gram-only", action="store_true",
                     help="only the tall-skinny FP64 MFMA kernels (Gram, CholQR2) at n = 1e6")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="only the matrix-core GEMM of the statistical workloads' operators")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the FP64 SpMM rate measurement (for profiling)")
     ap.add_argument("--rgg-n", default="2000,4000,8000,16000", help="rgg: graph sizes")
@@ -788,6 +831,12 @@ def main():
 
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         print(json.dumps({"gram": gram_shapes()}), flush=True)
+        return
+    if args.gemm_only:
+        import torch
+
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps({"gemm": gemm_shapes()}), flush=True)
         return
     if args.spmm_only:
         import torch

@@ -348,6 +348,25 @@ rafeast_status rafeast_gram_noalloc(void* hip_stream, int64_t n, int32_t k1, int
                                     const double* X, int32_t ldx, const double* Y, int32_t ldy,
                                     double* G, int32_t ldg);
 
+/* C = alpha op(A) B + beta C on the matrix cores: the product form of the
+ * dense operators of Section 4 (kernel matrix, eq. kernel-eig: K X; sample
+ * covariance, eq. sample-cov: Xd^T (Xd X) / (rows - 1)).  C (M x N, ldc >= N)
+ * and B (K x N, ldb >= N) row-major; op(A) M x K stored by rows (a_cols = 0:
+ * op(A)(i, k) = A[i lda + k], lda >= K) or by columns (a_cols = 1:
+ * A[k lda + i], lda >= M).  precision RAFEAST_FP64 (double buffers,
+ * v_mfma_f64_16x16x4f64) or RAFEAST_FP32_REFINED (float buffers,
+ * v_mfma_f32_16x16x4f32); alpha and beta are rounded to the buffers' type.
+ * All pointers device, caller-owned (A and B may be null when K == 0, C when
+ * M N == 0); beta == 0 does not read C.  A long inner
+ * dimension with few output tiles is split into chunks summed in a fixed
+ * order in a workspace this call allocates and frees.  Runs on hip_stream
+ * (nullable: the null stream) and waits for it.  Errors: INVALID_ARG for null
+ * pointers, negative sizes, short leading dimensions or another precision;
+ * OOM; DEVICE. */
+rafeast_status rafeast_gemm(void* hip_stream, int32_t precision, int32_t a_cols, int32_t M,
+                            int32_t N, int32_t K, const void* A, int64_t lda, const void* B,
+                            int64_t ldb, void* C, int64_t ldc, double alpha, double beta);
+
 /* CholQR2 of an n x k block in place (Y <- Y R^{-1}, twice), k <= 192, with
  * column scaling; when the first Cholesky fails, the shifted variant is used
  * and a third pass added.  *info (host, nullable): 0 plain, 1 shifted,

@@ -62,9 +62,8 @@ def build(jobs: int = 8, outdir: str = BUILD, lib: str = LIB, extra_compile=(),
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda src: _compile(src, outdir, extra_compile), srcs))
     tmp = lib + ".tmp"
-    # rocBLAS serves the dense operators' GEMMs (statistical workloads)
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-           "-L/opt/rocm/lib", "-lrocblas", *extra_link]
+           *extra_link]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -197,28 +197,32 @@ struct DenseOp {
   int kind = 0;
   int64_t n = 0, rows = 0;
   double scale = 1.0;
-  const double* a64 = nullptr;     // K or X, FP64
+  const double* a64 = nullptr;     // K or Xd (column-major, ld rows), FP64
   const float* a32 = nullptr;      // the same, FP32
-  double* t64 = nullptr;           // kind 2: X V (rows x tcols) and, when split > 1,
-  float* t32 = nullptr;            // split + 1 partial products after it
-  int64_t tcols = 0;
-  int split = 1;                   // kind 2: chunks of the inner dimension n of X V
-  const double* ones64 = nullptr;  // [split + 1] ones (the partial sums as a GEMV)
-  const float* ones32 = nullptr;
-  void* blas = nullptr;            // rocblas_handle
+  double* t64 = nullptr;           // workspace of wslabs slabs of rows x tcols: kind 2,
+  float* t32 = nullptr;            // Xd X in the first and the inner-dimension chunks of
+                                   // its product after it; kind 1, the chunks of K X
+  int64_t tcols = 0;               // most columns a product takes
+  int wslabs = 0;
 };
 // Y = alpha A X + beta Y for row-major n x k blocks X (ldx) and Y (ldy),
-// FP64; k <= tcols for kind 2.
+// FP64; k <= tcols.
 hipError_t dense_apply_f64(const DenseOp& A, hipStream_t st, int k, const double* X, int ldx,
                            double* Y, int ldy, double alpha, double beta);
 // Y = A X in FP32, same layout.
 hipError_t dense_apply_f32(const DenseOp& A, hipStream_t st, int k, const float* X, int ldx,
                            float* Y, int ldy);
 // y += a x over count contiguous doubles.
-hipError_t dense_axpy(const DenseOp& A, hipStream_t st, int64_t count, double a, const double* x,
-                      double* y);
-hipError_t dense_create_handle(void** blas);
-void dense_destroy_handle(void* blas);
+hipError_t dense_axpy(hipStream_t st, int64_t count, double a, const double* x, double* y);
+// C (M x N, row-major, ldc) = alpha op(A) B + beta C on the matrix cores;
+// op(A)(i, k) = A[k lda + i] when acol, else A[i lda + k]; B (K x N) by rows.
+// work (nullable): room for inner-dimension chunk slabs (work_elems elements).
+hipError_t launch_gemm_f64(hipStream_t st, bool acol, int M, int N, int K, const double* A,
+                           int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                           double alpha, double beta, double* work, size_t work_elems);
+hipError_t launch_gemm_f32(hipStream_t st, bool acol, int M, int N, int K, const float* A,
+                           int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
+                           float alpha, float beta, float* work, size_t work_elems);
 
 struct StreamMatrix {
   int n = 0;

@@ -114,8 +114,6 @@ struct rafeast_plan_s {
   float* d_k32 = nullptr;
   double* d_t64 = nullptr;
   float* d_t32 = nullptr;
-  double* d_ones64 = nullptr;
-  float* d_ones32 = nullptr;
   std::vector<void*> sbufs;       // device buffers behind swork
   int nitems = 0;
   bool have_start = false;
@@ -416,7 +414,7 @@ void free_plan(rafeast_plan_s* P) {
                   P->d_res,    P->d_qn,   P->d_gamma, P->d_info,  P->d_zw,   P->d_part,
                   P->d_D,      P->d_items, P->d_counter, P->d_iters, P->d_stats, P->d_flag,
                   P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm,
-                  P->d_k64, P->d_k32, P->d_t64, P->d_t32, P->d_ones64, P->d_ones32,
+                  P->d_k64, P->d_k32, P->d_t64, P->d_t32,
                   P->d_mtot, P->d_mtmp, P->d_pcW, P->d_pcWb, P->d_pcX, P->d_pcY, P->d_D64,
                   P->d_wrep};
   for (void* p : ptrs)
@@ -425,7 +423,6 @@ void free_plan(rafeast_plan_s* P) {
     if (p) (void)hipFree(p);
   for (auto& e : P->ev)
     if (e) (void)hipEventDestroy(e);
-  dense_destroy_handle(P->dop.blas);
   if (P->own_stream && P->st) (void)hipStreamDestroy(P->st);
   delete P;
 }
@@ -736,11 +733,11 @@ rafeast_status spmm(rafeast_plan_s* P, int k, const double* X, int ldx, double* 
     HIPCHK(P, dense_apply_f64(P->dop, P->st, k, X, ldx, Y, ldy, alpha, 0.0));
     if (beta != 0.0) {
       if (ldx != k || ldy != k) return fail(P, RAFEAST_UNSUPPORTED, "strided dense update");
-      HIPCHK(P, dense_axpy(P->dop, P->st, P->n * (int64_t)k, beta, X, Y));
+      HIPCHK(P, dense_axpy(P->st, P->n * (int64_t)k, beta, X, Y));
     }
     if (X2) {
       if (ldx2 != k || ldy != k) return fail(P, RAFEAST_UNSUPPORTED, "strided dense update");
-      HIPCHK(P, dense_axpy(P->dop, P->st, P->n * (int64_t)k, gamma, X2, Y));
+      HIPCHK(P, dense_axpy(P->st, P->n * (int64_t)k, gamma, X2, Y));
     }
     return RAFEAST_OK;
   }
@@ -1667,31 +1664,19 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     }
     op.a64 = P->d_k64;
     op.a32 = P->d_k32;
-    if (op.kind == 2) {
-      const int Bp = stream_padded_columns(P->m0, P->nc * P->m0, fp32);
-      op.tcols = std::max<int64_t>(2 * (int64_t)Bp, kMaxSmallK);
-      // X V has a small output and a long inner dimension: split it in
-      // chunks of at least 1024 (at most 32 chunks) so its GEMM fills the chip
-      op.split = (int)std::min<int64_t>(32, std::max<int64_t>(1, n / 1024));
-      const size_t slabs = op.split > 1 ? (size_t)op.split + 2 : 1;
-      PRCHK(dalloc(P, &P->d_t64, slabs * op.rows * op.tcols, "covariance scratch"));
-      PRCHK(dalloc(P, &P->d_t32, slabs * op.rows * op.tcols, "covariance scratch fp32"));
-      op.t64 = P->d_t64;
-      op.t32 = P->d_t32;
-      if (op.split > 1) {
-        const std::vector<double> o64(op.split + 1, 1.0);
-        const std::vector<float> o32(op.split + 1, 1.0f);
-        PRCHK(dalloc(P, &P->d_ones64, o64.size(), "ones"));
-        PRCHK(dalloc(P, &P->d_ones32, o32.size(), "ones fp32"));
-        PCHK(hipMemcpy(P->d_ones64, o64.data(), o64.size() * sizeof(double),
-                       hipMemcpyHostToDevice));
-        PCHK(hipMemcpy(P->d_ones32, o32.data(), o32.size() * sizeof(float),
-                       hipMemcpyHostToDevice));
-        op.ones64 = P->d_ones64;
-        op.ones32 = P->d_ones32;
-      }
-    }
-    PCHK(dense_create_handle(&op.blas));
+    // workspace: the widest product is the streaming engine's packed
+    // complex block (2 Bp real columns) or a small dense step
+    const int Bp = stream_padded_columns(P->m0, P->nc * P->m0, fp32);
+    op.tcols = std::max<int64_t>(2 * (int64_t)Bp, kMaxSmallK);
+    // covariance: X V (rows x tcols) and chunk slabs of its long inner
+    // dimension n (chunks of at least 512, at most 32); kernel: up to four
+    // chunk slabs of K X (n x tcols) for products with few output tiles
+    op.wslabs = op.kind == 2 ? 1 + (int)std::min<int64_t>(32, std::max<int64_t>(1, n / 512)) : 4;
+    const size_t wrows = op.kind == 2 ? (size_t)op.rows : (size_t)n;
+    PRCHK(dalloc(P, &P->d_t64, (size_t)op.wslabs * wrows * op.tcols, "dense workspace"));
+    PRCHK(dalloc(P, &P->d_t32, (size_t)op.wslabs * wrows * op.tcols, "dense workspace fp32"));
+    op.t64 = P->d_t64;
+    op.t32 = P->d_t32;
     std::vector<int> ident(n);
     for (int64_t r = 0; r < n; ++r) ident[r] = (int)r;
     PRCHK(dalloc(P, &P->d_sperm, n, "stream perm"));
@@ -2233,6 +2218,36 @@ rafeast_status rafeast_gram_noalloc(void* hip_stream, int64_t n, int32_t k1, int
   e = launch_gram_chunks(static_cast<hipStream_t>(hip_stream), n, k1, k2, X, ldx, Y, ldy, G, ldg,
                          part, chunks);
   if (e != hipSuccess) return hip_fail(nullptr, e, "rafeast_gram_noalloc: launch");
+  return RAFEAST_OK;
+}
+
+rafeast_status rafeast_gemm(void* hip_stream, int32_t precision, int32_t a_cols, int32_t M,
+                            int32_t N, int32_t K, const void* A, int64_t lda, const void* B,
+                            int64_t ldb, void* C, int64_t ldc, double alpha, double beta) {
+  // A and B may be null when K == 0, C when M N == 0 (nothing is read there)
+  if ((K > 0 && M > 0 && !A) || (K > 0 && N > 0 && !B) || ((int64_t)M * N > 0 && !C) || M < 0 ||
+      N < 0 || K < 0 || ldb < N || ldc < N ||
+      lda < (a_cols ? M : K) || lda < 1 || (a_cols != 0 && a_cols != 1) ||
+      (precision != RAFEAST_FP64 && precision != RAFEAST_FP32_REFINED))
+    return fail(nullptr, RAFEAST_INVALID_ARG, "rafeast_gemm: bad argument");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const bool f64 = precision == RAFEAST_FP64;
+  const size_t es = f64 ? sizeof(double) : sizeof(float);
+  // room for as many chunk slabs as the launcher may choose (at most 64)
+  const size_t room = K >= 1024 ? std::min<size_t>(64, (size_t)K / 512) * M * N : 0;
+  void* work = nullptr;
+  if (room) {
+    const hipError_t e = hipMalloc(&work, room * es);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "rafeast_gemm: workspace");
+  }
+  hipError_t e =
+      f64 ? launch_gemm_f64(st, a_cols, M, N, K, (const double*)A, lda, (const double*)B, ldb,
+                            (double*)C, ldc, alpha, beta, (double*)work, room)
+          : launch_gemm_f32(st, a_cols, M, N, K, (const float*)A, lda, (const float*)B, ldb,
+                            (float*)C, ldc, (float)alpha, (float)beta, (float*)work, room);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (work) (void)hipFree(work);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "rafeast_gemm");
   return RAFEAST_OK;
 }
 

@@ -161,6 +161,9 @@ def lib():
     L.rafeast_gram_noalloc.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int32, P,
                                        C.c_int32, P, C.c_int32]
     L.rafeast_gram_noalloc.restype = C.c_int
+    L.rafeast_gemm.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P,
+                               C.c_int64, P, C.c_int64, P, C.c_int64, C.c_double, C.c_double]
+    L.rafeast_gemm.restype = C.c_int
     L.rafeast_cholqr2.argtypes = [P, C.c_int64, C.c_int32, P, C.c_int32, C.POINTER(C.c_int32)]
     L.rafeast_cholqr2.restype = C.c_int
     L.rafeast_syev.argtypes = [P, C.c_int32, P, P, P]
@@ -223,6 +226,29 @@ def gram_noalloc(X, Y, G, stream=None, n=None, k1=None, k2=None):
                                    _tptr(X, torch.float64), X.stride(0),
                                    _tptr(Y, torch.float64), Y.stride(0),
                                    _tptr(G, torch.float64), G.stride(0))
+    if s != 0:
+        raise RafeastError(s, lib().rafeast_last_error(None).decode())
+
+
+def gemm(A, B, Cm, alpha=1.0, beta=0.0, a_cols=False, stream=None):
+    """Cm = alpha op(A) B + beta Cm through rafeast_gemm.  B, Cm: contiguous
+    row-major device tensors (float64 or float32, K x N and M x N); A: the
+    same dtype, op(A) = A (M x K, a_cols False) or op(A) = A^T with A stored
+    K x M (a_cols True: op(A)(i, k) = A[k, i])."""
+    import torch
+
+    dt = Cm.dtype
+    prec = PRECISION["fp64"] if dt == torch.float64 else PRECISION["fp32"]
+    M, N = Cm.shape
+    K = A.shape[0] if a_cols else A.shape[1]
+    st = stream if stream is not None else torch.cuda.current_stream()
+
+    def ld(t):  # an empty tensor may report stride 0: its row length then
+        return t.stride(0) if t.numel() else max(1, t.shape[1])
+
+    s = lib().rafeast_gemm(C.c_void_p(st.cuda_stream), prec, int(bool(a_cols)), M, N, K,
+                           _tptr(A, dt), ld(A), _tptr(B, dt), ld(B), _tptr(Cm, dt), ld(Cm),
+                           alpha, beta)
     if s != 0:
         raise RafeastError(s, lib().rafeast_last_error(None).decode())
 

@@ -256,3 +256,17 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")], capture_output=True,
                        text=True, timeout=120, env=env)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_gemm_arguments_checked_before_the_device(native):
+    L = native.lib()
+    p = C.c_void_p(16)  # never dereferenced: every call fails its checks first
+    # short leading dimension of B, unknown precision, bad a_cols, null A,
+    # negative size, short lda for a column-stored A
+    assert L.rafeast_gemm(None, 0, 0, 4, 4, 4, p, 4, p, 3, p, 4, 1.0, 0.0) == 1
+    assert L.rafeast_gemm(None, 7, 0, 4, 4, 4, p, 4, p, 4, p, 4, 1.0, 0.0) == 1
+    assert L.rafeast_gemm(None, 0, 2, 4, 4, 4, p, 4, p, 4, p, 4, 1.0, 0.0) == 1
+    assert L.rafeast_gemm(None, 0, 0, 4, 4, 4, None, 4, p, 4, p, 4, 1.0, 0.0) == 1
+    assert L.rafeast_gemm(None, 0, 0, -1, 4, 4, p, 4, p, 4, p, 4, 1.0, 0.0) == 1
+    assert L.rafeast_gemm(None, 1, 1, 8, 4, 4, p, 4, p, 4, p, 4, 1.0, 0.0) == 1
+    assert "rafeast_gemm" in L.rafeast_last_error(None).decode()
