@@ -94,6 +94,16 @@ enum { RAFEAST_ENGINE_AUTO = 0,
                                         SpMV of the m0 columns per iteration instead of
                                         nc complex ones; vectors in HBM in the streaming
                                         engine's row order.  Never chosen by AUTO */
+enum { RAFEAST_ENGINE_DIRECT = 4 };  /* precision FP64 and CSR plans only: standard FEAST
+                                        with exact solves (Section 5.1's baseline): the plan
+                                        factorizes each z_j I - A once as L D L^T
+                                        (complex symmetric, no pivoting: Im z_j != 0 makes
+                                        every pivot exist) in the band of the reverse
+                                        Cuthill-McKee order, and every filter application
+                                        solves by substitution.  Memory nc n (b + 1) complex
+                                        doubles for bandwidth b (OOM when the device cannot
+                                        hold it; BREAKDOWN if a pivot vanishes).  Reports
+                                        zero COCG iterations.  Never chosen by AUTO */
 
 /* rafeast_params.precond: preconditioner of the shifted solves. */
 enum { RAFEAST_PC_NONE = 0,       /* unpreconditioned COCG on the plan's engine */

@@ -224,6 +224,24 @@ hipError_t launch_gemm_f32(hipStream_t st, bool acol, int M, int N, int K, const
                            int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                            float alpha, float beta, float* work, size_t work_elems);
 
+// Band LDL^T of the shifted matrices (standard FEAST with exact solves).
+// W: nz blocks of n x (b + 1) complex, row r of block j holding
+// (z_j I - A)(r, r - d) in column d, A in engine (reverse Cuthill-McKee)
+// order; factorized in place (D on d = 0, L below).  info: device [nz],
+// 0 or 1 + the row of a vanishing pivot.
+int band_panel_width(int b);
+size_t band_lds_bytes(int b);
+hipError_t band_assemble(hipStream_t st, int n, int b, const int* rowptr, const int* col,
+                         const double* val, int nz, const double* z, cpx<double>* W);
+hipError_t band_factor(hipStream_t st, int n, int b, int nz, cpx<double>* W, int* info);
+// X[:, j k + c] = (z_j I - A)^{-1} B[:, c] (caller order through perm).
+hipError_t band_solve(hipStream_t st, int n, int b, int nz, const cpx<double>* W, const int* perm,
+                      const double* B, int ldb, int k, cpx<double>* X, int64_t ldx);
+// resid[j k + c] = ||B_c - (z_j I - A) X_{j,c}|| / ||B_c||, caller-order CSR.
+hipError_t band_resid(hipStream_t st, int n, const int* rowptr, const int* col, const double* val,
+                      int nz, const double* z, const double* B, int ldb, int k,
+                      const cpx<double>* X, int64_t ldx, double* resid);
+
 struct StreamMatrix {
   int n = 0;
   const DenseOp* dense = nullptr;  // set: A is this dense operator (no CSR; perm identity)

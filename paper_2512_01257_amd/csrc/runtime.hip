@@ -109,6 +109,12 @@ struct rafeast_plan_s {
   StreamWork swork;               // sized for the nc * m0 systems of a solve
   MsWork mswork;                  // multi-shift engine: sized for nc shifts x m0 columns
   double* d_wrep = nullptr;       // its literal-form weights: w_j for every column (2 nc m0)
+  // direct engine: band LDL^T factors of the nc shifted matrices (engine
+  // order), the lower bandwidth, and the factorization's pivot report
+  cpx<double>* d_band = nullptr;
+  int band_b = 0;
+  int* d_binfo = nullptr;
+  float factor_ms = 0.0f;
   DenseOp dop;                    // dense operator (kind 0: A is the CSR matrix)
   double* d_k64 = nullptr;        // its device matrices and scratch
   float* d_k32 = nullptr;
@@ -293,12 +299,16 @@ rafeast_status validate_params(const rafeast_params* p, int64_t n, std::string& 
     msg = "unknown rhs_form";
     return RAFEAST_INVALID_ARG;
   }
-  if (p->engine < RAFEAST_ENGINE_AUTO || p->engine > RAFEAST_ENGINE_MULTISHIFT) {
+  if (p->engine < RAFEAST_ENGINE_AUTO || p->engine > RAFEAST_ENGINE_DIRECT) {
     msg = "unknown engine";
     return RAFEAST_INVALID_ARG;
   }
   if (p->engine == RAFEAST_ENGINE_MULTISHIFT && p->precision != RAFEAST_FP64) {
     msg = "the multi-shift engine runs in FP64 (precision RAFEAST_FP64)";
+    return RAFEAST_INVALID_ARG;
+  }
+  if (p->engine == RAFEAST_ENGINE_DIRECT && p->precision != RAFEAST_FP64) {
+    msg = "the direct engine runs in FP64 (precision RAFEAST_FP64)";
     return RAFEAST_INVALID_ARG;
   }
   if (p->precond != RAFEAST_PC_NONE && p->precond != RAFEAST_PC_LEARNED) {
@@ -416,7 +426,7 @@ void free_plan(rafeast_plan_s* P) {
                   P->d_sel, P->d_xhi, P->d_srow, P->d_scol, P->d_sv32, P->d_sv64, P->d_sperm,
                   P->d_k64, P->d_k32, P->d_t64, P->d_t32,
                   P->d_mtot, P->d_mtmp, P->d_pcW, P->d_pcWb, P->d_pcX, P->d_pcY, P->d_D64,
-                  P->d_wrep};
+                  P->d_wrep, P->d_band, P->d_binfo};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : P->sbufs)
@@ -943,6 +953,32 @@ rafeast_status run_ms(rafeast_plan_s* P, const MsWork& W, int nz, const double* 
   return RAFEAST_OK;
 }
 
+// Direct engine: assemble and factorize z_j I - A for the plan's nc nodes
+// (once per plan: the shifts are fixed).  A vanishing pivot is BREAKDOWN.
+rafeast_status band_factor_shifts(rafeast_plan_s* P) {
+  const int n = (int)P->n, b = P->band_b;
+  hipEvent_t t0 = P->ev[0], t1 = P->ev[1];
+  HIPCHK(P, hipEventRecord(t0, P->st));
+  HIPCHK(P, band_assemble(P->st, n, b, P->d_srow, P->d_scol, P->d_sv64, P->nc, P->d_zw,
+                          P->d_band));
+  HIPCHK(P, band_factor(P->st, n, b, P->nc, P->d_band, P->d_binfo));
+  HIPCHK(P, hipEventRecord(t1, P->st));
+  std::vector<int> info(P->nc);
+  HIPCHK(P, hipMemcpyAsync(info.data(), P->d_binfo, P->nc * sizeof(int), hipMemcpyDeviceToHost,
+                           P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  HIPCHK(P, hipEventElapsedTime(&P->factor_ms, t0, t1));
+  for (int j = 0; j < P->nc; ++j)
+    if (info[j] != 0)
+      return fail(P, RAFEAST_BREAKDOWN,
+                  "LDL^T of z_" + std::to_string(j) + " I - A: pivot " +
+                      std::to_string(info[j] - 1) + " vanished");
+  if (verbose_log())
+    std::fprintf(stderr, "rafeast: direct engine: bandwidth %d, %d shifts factorized in %.2f ms\n",
+                 b, P->nc, P->factor_ms);
+  return RAFEAST_OK;
+}
+
 // Orders (shift, column) pairs longest-first: the smaller Im z, the more COCG
 // iterations a system needs.
 std::vector<int> make_items(int nz, const double* zs, int k, int g = 0) {
@@ -1270,6 +1306,14 @@ rafeast_status solve_shifted_systems(rafeast_plan_s* P, SolveRun& S) {
     S.combined = true;
     return RAFEAST_OK;
   }
+  if (P->engine == RAFEAST_ENGINE_DIRECT) {
+    // exact solves by the factors; no Krylov iterations to report
+    HIPCHK(P, hipMemsetAsync(P->d_iters, 0, P->nitems * sizeof(int), P->st));
+    HIPCHK(P, band_solve(P->st, (int)P->n, P->band_b, nc, P->d_band, P->d_sperm,
+                         residual_form ? P->d_R : P->d_Q, ld, m0,
+                         static_cast<cpx<double>*>(P->d_D), (int64_t)nc * m0));
+    return RAFEAST_OK;
+  }
   if (P->engine == RAFEAST_ENGINE_STREAM)
     return run_stream(P, P->swork, nc, m0, residual_form ? P->d_R : P->d_Q, ld, P->d_D, nc * m0,
                       P->tau, P->d_iters);
@@ -1535,8 +1579,11 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
                 "m0 + p = " + std::to_string(w) + " exceeds the small-matrix limit 192");
   const bool fp32 = prm->precision == RAFEAST_FP32_REFINED;
   int engine = prm->engine;
-  if (D && (engine == RAFEAST_ENGINE_RESIDENT || engine == RAFEAST_ENGINE_MULTISHIFT))
+  if (D && (engine == RAFEAST_ENGINE_RESIDENT || engine == RAFEAST_ENGINE_MULTISHIFT ||
+            engine == RAFEAST_ENGINE_DIRECT))
     return fail(nullptr, RAFEAST_UNSUPPORTED, "dense operators run on the streaming engine");
+  if (engine == RAFEAST_ENGINE_DIRECT && prm->precond != RAFEAST_PC_NONE)
+    return fail(nullptr, RAFEAST_UNSUPPORTED, "the direct engine solves exactly (precond NONE)");
   if (engine == RAFEAST_ENGINE_MULTISHIFT && prm->m0 > 192)
     return fail(nullptr, RAFEAST_UNSUPPORTED, "the multi-shift engine takes m0 <= 192");
   if (D) engine = RAFEAST_ENGINE_STREAM;
@@ -1700,7 +1747,8 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
       PCHK(hipMemcpy(P->d_col, cl.data(), nnz * sizeof(int), hipMemcpyHostToDevice));
       PCHK(hipMemcpy(P->d_val, A->values, nnz * sizeof(double), hipMemcpyHostToDevice));
     }
-    if (engine != RAFEAST_ENGINE_STREAM && engine != RAFEAST_ENGINE_MULTISHIFT) {
+    if (engine != RAFEAST_ENGINE_STREAM && engine != RAFEAST_ENGINE_MULTISHIFT &&
+        engine != RAFEAST_ENGINE_DIRECT) {
     // SELL-64 of the resident engine: rows sorted by decreasing length (ties
     // by index), slices of 64 slots, widths padded to a multiple of 4
     const int nsl = (int)((n + 63) / 64);
@@ -1807,9 +1855,11 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
       P->sell.wave_rpt = rpt;
     }
     }
-    if (engine == RAFEAST_ENGINE_STREAM || engine == RAFEAST_ENGINE_MULTISHIFT) {
+    if (engine == RAFEAST_ENGINE_STREAM || engine == RAFEAST_ENGINE_MULTISHIFT ||
+        engine == RAFEAST_ENGINE_DIRECT) {
       // CSR of the streaming engine in reverse Cuthill-McKee order, so that
-      // the rows a workgroup gathers sit close to its own
+      // the rows a workgroup gathers sit close to its own (and, for the
+      // direct engine, the order whose band holds the factors)
       const std::vector<int> perm = rcm_order(n, rp, cl);
       std::vector<int> inv(n);
       for (int64_t r = 0; r < n; ++r) inv[perm[r]] = (int)r;
@@ -1850,6 +1900,30 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
       P->smat.val32 = P->d_sv32;
       P->smat.val64 = P->d_sv64;
       P->smat.perm = P->d_sperm;
+      if (engine == RAFEAST_ENGINE_DIRECT) {
+        // lower bandwidth of the reordered matrix, and room for the factors
+        int b = 0;
+        for (int64_t r = 0; r < n; ++r)
+          if (srp[r + 1] > srp[r]) b = std::max<int>(b, (int)r - scl[srp[r]]);
+        P->band_b = b;
+        if (band_lds_bytes(b) > 160 * 1024)
+          return bail(fail(P, RAFEAST_UNSUPPORTED,
+                           "bandwidth " + std::to_string(b) +
+                               " of the reordered matrix exceeds the direct engine's panel "
+                               "(one column of b + 1 rows in LDS)"));
+        const size_t bytes = (size_t)P->nc * (size_t)n * (size_t)(b + 1) * sizeof(cpx<double>);
+        size_t fr = 0, tot = 0;
+        PCHK(hipMemGetInfo(&fr, &tot));
+        if (bytes > fr / 10 * 9)
+          return bail(fail(P, RAFEAST_OOM,
+                           "the band factors need " + std::to_string(bytes >> 20) +
+                               " MiB (bandwidth " + std::to_string(b) + ", " +
+                               std::to_string(P->nc) + " shifts); " +
+                               std::to_string(fr >> 20) + " MiB free"));
+        hipError_t e = hipMalloc(&P->d_band, bytes);
+        if (e != hipSuccess) return bail(hip_fail(P, e, "band factors"));
+        PRCHK(dalloc(P, &P->d_binfo, (size_t)P->nc, "band pivot report"));
+      }
     }
     P->engine = engine;
   }
@@ -1908,6 +1982,8 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     P->xhi_slots = cocg_resident_xhi_slots((int)n, P->num_cu);
     hipError_t e = hipMalloc(&P->d_xhi, P->xhi_slots * 2 * sizeof(double));
     if (e != hipSuccess) return bail(hip_fail(P, e, "solution scratch"));
+  } else if (P->engine == RAFEAST_ENGINE_DIRECT) {
+    // the factors are the whole workspace
   } else if (P->engine == RAFEAST_ENGINE_MULTISHIFT) {
     PRCHK(alloc_ms_work(P, P->nc, P->m0, P->mswork, P->sbufs, true));
     if (prm->rhs_form == RAFEAST_RHS_LITERAL) {  // literal form: g_{j,c} = w_j
@@ -1932,6 +2008,7 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     PCHK(hipMemcpy(P->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
   }
   if (P->engine == RAFEAST_ENGINE_RESIDENT) PRCHK(tune_resident(P));
+  if (P->engine == RAFEAST_ENGINE_DIRECT) PRCHK(band_factor_shifts(P));
   PCHK(hipMemset(P->d_stats, 0, 2 * sizeof(int)));
   PCHK(hipDeviceSynchronize());
 #undef PCHK
@@ -2310,7 +2387,42 @@ rafeast_status rafeast_shifted_solve(rafeast_plan_t P, int32_t nz, const double*
   if (e != hipSuccess) {
     s = hip_fail(P, e, "shifted_solve setup");
   } else {
-    if (P->engine == RAFEAST_ENGINE_MULTISHIFT) {
+    if (P->engine == RAFEAST_ENGINE_DIRECT) {
+      // factorize the requested shifts into a band workspace of this call
+      const int n = (int)P->n, b = P->band_b;
+      cpx<double>* Wb = nullptr;
+      int* d_info = nullptr;
+      e = hipMalloc(&Wb, (size_t)nz * n * (b + 1) * sizeof(cpx<double>));
+      if (e == hipSuccess) e = hipMalloc(&d_info, nz * sizeof(int));
+      if (e != hipSuccess) s = hip_fail(P, e, "shifted_solve band workspace");
+      if (s == RAFEAST_OK) {
+        e = band_assemble(P->st, n, b, P->d_srow, P->d_scol, P->d_sv64, nz, d_z, Wb);
+        if (e == hipSuccess) e = band_factor(P->st, n, b, nz, Wb, d_info);
+        std::vector<int> info(nz);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(info.data(), d_info, nz * sizeof(int), hipMemcpyDeviceToHost, P->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->st);
+        if (e != hipSuccess) s = hip_fail(P, e, "shifted_solve factorization");
+        for (int j = 0; s == RAFEAST_OK && j < nz; ++j)
+          if (info[j] != 0)
+            s = fail(P, RAFEAST_BREAKDOWN,
+                     "LDL^T of z_" + std::to_string(j) + " I - A: pivot " +
+                         std::to_string(info[j] - 1) + " vanished");
+      }
+      if (s == RAFEAST_OK) {
+        e = hipMemsetAsync(d_it, 0, nitems * sizeof(int), P->st);
+        if (e == hipSuccess)
+          e = band_solve(P->st, n, b, nz, Wb, P->d_sperm, B, ldb, k,
+                         static_cast<cpx<double>*>(X), (int64_t)nz * k);
+        if (e == hipSuccess)
+          e = band_resid(P->st, n, P->d_rowptr, P->d_col, P->d_val, nz, d_z, B, ldb, k,
+                         static_cast<const cpx<double>*>(X), (int64_t)nz * k, d_rs);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->st);
+        if (e != hipSuccess) s = hip_fail(P, e, "shifted_solve");
+      }
+      if (Wb) (void)hipFree(Wb);
+      if (d_info) (void)hipFree(d_info);
+    } else if (P->engine == RAFEAST_ENGINE_MULTISHIFT) {
       std::vector<void*> bufs;
       MsWork W;
       // pi_k = R_k(z_j - s) can vanish for a real z_j inside the seed's
@@ -2506,11 +2618,16 @@ rafeast_status rafeast_plan_batch(int32_t count, const rafeast_csr* A, const raf
   if (!out) return batch_fail(nullptr, RAFEAST_INVALID_ARG, "null output");
   *out = nullptr;
   if (count < 1 || !A || !prm) return batch_fail(nullptr, RAFEAST_INVALID_ARG, "need count >= 1 and arrays");
-  for (int g = 0; g < count; ++g)
+  for (int g = 0; g < count; ++g) {
     if (prm[g].precond != RAFEAST_PC_NONE)
       return batch_fail(nullptr, RAFEAST_UNSUPPORTED,
                         "the batching form runs unpreconditioned COCG (member " +
                             std::to_string(g) + " asks for precond LEARNED)");
+    if (prm[g].engine == RAFEAST_ENGINE_DIRECT)
+      return batch_fail(nullptr, RAFEAST_UNSUPPORTED,
+                        "the batching form runs COCG (member " + std::to_string(g) +
+                            " asks for the direct engine)");
+  }
   for (int g = 1; g < count; ++g)
     if (prm[g].precision != prm[0].precision || prm[g].tol_solve != prm[0].tol_solve ||
         prm[g].max_cocg != prm[0].max_cocg)

@@ -29,7 +29,7 @@ RESULT_STATUSES = {0, 6, 7, 8, 9}
 PRECISION = {"fp64": 0, "fp32": 1}
 WS_OP = {"auto": 0, "literal": 1, "flip": 2, "fold": 3, "none": 4}
 RHS_FORM = {"residual": 0, "literal": 1}
-ENGINE = {"auto": 0, "resident": 1, "stream": 2, "multishift": 3}
+ENGINE = {"auto": 0, "resident": 1, "stream": 2, "multishift": 3, "direct": 4}
 PRECOND = {"none": 0, "learned": 1}
 NPHASE = 5
 PHASES = ("rr", "solve", "combine", "orth", "total")

@@ -270,3 +270,32 @@ def test_gemm_arguments_checked_before_the_device(native):
     assert L.rafeast_gemm(None, 0, 0, -1, 4, 4, p, 4, p, 4, p, 4, 1.0, 0.0) == 1
     assert L.rafeast_gemm(None, 1, 1, 8, 4, 4, p, 4, p, 4, p, 4, 1.0, 0.0) == 1
     assert "rafeast_gemm" in L.rafeast_last_error(None).decode()
+
+
+def test_direct_engine_validated_before_the_device(native):
+    # the direct engine: FP64 only, CSR plans only, no preconditioner, not in
+    # the batching form; all refused before any device call
+    L = native.lib()
+    csr = grid_laplacian((6, 6), 0.01)
+    A, keep = native._csr_struct(csr)
+    h = C.c_void_p()
+    p32 = native._params(0.0, 0.5, 8, 4, 1, -1, 1e-10, 1e-6, 20, 20000, "fp32", "auto",
+                         "residual", "direct", 0, None)
+    assert L.rafeast_plan(C.byref(A), C.byref(p32), C.byref(h)) == 1
+    assert b"direct engine runs in FP64" in L.rafeast_last_error(None)
+    p64 = native._params(0.0, 0.5, 8, 4, 1, -1, 1e-10, 1e-6, 20, 20000, "fp64", "auto",
+                         "residual", "direct", 0, None)
+    p64.precond = native.PRECOND["learned"]
+    assert native.STATUS[L.rafeast_plan(C.byref(A), C.byref(p64), C.byref(h))] == "UNSUPPORTED"
+    p64.precond = native.PRECOND["none"]
+    p64.m0 = 2
+    K = np.eye(4) * 2.0
+    assert native.STATUS[L.rafeast_plan_dense(4, K.ctypes.data_as(C.POINTER(C.c_double)), 4,
+                                              C.byref(p64), C.byref(h))] == "UNSUPPORTED"
+    p64.m0 = 8
+    As = (native.Csr * 1)(A)
+    assert native.STATUS[L.rafeast_plan_batch(1, As, (native.Params * 1)(p64),
+                                              C.byref(h))] == "UNSUPPORTED"
+    assert b"direct" in L.rafeast_batch_last_error(None)
+    p64.engine = 5
+    assert L.rafeast_plan(C.byref(A), C.byref(p64), C.byref(h)) == 1
