@@ -51,9 +51,11 @@ __device__ __forceinline__ zc cinv(zc a) {
 __device__ __forceinline__ bool cfinite(zc a) { return isfinite(a.re) && isfinite(a.im); }
 
 constexpr int kFactorThreads = 512;
+constexpr size_t kBandSolveRingBytes = 128 * 1024;  // LDS ring of the solve
 constexpr int kSolveThreads = 256;
 constexpr int kSolveRows = 32;  // rows per solve block
 constexpr int kSolveCols = 2;   // right-hand sides per workgroup
+constexpr int kSolveSlices = kSolveThreads / kSolveRows;  // threads per block row
 
 // W_j: every entry zero, then z_j on the diagonal and -A(r, c) at (r, r - c)
 // for the lower entries c <= r of the reordered CSR.  Thread per row.
@@ -189,23 +191,28 @@ __global__ __launch_bounds__(kFactorThreads) void k_band_factor(int n, int b, in
 // X[:, j k + c] = M_j^{-1} B[:, c] for the columns of group blockIdx.x and
 // shift blockIdx.y, with the factors of W_j.  Rows of A in the engine order
 // r map to caller rows perm[r]; B (n x k, ldb) and X (n x (nz k) complex,
-// ldx) are in caller order.  The solve runs in place in X.  Per block of 32
-// rows: the multipliers inside the block (its strict lower triangle) and the
-// pivots are staged in LDS, so the 31 sequential steps of the in-block solve
-// wait on LDS, not on L2.
+// ldx) are in caller order.  The solve runs in place in X.
+// LDS: a ring of the last ring_rows solved rows of the group's columns
+// (ring_rows a power of two >= b + 32), so the band terms read solved values
+// from LDS; per block the strict lower triangle and the pivots.  Band terms:
+// eight threads per block row, the row's band streamed in order by each
+// (forward), or consecutive rows of the block on consecutive threads, which
+// makes each row's band entries contiguous across the threads (backward, L^T
+// read by columns).
 __global__ __launch_bounds__(kSolveThreads) void k_band_solve(int n, int b, const zc* __restrict__ Wall,
                                                               size_t stride,
                                                               const int* __restrict__ perm,
                                                               const double* __restrict__ B, int ldb,
                                                               int k, zc* __restrict__ X,
-                                                              int64_t ldx) {
+                                                              int64_t ldx, int ring_rows) {
+  extern __shared__ zc ring[];  // [ring_rows][kSolveCols]
   __shared__ zc yb[kSolveRows][kSolveCols];
   __shared__ zc tri[kSolveRows][kSolveRows + 1];  // tri[r][q] = L(r0 + r, r0 + q), q < r
   __shared__ zc piv[kSolveRows];
-  __shared__ zc part[kSolveThreads];
+  __shared__ zc part[kSolveSlices][kSolveRows][kSolveCols];
   const int j = blockIdx.y, g = blockIdx.x;
   const zc* __restrict__ W = Wall + (size_t)j * stride;
-  const int ldw = b + 1;
+  const int ldw = b + 1, mask = ring_rows - 1;
   const int c0g = g * kSolveCols, ncol = min(kSolveCols, k - c0g);
   const int tid = threadIdx.x;
   auto xat = [&](int r, int cc) -> zc& {
@@ -226,72 +233,94 @@ __global__ __launch_bounds__(kSolveThreads) void k_band_solve(int n, int b, cons
     xat(r, cc) = zc{B[(size_t)perm[r] * ldb + c0g + cc], 0.0};
   }
   __syncthreads();
-  // kTPP threads per (row of the block, column) pair split the band's terms;
-  // their sums meet in LDS
-  constexpr int kTPP = kSolveThreads / (kSolveRows * kSolveCols);
-  const int pr = tid / (kTPP * kSolveCols), pc = (tid / kTPP) % kSolveCols, ph = tid % kTPP;
-  const bool lead = ph == 0 && pc < ncol;
+  const int rr = tid % kSolveRows, h = tid / kSolveRows;  // block row, slice
+  const bool lead = tid < kSolveRows * kSolveCols;        // one thread per (row, column)
+  const int lr = tid / kSolveCols, lc = tid % kSolveCols;
 
   // forward: L y = b
   for (int r0 = 0; r0 < n; r0 += kSolveRows) {
     const int nr = min(kSolveRows, n - r0);
     stage(r0, nr);
-    zc s{0.0, 0.0};
-    const int r = r0 + pr;
-    if (pr < nr && pc < ncol) {
+    zc s[kSolveCols];
+#pragma unroll
+    for (int cc = 0; cc < kSolveCols; ++cc) s[cc] = zc{0.0, 0.0};
+    if (rr < nr) {
+      const int r = r0 + rr;
+      const zc* __restrict__ wrow = W + (size_t)r * ldw;
 #pragma unroll 4
-      for (int q = max(0, r - b) + ph; q < r0; q += kTPP) {
-        const zc l = W[(size_t)r * ldw + (r - q)];
-        const zc y = xat(q, pc);
-        s.re += l.re * y.re - l.im * y.im;
-        s.im += l.re * y.im + l.im * y.re;
+      for (int q = r0 - 1 - h; q >= max(0, r - b); q -= kSolveSlices) {
+        const zc l = wrow[r - q];
+#pragma unroll
+        for (int cc = 0; cc < kSolveCols; ++cc) {
+          const zc y = ring[(q & mask) * kSolveCols + cc];
+          s[cc].re += l.re * y.re - l.im * y.im;
+          s[cc].im += l.re * y.im + l.im * y.re;
+        }
       }
     }
-    part[tid] = s;
+#pragma unroll
+    for (int cc = 0; cc < kSolveCols; ++cc) part[h][rr][cc] = s[cc];
     __syncthreads();
-    if (lead && pr < nr) {
-      zc t = xat(r, pc);
-      for (int h = 0; h < kTPP; ++h) t = csub(t, part[tid + h]);
-      yb[pr][pc] = t;
+    if (lead && lr < nr && lc < ncol) {
+      zc t = xat(r0 + lr, lc);
+      for (int q = 0; q < kSolveSlices; ++q) t = csub(t, part[q][lr][lc]);
+      yb[lr][lc] = t;
     }
     __syncthreads();
     for (int kk = 0; kk < nr - 1; ++kk) {
       // rows below kk within the block take its contribution
-      if (lead && pr > kk && pr < nr) yb[pr][pc] = csub(yb[pr][pc], cmul(tri[pr][kk], yb[kk][pc]));
+      if (lead && lr > kk && lr < nr && lc < ncol)
+        yb[lr][lc] = csub(yb[lr][lc], cmul(tri[lr][kk], yb[kk][lc]));
       __syncthreads();
     }
-    if (lead && pr < nr) xat(r, pc) = yb[pr][pc];
+    if (lead && lr < nr) {
+      const zc v = lc < ncol ? yb[lr][lc] : zc{0.0, 0.0};
+      ring[((r0 + lr) & mask) * kSolveCols + lc] = v;
+      if (lc < ncol) xat(r0 + lr, lc) = v;
+    }
     __syncthreads();
   }
-  // backward: L^T x = D^{-1} y, blocks from the last
+  // backward: L^T x = D^{-1} y, blocks from the last; the ring now takes the
+  // solved x of the rows after the block
   for (int r1 = n; r1 > 0; r1 -= kSolveRows) {
     const int r0 = max(0, r1 - kSolveRows), nr = r1 - r0;
     stage(r0, nr);
-    zc s{0.0, 0.0};
-    const int r = r0 + pr;
-    if (pr < nr && pc < ncol) {
+    zc s[kSolveCols];
+#pragma unroll
+    for (int cc = 0; cc < kSolveCols; ++cc) s[cc] = zc{0.0, 0.0};
+    if (rr < nr) {
+      const int r = r0 + rr;
       const int hi = min(n - 1, r + b);
 #pragma unroll 4
-      for (int i = r1 + ph; i <= hi; i += kTPP) {
+      for (int i = r1 + h; i <= hi; i += kSolveSlices) {
         const zc l = W[(size_t)i * ldw + (i - r)];
-        const zc x = xat(i, pc);
-        s.re += l.re * x.re - l.im * x.im;
-        s.im += l.re * x.im + l.im * x.re;
+#pragma unroll
+        for (int cc = 0; cc < kSolveCols; ++cc) {
+          const zc x = ring[(i & mask) * kSolveCols + cc];
+          s[cc].re += l.re * x.re - l.im * x.im;
+          s[cc].im += l.re * x.im + l.im * x.re;
+        }
       }
     }
-    part[tid] = s;
+#pragma unroll
+    for (int cc = 0; cc < kSolveCols; ++cc) part[h][rr][cc] = s[cc];
     __syncthreads();
-    if (lead && pr < nr) {
-      zc t = cmul(xat(r, pc), cinv(piv[pr]));
-      for (int h = 0; h < kTPP; ++h) t = csub(t, part[tid + h]);
-      yb[pr][pc] = t;
+    if (lead && lr < nr && lc < ncol) {
+      zc t = cmul(xat(r0 + lr, lc), cinv(piv[lr]));
+      for (int q = 0; q < kSolveSlices; ++q) t = csub(t, part[q][lr][lc]);
+      yb[lr][lc] = t;
     }
     __syncthreads();
     for (int kk = nr - 1; kk > 0; --kk) {
-      if (lead && pr < kk) yb[pr][pc] = csub(yb[pr][pc], cmul(tri[kk][pr], yb[kk][pc]));
+      if (lead && lr < kk && lc < ncol)
+        yb[lr][lc] = csub(yb[lr][lc], cmul(tri[kk][lr], yb[kk][lc]));
       __syncthreads();
     }
-    if (lead && pr < nr) xat(r, pc) = yb[pr][pc];
+    if (lead && lr < nr) {
+      const zc v = lc < ncol ? yb[lr][lc] : zc{0.0, 0.0};
+      ring[((r0 + lr) & mask) * kSolveCols + lc] = v;
+      if (lc < ncol) xat(r0 + lr, lc) = v;
+    }
     __syncthreads();
   }
 }
@@ -352,6 +381,17 @@ size_t band_lds_bytes(int b) {
   return (size_t)(b + nb) * (nb + 1) * sizeof(zc) + nb * sizeof(zc);
 }
 
+int band_solve_ring_rows(int b) {
+  int rows = kSolveRows;
+  while (rows < b + kSolveRows) rows *= 2;
+  return rows;
+}
+
+bool band_supported(int b) {
+  return band_lds_bytes(b) <= 160 * 1024 &&
+         (size_t)band_solve_ring_rows(b) * kSolveCols * sizeof(zc) <= kBandSolveRingBytes;
+}
+
 hipError_t band_assemble(hipStream_t st, int n, int b, const int* rowptr, const int* col,
                          const double* val, int nz, const double* z, cpx<double>* W) {
   if (n <= 0 || nz <= 0) return hipSuccess;
@@ -376,9 +416,15 @@ hipError_t band_factor(hipStream_t st, int n, int b, int nz, cpx<double>* W, int
 hipError_t band_solve(hipStream_t st, int n, int b, int nz, const cpx<double>* W, const int* perm,
                       const double* B, int ldb, int k, cpx<double>* X, int64_t ldx) {
   if (n <= 0 || nz <= 0 || k <= 0) return hipSuccess;
+  const int ring = band_solve_ring_rows(b);
+  const size_t lds = (size_t)ring * kSolveCols * sizeof(zc);
+  if (lds > kBandSolveRingBytes) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void*)k_band_solve,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   dim3 grid((k + kSolveCols - 1) / kSolveCols, nz);
-  hipLaunchKernelGGL(k_band_solve, grid, dim3(kSolveThreads), 0, st, n, b, W,
-                     (size_t)n * (b + 1), perm, B, ldb, k, X, ldx);
+  hipLaunchKernelGGL(k_band_solve, grid, dim3(kSolveThreads), lds, st, n, b, W,
+                     (size_t)n * (b + 1), perm, B, ldb, k, X, ldx, ring);
   return hipGetLastError();
 }
 

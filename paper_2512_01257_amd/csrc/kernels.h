@@ -231,6 +231,9 @@ hipError_t launch_gemm_f32(hipStream_t st, bool acol, int M, int N, int K, const
 // 0 or 1 + the row of a vanishing pivot.
 int band_panel_width(int b);
 size_t band_lds_bytes(int b);
+int band_solve_ring_rows(int b);
+// whether bandwidth b fits the factorization's panel and the solve's LDS ring
+bool band_supported(int b);
 hipError_t band_assemble(hipStream_t st, int n, int b, const int* rowptr, const int* col,
                          const double* val, int nz, const double* z, cpx<double>* W);
 hipError_t band_factor(hipStream_t st, int n, int b, int nz, cpx<double>* W, int* info);

@@ -1906,11 +1906,11 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
         for (int64_t r = 0; r < n; ++r)
           if (srp[r + 1] > srp[r]) b = std::max<int>(b, (int)r - scl[srp[r]]);
         P->band_b = b;
-        if (band_lds_bytes(b) > 160 * 1024)
+        if (!band_supported(b))
           return bail(fail(P, RAFEAST_UNSUPPORTED,
                            "bandwidth " + std::to_string(b) +
-                               " of the reordered matrix exceeds the direct engine's panel "
-                               "(one column of b + 1 rows in LDS)"));
+                               " of the reordered matrix exceeds the direct engine's LDS "
+                               "(the factorization's panel, the solve's ring of b + 32 rows)"));
         const size_t bytes = (size_t)P->nc * (size_t)n * (size_t)(b + 1) * sizeof(cpx<double>);
         size_t fr = 0, tot = 0;
         PCHK(hipMemGetInfo(&fr, &tot));
