@@ -27,6 +27,9 @@ namespace {
 thread_local std::string g_plan_error;
 
 constexpr int kMaxSmallK = 192;
+#ifndef RAFEAST_SELL_BANK_GROUPS
+#define RAFEAST_SELL_BANK_GROUPS 32  // lanes per LDS cycle of 8-byte gathers
+#endif
 
 // Ritz pairs with a smaller filter gain are spurious (not counted in M).
 constexpr double kSpuriousGain = 0.25;
@@ -1776,8 +1779,53 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     std::vector<float> v32(tot, 0.0f);
     std::vector<uint16_t> o32(tot, 0);
     std::vector<SellEntry64> e64(tot, SellEntry64{0, 0, 0.0});
+    // Order of each row's entries (free: it only changes the rounding of the
+    // row's sum).  At entry position kk the 64 lanes of a slice gather p at
+    // the slots of their kk-th entries in one LDS instruction, which the LDS
+    // serves a group of lanes per cycle (taken as 32 lanes of 8-byte complex
+    // FP32, 16 of 16-byte complex FP64, i.e. 64 banks of 4 bytes); lanes of a
+    // group whose slots fall in the same bank group (slot mod 32, mod 16)
+    // conflict.  Greedy per position:
+    // each lane takes its remaining entry whose bank group its lane group
+    // has used least; padding entries (value zero) point at a slot of the
+    // least used group.
+    const int bgrp = fp32 ? RAFEAST_SELL_BANK_GROUPS : RAFEAST_SELL_BANK_GROUPS / 2;
+    std::vector<int> pick, padslot;
+    auto order_slice = [&](int s, int wd) {
+      pick.assign((size_t)wd * 64, -1);
+      padslot.assign((size_t)wd * 64, 0);
+      std::vector<std::vector<int>> rem(64);
+      for (int l = 0; l < 64; ++l) {
+        const int64_t sl = (int64_t)s * 64 + l;
+        if (sl < n)
+          for (int t = rp[order[sl]]; t < rp[order[sl] + 1]; ++t) rem[l].push_back(t);
+      }
+      std::vector<int> cnt((64 / bgrp) * bgrp);
+      for (int kk = 0; kk < wd; ++kk) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int l = 0; l < 64; ++l) {
+          int* c = cnt.data() + (l / bgrp) * bgrp;
+          if (!rem[l].empty()) {
+            size_t best = 0;
+            for (size_t u = 1; u < rem[l].size(); ++u)
+              if (c[slot_of[cl[rem[l][u]]] % bgrp] < c[slot_of[cl[rem[l][best]]] % bgrp]) best = u;
+            const int t = rem[l][best];
+            rem[l].erase(rem[l].begin() + best);
+            pick[(size_t)kk * 64 + l] = t;
+            ++c[slot_of[cl[t]] % bgrp];
+          } else {
+            int r = 0;
+            for (int q = 1; q < bgrp; ++q)
+              if (c[q] < c[r]) r = q;
+            padslot[(size_t)kk * 64 + l] = r;
+            ++c[r];
+          }
+        }
+      }
+    };
     for (int s = 0; s < nsl; ++s) {
       const int wd = (sb[s + 1] - sb[s]) / 64;
+      order_slice(s, wd);
       for (int kk = 0; kk < wd; ++kk)
         for (int l = 0; l < 64; ++l) {
           const int64_t sl = (int64_t)s * 64 + l;
@@ -1794,15 +1842,16 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
           } else {
             vi = oi = (size_t)sb[s] + (size_t)n8 * 512 + (size_t)l * 4 + (kk - 8 * n8);
           }
-          if (row >= 0 && kk < rp[row + 1] - rp[row]) {
-            const int t = rp[row] + kk;
+          const int t = pick[(size_t)kk * 64 + l];
+          if (row >= 0 && t >= 0) {
             v32[vi] = (float)A->values[t];
             o32[oi] = (uint16_t)(slot_of[cl[t]] * 8);
             e64[e] = SellEntry64{slot_of[cl[t]] * 16, 0, A->values[t]};
           } else {
-            // padding: own slot, zero value
-            o32[oi] = (uint16_t)(sl * 8);
-            e64[e] = SellEntry64{(int)sl * 16, 0, 0.0};
+            // padding: zero value at a slot of the least used bank group
+            const int ps = padslot[(size_t)kk * 64 + l];
+            o32[oi] = (uint16_t)(ps * 8);
+            e64[e] = SellEntry64{ps * 16, 0, 0.0};
           }
         }
     }
