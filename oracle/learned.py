@@ -97,14 +97,46 @@ def gelu_grad(x):
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2 * math.pi)
 
 
-def mlp_forward(params, X, norm=None):
+def bf16_round(x):
+    """x rounded to bfloat16 (the upper 16 bits of an IEEE binary32, round to
+    nearest, ties to even), returned as float32 values."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def _layer_fp32(W, b, H):
+    """b + W h per row of H in float32, the inputs summed in index order (a
+    product of two bfloat16 values is exact in float32)."""
+    W = np.asarray(W, dtype=np.float32)
+    Z = np.repeat(np.asarray(b, dtype=np.float32)[None, :], H.shape[0], axis=0)
+    for i in range(W.shape[1]):
+        Z = (Z + H[:, i:i + 1] * W[:, i][None, :]).astype(np.float32)
+    return Z
+
+
+def mlp_forward(params, X, norm=None, bf16=False):
     """Outputs Y (N x 16) of features X (N x 4); params = [(W, b)] with W
     (out x in); norm = (mu, sd): the network sees (X - mu) / sd (None: X).
-    Returns (Y, cache) with the pre-activations for backward."""
+    bf16: the reduced-precision network (weights, biases and every layer's
+    input rounded to bfloat16, sums and GELU in float32), else float64
+    throughout.  Returns (Y, cache) with the pre-activations for backward."""
     H = np.asarray(X, dtype=np.float64)
     if norm is not None:
         H = (H - np.asarray(norm[0], dtype=np.float64)) / np.asarray(norm[1], dtype=np.float64)
     cache = []
+    if bf16:
+        H = bf16_round(H)
+        for l, (W, b) in enumerate(params):
+            Zp = _layer_fp32(bf16_round(W), bf16_round(b), H)
+            cache.append((H.astype(np.float64), Zp.astype(np.float64)))
+            if l < len(params) - 1:
+                g = (np.float32(0.5) * Zp *
+                     (np.float32(1.0) + erf(Zp * np.float32(0.70710678118654752))).astype(np.float32))
+                H = bf16_round(g)
+            else:
+                H = Zp
+        return H.astype(np.float64), cache
     for l, (W, b) in enumerate(params):
         Zp = H @ np.asarray(W, dtype=np.float64).T + np.asarray(b, dtype=np.float64)
         cache.append((H, Zp))
@@ -112,15 +144,16 @@ def mlp_forward(params, X, norm=None):
     return H, cache
 
 
-def mlp_backward(params, cache, dY):
-    """Gradients [(dW, db)] of sum(dY * Y) with respect to every layer."""
+def mlp_backward(params, cache, dY, bf16=False):
+    """Gradients [(dW, db)] of sum(dY * Y) with respect to every layer (with
+    the bfloat16 weights when bf16, the cache then from the bf16 forward)."""
     grads = [None] * len(params)
     D = np.asarray(dY, dtype=np.float64)
     for l in range(len(params) - 1, -1, -1):
         H, Zp = cache[l]
         if l < len(params) - 1:
             D = D * gelu_grad(Zp)
-        W = np.asarray(params[l][0], dtype=np.float64)
+        W = np.asarray(bf16_round(params[l][0]) if bf16 else params[l][0], dtype=np.float64)
         grads[l] = (D.T @ H, D.sum(axis=0))
         D = D @ W
     return grads
@@ -135,17 +168,17 @@ def coeffs(Y, X):
     return (Y[:, 0::2] + 1j * Y[:, 1::2]) / X[:, 1:2]
 
 
-def batch_loss(params, X, G, h, rr, norm=None):
+def batch_loss(params, X, G, h, rr, norm=None, bf16=False):
     """Mean loss over samples: X (N x 4), G (N x 8 x 8), h (N x 8), rr (N)."""
-    C = coeffs(mlp_forward(params, X, norm)[0], X)
+    C = coeffs(mlp_forward(params, X, norm, bf16)[0], X)
     return float(np.mean([quad_loss(C[s], G[s], h[s], rr[s]) for s in range(len(rr))]))
 
 
-def batch_grad(params, X, G, h, rr, norm=None):
+def batch_grad(params, X, G, h, rr, norm=None, bf16=False):
     """Gradients of batch_loss: dL/dRe c = 2 Re(Gc - h)/rr, dL/dIm c =
     2 Im(Gc - h)/rr per sample, times dc/dy = 1 / Im z^, averaged, then back
     through the network."""
-    Y, cache = mlp_forward(params, X, norm)
+    Y, cache = mlp_forward(params, X, norm, bf16)
     C = coeffs(Y, X)
     N = len(rr)
     dY = np.zeros_like(Y)
@@ -153,7 +186,7 @@ def batch_grad(params, X, G, h, rr, norm=None):
         g = 2.0 * (G[s] @ C[s] - h[s]) / rr[s] / float(X[s][1])
         dY[s, 0::2] = g.real / N
         dY[s, 1::2] = g.imag / N
-    return mlp_backward(params, cache, dY)
+    return mlp_backward(params, cache, dY, bf16)
 
 
 # -------------------------------------------------- preconditioned solve ---

@@ -92,18 +92,26 @@ def test_network_forward_and_gradient_bf16(gpu_lib, torch_dev):
     ref_sd[ref_sd <= 1e-9 * np.maximum(1.0, np.abs(host[0].mean(axis=0)))] = 1.0
     np.testing.assert_allclose(sd, ref_sd, rtol=1e-6)
     norm = (mu, sd)
-    Yr = Lr.mlp_forward(P64, host[0], norm)[0]
-    assert np.linalg.norm(Y - Yr) <= 2e-2 * np.linalg.norm(Yr)
-    ref = Lr.batch_grad(P64, *host, norm=norm)
+    # against the oracle's bfloat16 network (weights, biases and layer inputs
+    # rounded to nearest even, FP32 sums): what remains is FP32 summation
+    # order, the GELU's erf implementations and the rare bfloat16 rounding
+    # they flip, so the bound is 1e-3 rather than the 2e-2 that bfloat16
+    # rounding itself would need against the FP64 network
+    Yr = Lr.mlp_forward(P64, host[0], norm, bf16=True)[0]
+    assert np.linalg.norm(Y - Yr) <= 1e-3 * np.linalg.norm(Yr)
+    Y64 = Lr.mlp_forward(P64, host[0], norm)[0]
+    assert np.linalg.norm(Y - Y64) <= 2e-2 * np.linalg.norm(Y64)
+    ref = Lr.batch_grad(P64, *host, norm=norm, bf16=True)
     gr = np.concatenate([np.concatenate([dw.ravel(), db]) for dw, db in ref])
     gg = g.cpu().numpy().astype(np.float64)
     assert np.all(gg[len(gr):] == 0.0)  # the standardization is not trained
     gg = gg[: len(gr)]
-    assert np.linalg.norm(gg - gr) <= 2e-2 * np.linalg.norm(gr)
-    for l, (dw, db) in enumerate(unflatten(gg)):  # layer by layer too
-        assert np.linalg.norm(dw - ref[l][0]) <= 5e-2 * np.linalg.norm(ref[l][0]), l
-    lr = Lr.batch_loss(P64, *host, norm=norm)
-    assert abs(loss - lr) <= 2e-2 * abs(lr)
+    assert np.linalg.norm(gg - gr) <= 1e-3 * np.linalg.norm(gr)
+    for l, (dw, db) in enumerate(unflatten(gg)):  # layer by layer, weights and biases
+        assert np.linalg.norm(dw - ref[l][0]) <= 2e-3 * np.linalg.norm(ref[l][0]), l
+        assert np.linalg.norm(db - ref[l][1]) <= 2e-3 * np.linalg.norm(ref[l][1]), l
+    lr = Lr.batch_loss(P64, *host, norm=norm, bf16=True)
+    assert abs(loss - lr) <= 1e-3 * abs(lr)
 
 
 def test_training_lowers_the_loss(gpu_lib, torch_dev):

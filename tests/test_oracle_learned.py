@@ -150,3 +150,36 @@ def test_preconditioned_cocg_against_direct_solve():
         assert r <= 1e-10
         assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 1.1 * kappa * 1e-10
     assert it1 < it0  # the fitted polynomial cuts the iteration count
+
+
+def test_bf16_round_is_nearest_even():
+    # hand cases: ties go to the even neighbour, 1 + 2^-7 is the next value
+    # above 1, 65504 rounds up to 65536
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -1 - 2.0 ** -8, 65504.0,
+                  1 + 2.0 ** -7 + 2.0 ** -9])
+    want = np.array([1.0, 1.0, 1 + 2.0 ** -6, -1.0, 65536.0, 1 + 2.0 ** -7])
+    np.testing.assert_array_equal(Lr.bf16_round(x).astype(np.float64), want)
+    # against torch's own bfloat16 conversion (an independent implementation)
+    import torch
+
+    r = np.random.default_rng(3).standard_normal(20000).astype(np.float32) * 10.0 ** np.arange(
+        -10, 10).repeat(1000).astype(np.float32)
+    ref = torch.from_numpy(r).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(Lr.bf16_round(r), ref)
+
+
+def test_bf16_network_stays_near_the_fp64_one():
+    # the reduced-precision network differs from the FP64 one by bfloat16
+    # rounding (8 significant bits), not by more
+    params = init_weights(4)
+    X = np.random.default_rng(8).standard_normal((40, 4))
+    norm = (X.mean(axis=0), X.std(axis=0))
+    Y64 = Lr.mlp_forward(params, X, norm)[0]
+    Y16 = Lr.mlp_forward(params, X, norm, bf16=True)[0]
+    rel = np.linalg.norm(Y16 - Y64) / np.linalg.norm(Y64)
+    assert 1e-5 < rel < 3e-2
+    # identity weights through one layer: bf16 rounding of the input only
+    P1 = [(np.eye(4, dtype=np.float32), np.zeros(4, dtype=np.float32))]
+    x = np.array([[1 + 3 * 2.0 ** -8, 2.0, -0.5, 1 + 2.0 ** -9]])
+    np.testing.assert_array_equal(Lr.mlp_forward(P1, x, bf16=True)[0],
+                                  Lr.bf16_round(x).astype(np.float64))
