@@ -297,7 +297,15 @@ def main_batch(args):
     # the same problems one after another
     seq = None
     if args.plain_steps != 0:
-        plans = [native.Plan(p["csr"], p["lmin"], p["lmax"], p["m0"], **kw) for p in probs]
+        # each problem on the engine the batch gives it (members the resident
+        # engine cannot hold: the multi-shift engine in FP64)
+        def member_plan(p):
+            if p["csr"].n > 8192:
+                return native.Plan(p["csr"], p["lmin"], p["lmax"], p["m0"],
+                                   **dict(kw, precision="fp64", engine="multishift"))
+            return native.Plan(p["csr"], p["lmin"], p["lmax"], p["m0"], **kw)
+
+        plans = [member_plan(p) for p in probs]
         for pl in plans:  # warm up
             pl.warmstart()
             pl.solve(want_vectors=False)

@@ -421,8 +421,9 @@ rafeast_status rafeast_gaussian(rafeast_plan_t plan, int32_t w, uint64_t seed, d
  * systems of every member that fits on chip (the resident engine) are solved
  * in one persistent launch, replayed from a captured HIP graph: its work
  * items are (member, node, column) triples, longest first across members.
- * Members too large for the resident engine use the streaming engine after
- * that launch, concurrently with each other.  The Rayleigh-Ritz,
+ * Members too large for the resident engine whose engine is AUTO run the
+ * multi-shift engine in FP64 (others the engine they name), after that
+ * launch, concurrently with each other.  The Rayleigh-Ritz,
  * combination and CholQR2 steps run per member.  Each member computes
  * exactly what rafeast_solve computes for it.
  * ------------------------------------------------------------------------- */
@@ -431,8 +432,8 @@ rafeast_status rafeast_gaussian(rafeast_plan_t plan, int32_t w, uint64_t seed, d
  * members must share precision, tol_solve and max_cocg (INVALID_ARG
  * otherwise).  prm[0].hip_stream (or a stream the batch creates) carries the
  * shared launch; every member gets a stream of its own (owned by the batch;
- * the members' hip_stream fields are ignored), and streaming-engine members
- * solve concurrently from host worker threads.  Errors as rafeast_plan, for the first member
+ * the members' hip_stream fields are ignored), and the members outside the
+ * shared launch solve concurrently from host worker threads.  Errors as rafeast_plan, for the first member
  * that fails (the text names it). */
 rafeast_status rafeast_plan_batch(int32_t count, const rafeast_csr* A, const rafeast_params* prm,
                                   rafeast_batch_t* out);

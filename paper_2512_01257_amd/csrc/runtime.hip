@@ -2715,6 +2715,14 @@ rafeast_status rafeast_plan_batch(int32_t count, const rafeast_csr* A, const raf
   for (int g = 0; g < count; ++g) {
     rafeast_params q = prm[g];
     q.hip_stream = B->mst[g];
+    // members left to the library's choice that the shared resident launch
+    // cannot hold run the multi-shift engine (FP64; it needs nothing from
+    // the shared launch and takes one real SpMV of m0 columns per iteration)
+    if (q.engine == RAFEAST_ENGINE_AUTO && A[g].n > cocg_resident_max_n(B->fp32) &&
+        q.m0 <= 192) {
+      q.engine = RAFEAST_ENGINE_MULTISHIFT;
+      q.precision = RAFEAST_FP64;
+    }
     rafeast_plan_t P = nullptr;
     const rafeast_status st = rafeast_plan(&A[g], &q, &P);
     if (st != RAFEAST_OK) {

@@ -66,8 +66,10 @@ def test_batch_parity(gpu_lib, precision, relaxed):
     for pr, r in zip(probs, rel):
         pr["tol_solve_relaxed"] = r
     with gpu_lib.Batch(probs, nc=4, q=2, p=10, precision=precision) as B:
-        assert B.resident_count == len(members) - 1  # the 100 x 100 grid streams
-        assert [m.engine for m in B.members] == ["resident", "stream"] + ["resident"] * 4
+        assert B.resident_count == len(members) - 1
+        # the 100 x 100 grid is too large for the shared launch: multi-shift, FP64
+        engines = [m.engine for m in B.members]
+        assert engines == ["resident", "multishift"] + ["resident"] * 4
         for g, m in enumerate(B.members):
             m.warmstart(omega=gaussian(m.n, m.w, g))
         outs, t_ms, status = B.solve()
@@ -87,8 +89,10 @@ def test_batch_parity(gpu_lib, precision, relaxed):
     # each member alone, on the eager single-plan path: same iteration counts,
     # same eigenvalues
     for g, (m, out) in enumerate(zip(members, outs)):
+        ms = engines[g] == "multishift"
         with gpu_lib.Plan(m["csr"], m["lmin"], m["lmax"], m["m0"], nc=4, q=2, p=10,
-                          precision=precision, tol_solve_relaxed=rel[g]) as plan:
+                          precision="fp64" if ms else precision, tol_solve_relaxed=rel[g],
+                          engine="multishift" if ms else "auto") as plan:
             plan.warmstart(omega=gaussian(plan.n, plan.w, g))
             alone = plan.solve()
         s_win = max(abs(m["lmin"]), abs(m["lmax"]))
