@@ -17,17 +17,22 @@
 // in W[r][d], d = 0..b (d = 0 the diagonal).  After the factorization
 // W[r][0] = D(r) and W[r][d] = L(r, r - d).
 //
-// Factorization: one workgroup per shift, panels of nb columns.  The panel's
-// rows (its nb rows and the b rows below that the band reaches) are staged in
-// LDS, factorized there column by column (the multipliers l = m / d and their
-// rank-one updates within the panel), written back, and the Schur complement
-// of the b x b window below the panel is updated in 4 x 4 register tiles:
-// W(i, j) -= sum_k l_ik d_k l_jk.  Solves: one workgroup per (shift, group of
+// Factorization: panels of nb = 32 columns, all shifts together, two
+// launches per panel.  One workgroup per shift factorizes the panel's
+// diagonal block in LDS and gives every row below it that the band reaches
+// its multipliers (a product with the block's inverse triangle); the Schur
+// complement of the b x b
+// window below the panel, W(i, j) -= sum_k l_ik d_k l_jk, is spread over
+// many workgroups per shift in 64 x 64 blocks of 4 x 4 register tiles, so a
+// factorization's time grows with the number of shifts, not only with one
+// CU's rate.  Solves: one workgroup per (shift, group of
 // right-hand sides); blocks of 32 rows, each first reduced by the solved rows
 // within the band, then solved within the block in LDS; forward with L, then
 // D, then backward with L^T.
 #include "device.h"
 #include "kernels.h"
+
+#include <algorithm>
 
 namespace rafeast {
 
@@ -50,7 +55,9 @@ __device__ __forceinline__ zc cinv(zc a) {
 }
 __device__ __forceinline__ bool cfinite(zc a) { return isfinite(a.re) && isfinite(a.im); }
 
-constexpr int kFactorThreads = 512;
+constexpr int kPanelThreads = 256;
+constexpr int kPanelRows = kPanelThreads / 2;  // rows per staged chunk (two threads each)
+constexpr int kBandMaxPanel = 32;  // panel width
 constexpr size_t kBandSolveRingBytes = 128 * 1024;  // LDS ring of the solve
 constexpr int kSolveThreads = 256;
 constexpr int kSolveRows = 32;  // rows per solve block
@@ -77,115 +84,201 @@ __global__ __launch_bounds__(256) void k_band_assemble(int n, int b, const int* 
   }
 }
 
-// In-place band LDL^T of W_j (workgroup j).  info[j] = 0 on success, else
-// 1 + the row whose pivot was zero or not finite (the factorization stops
-// there).  LDS: the panel, (b + nb) rows of nb + 1 entries, then nb pivots.
-__global__ __launch_bounds__(kFactorThreads) void k_band_factor(int n, int b, int nb,
-                                                                zc* __restrict__ Wall,
-                                                                size_t stride,
-                                                                int* __restrict__ info) {
-  extern __shared__ zc P[];
-  const int j = blockIdx.x;
-  zc* __restrict__ W = Wall + (size_t)j * stride;
-  const int ldw = b + 1, ldp = nb + 1;
-  zc* __restrict__ Dp = P + (size_t)(b + nb) * ldp;
+// Panel c of the band LDL^T of W_j (workgroup j).  The workgroup factorizes
+// the panel's diagonal block (nb x nb, in LDS: multipliers l = m / d and the
+// rank-one updates, column by column, each thread owning fixed entries) and
+// forms the inverse of its unit lower triangle L11 (by elimination on the
+// identity, likewise).  Every row i below the block that the band reaches then
+// takes its multipliers as a product with that inverse:
+//   l_ik = (sum_{q <= k} m_iq (L11^{-1})_kq) / d_k,
+// i.e. L21 = M21 L11^{-T} D^{-1}: chunks of rows staged in LDS, two threads
+// per row with nb / 2 independent sums each.
+// info[j] = 1 + the row of a vanishing or non-finite pivot (that shift's
+// factorization stops there: later panels and updates of it return at once).
+__global__ __launch_bounds__(kPanelThreads) void k_band_panel(int n, int b, int nb, int c,
+                                                              zc* __restrict__ Wall,
+                                                              size_t stride,
+                                                              int* __restrict__ info) {
+  constexpr int L = kBandMaxPanel + 1;
+  __shared__ zc Pd[kBandMaxPanel][L];  // the diagonal block, then its factors
+  __shared__ zc Li[kBandMaxPanel][L];  // Li[k][q] = (L11^{-1})_kq, q <= k
+  __shared__ zc Dinv[kBandMaxPanel];
   __shared__ int bad;
+  const int j = blockIdx.x;
+  if (info[j] != 0) return;
+  zc* __restrict__ W = Wall + (size_t)j * stride;
+  const int ldw = b + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int e = min(c + nb, n), w = e - c, rend = min(n, e + b);
+  for (int idx = tid; idx < kBandMaxPanel * kBandMaxPanel; idx += nt) {
+    const int ii = idx / kBandMaxPanel, kk = idx % kBandMaxPanel;
+    const int i = c + ii, k = c + kk;
+    Pd[ii][kk] = (ii < w && kk <= ii && i - k <= b) ? W[(size_t)i * ldw + (i - k)] : zc{0.0, 0.0};
+  }
   if (tid == 0) bad = 0;
-  for (int c = 0; c < n; c += nb) {
-    const int e = min(c + nb, n), w = e - c, rend = min(n, e + b), rows = rend - c;
-    // stage the panel's rows, panel columns: P[i - c][k - c] = M(i, k)
-    for (int idx = tid; idx < rows * nb; idx += nt) {
-      const int i = c + idx / nb, kk = idx % nb, k = c + kk;
-      zc v{0.0, 0.0};
-      if (kk < w && k <= i && i - k <= b) v = W[(size_t)i * ldw + (i - k)];
-      P[(idx / nb) * ldp + kk] = v;
+  __syncthreads();
+  // the block's pivot steps: every thread owns fixed entries of the 32 x 32
+  // block (entry t + 256 u: row (t + 256 u) / 32, column (t + 256 u) % 32)
+  static_assert(kBandMaxPanel == 32, "entry indices by shifts");
+  constexpr int kOwn = kBandMaxPanel * kBandMaxPanel / kPanelThreads;
+  static_assert(kOwn * kPanelThreads == kBandMaxPanel * kBandMaxPanel, "entry ownership");
+  int fail = 0;
+  for (int kk = 0; kk < w; ++kk) {
+    const zc d = Pd[kk][kk];
+    if (!(cfinite(d) && (d.re != 0.0 || d.im != 0.0))) {
+      fail = c + kk + 1;
+      break;  // uniform: every thread read the same pivot
+    }
+    const zc inv = cinv(d);
+    if (tid == 0) Dinv[kk] = inv;
+    if (tid > kk && tid < w) Pd[tid][kk] = cmul(Pd[tid][kk], inv);  // column kk's multipliers
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kOwn; ++u) {
+      const int en = tid + kPanelThreads * u, ii = en >> 5, jj = en & 31;
+      if (jj > kk && jj <= ii && ii < w)
+        Pd[ii][jj] = csub(Pd[ii][jj], cmul(cmul(Pd[ii][kk], d), Pd[jj][kk]));
     }
     __syncthreads();
-    for (int kk = 0; kk < w; ++kk) {
-      const zc d = P[kk * ldp + kk];
-      const bool ok = cfinite(d) && (d.re != 0.0 || d.im != 0.0);
-      if (!ok) {
-        if (tid == 0) {
-          bad = 1;
-          info[j] = c + kk + 1;
-        }
-      }
-      __syncthreads();
-      if (bad) return;  // uniform: every thread read the flag after the barrier
-      const zc inv = cinv(d);
-      // multipliers of column k for the rows below it
-      for (int ii = kk + 1 + tid; ii < rows; ii += nt) P[ii * ldp + kk] = cmul(P[ii * ldp + kk], inv);
-      if (tid == 0) Dp[kk] = d;
-      __syncthreads();
-      // rank-one update of the panel's remaining columns
-      const int rem = w - kk - 1;
-      if (rem > 0) {
-        const int cnt = (rows - kk - 1) * rem;
-        for (int idx = tid; idx < cnt; idx += nt) {
-          const int ii = kk + 1 + idx / rem, jj = kk + 1 + idx % rem;
-          if (jj > ii) continue;
-          const zc t = cmul(cmul(P[ii * ldp + kk], d), P[jj * ldp + kk]);
-          P[ii * ldp + jj] = csub(P[ii * ldp + jj], t);
-        }
+  }
+  if (fail) {
+    if (tid == 0) {
+      bad = 1;
+      info[j] = fail;
+    }
+  } else {
+    // L11^{-1} by elimination on the identity, column q at a time:
+    // X[i][:q] -= l_iq X[q][:q] for i > q
+#pragma unroll
+    for (int u = 0; u < kOwn; ++u) {
+      const int en = tid + kPanelThreads * u, i = en >> 5, q = en & 31;
+      Li[i][q] = zc{i == q ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    for (int q = 0; q + 1 < w; ++q) {
+#pragma unroll
+      for (int u = 0; u < kOwn; ++u) {
+        const int en = tid + kPanelThreads * u, i = en >> 5, jx = en & 31;
+        if (i > q && i < w && jx <= q) Li[i][jx] = csub(Li[i][jx], cmul(Pd[i][q], Li[q][jx]));
       }
       __syncthreads();
     }
-    // write the panel back: multipliers below the diagonal, pivots on it
-    for (int idx = tid; idx < rows * w; idx += nt) {
-      const int ii = idx / w, kk = idx % w, i = c + ii, k = c + kk;
-      if (k <= i && i - k <= b) W[(size_t)i * ldw + (i - k)] = P[ii * ldp + kk];
+  }
+  __syncthreads();
+  if (bad) return;
+  // the block back to W: multipliers below its diagonal, pivots on it
+  for (int idx = tid; idx < w * w; idx += nt) {
+    const int ii = idx / w, kk = idx % w, i = c + ii, k = c + kk;
+    if (kk <= ii && i - k <= b) W[(size_t)i * ldw + (i - k)] = Pd[ii][kk];
+  }
+  // rows below the block, in chunks of kPanelRows staged in LDS by coalesced
+  // loads; two threads per row, one per half of the nb sums (16 each)
+  extern __shared__ zc Rs[];  // [kPanelRows][L]
+  constexpr int H = kBandMaxPanel / 2;
+  const int rr = tid % kPanelRows, h = tid / kPanelRows;
+  for (int i0 = e; i0 < rend; i0 += kPanelRows) {
+    for (int idx = tid; idx < kPanelRows * kBandMaxPanel; idx += nt) {
+      const int r = idx / kBandMaxPanel, q = idx % kBandMaxPanel, i = i0 + r;
+      Rs[r * L + q] = (i < rend && q < w && i - (c + q) <= b) ? W[(size_t)i * ldw + (i - c - q)]
+                                                              : zc{0.0, 0.0};
     }
-    // Schur complement of the window below the panel, lower triangle, in
-    // 4 x 4 tiles: W(i, jc) -= sum_k l_ik d_k l_jc,k for e <= jc <= i < rend
-    const int m = rend - e;
-    if (m > 0) {
-      const int ntile = (m + 3) / 4;
-      const int count = ntile * (ntile + 1) / 2;
-      const int o = e - c;  // first window row within the panel
-      for (int t = tid; t < count; t += nt) {
-        int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-        while (ti * (ti + 1) / 2 > t) --ti;
-        const int tj = t - ti * (ti + 1) / 2;
-        zc acc[4][4];
+    __syncthreads();
+    const int i = i0 + rr;
+    if (i < rend) {
+      zc acc[H];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+      for (int k = 0; k < H; ++k) acc[k] = zc{0.0, 0.0};
+      const int qend = min(w, H * (h + 1));
+#pragma unroll 1
+      for (int q = 0; q < qend; ++q) {
+        const zc mq = Rs[rr * L + q];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = zc{0.0, 0.0};
-        for (int kk = 0; kk < w; ++kk) {
-          const zc dk = Dp[kk];
-          zc a[4], bv[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int ri = min(o + 4 * ti + u, rows - 1);
-            const int rj = min(o + 4 * tj + u, rows - 1);
-            a[u] = cmul(P[ri * ldp + kk], dk);
-            bv[u] = P[rj * ldp + kk];
+        for (int k = 0; k < H; ++k) {
+          if (H * h + k >= q) {
+            const zc l = Li[H * h + k][q];
+            acc[k].re += mq.re * l.re - mq.im * l.im;
+            acc[k].im += mq.re * l.im + mq.im * l.re;
           }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              acc[u][v].re += a[u].re * bv[v].re - a[u].im * bv[v].im;
-              acc[u][v].im += a[u].re * bv[v].im + a[u].im * bv[v].re;
-            }
         }
+      }
+      zc* __restrict__ row = W + (size_t)i * ldw;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = e + 4 * ti + u, jc = e + 4 * tj + v;
-            if (i < rend && jc <= i) {
-              zc* p = W + (size_t)i * ldw + (i - jc);
-              *p = csub(*p, acc[u][v]);
-            }
-          }
+      for (int k = 0; k < H; ++k) {
+        const int kk = H * h + k;
+        if (kk < w && i - (c + kk) <= b) row[i - c - kk] = cmul(acc[k], Dinv[kk]);
       }
     }
     __syncthreads();
   }
-  if (tid == 0) info[j] = 0;
+}
+
+// Schur complement of the window below panel c of W_j (shift blockIdx.y):
+// W(i, jc) -= sum_{k in panel} l_ik d_k l_jc,k for e <= jc <= i < rend, in
+// 64 x 64 blocks of the window's lower triangle (blockIdx.x enumerates the
+// pairs bi >= bj), each thread a 4 x 4 tile.  The panel's multipliers of the
+// block's rows and columns and the pivots are staged in LDS.
+constexpr int kSchurBlock = 64;
+__global__ __launch_bounds__(256) void k_band_schur(int n, int b, int nb, int c,
+                                                    zc* __restrict__ Wall, size_t stride,
+                                                    const int* __restrict__ info) {
+  __shared__ zc Lr[kSchurBlock][kBandMaxPanel + 1];
+  __shared__ zc Lc[kSchurBlock][kBandMaxPanel + 1];
+  __shared__ zc Dp[kBandMaxPanel];
+  const int j = blockIdx.y;
+  if (info[j] != 0) return;
+  zc* __restrict__ W = Wall + (size_t)j * stride;
+  const int ldw = b + 1;
+  const int e = min(c + nb, n), w = e - c, rend = min(n, e + b), m = rend - e;
+  const int t = blockIdx.x;
+  int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+  while (bi * (bi + 1) / 2 > t) --bi;
+  const int bj = t - bi * (bi + 1) / 2;
+  const int i0 = e + bi * kSchurBlock, j0 = e + bj * kSchurBlock;
+  const int tid = threadIdx.x;
+  // multipliers l(r, k) = W[r][r - k] of the block's rows and columns
+  for (int idx = tid; idx < kSchurBlock * w; idx += 256) {
+    const int r = idx / w, kk = idx % w, k = c + kk;
+    const int ri = i0 + r, rj = j0 + r;
+    Lr[r][kk] = (ri < rend && ri - k <= b) ? W[(size_t)ri * ldw + (ri - k)] : zc{0.0, 0.0};
+    Lc[r][kk] = (rj < rend && rj - k <= b) ? W[(size_t)rj * ldw + (rj - k)] : zc{0.0, 0.0};
+  }
+  if (tid < w) Dp[tid] = W[(size_t)(c + tid) * ldw];
+  __syncthreads();
+  const int ti = tid / 16, tj = tid % 16;
+  if (i0 + 4 * ti >= rend || j0 + 4 * tj > i0 + 4 * ti + 3) return;  // tile outside the triangle
+  zc acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = zc{0.0, 0.0};
+  for (int kk = 0; kk < w; ++kk) {
+    const zc dk = Dp[kk];
+    zc a[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = cmul(Lr[4 * ti + u][kk], dk);
+      bv[u] = Lc[4 * tj + u][kk];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[u][v].re += a[u].re * bv[v].re - a[u].im * bv[v].im;
+        acc[u][v].im += a[u].re * bv[v].im + a[u].im * bv[v].re;
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 4 * ti + u, jc = j0 + 4 * tj + v;
+      if (i < rend && jc <= i) {
+        zc* p = W + (size_t)i * ldw + (i - jc);
+        *p = csub(*p, acc[u][v]);
+      }
+    }
+  (void)m;
 }
 
 // X[:, j k + c] = M_j^{-1} B[:, c] for the columns of group blockIdx.x and
@@ -370,15 +463,14 @@ __global__ __launch_bounds__(256) void k_band_resid(int n, const int* __restrict
 }  // namespace
 
 int band_panel_width(int b) {
-  // the largest power of two up to 32 whose panel fits 144 KiB of LDS
-  int nb = 32;
-  while (nb > 1 && (size_t)(b + nb) * (nb + 1) * sizeof(zc) + nb * sizeof(zc) > 147456) nb /= 2;
-  return nb;
+  (void)b;
+  return kBandMaxPanel;
 }
 
 size_t band_lds_bytes(int b) {
-  const int nb = band_panel_width(b);
-  return (size_t)(b + nb) * (nb + 1) * sizeof(zc) + nb * sizeof(zc);
+  (void)b;
+  // the panel kernel's dynamic LDS: a chunk of rows below the block
+  return (size_t)kPanelRows * (kBandMaxPanel + 1) * sizeof(zc);
 }
 
 int band_solve_ring_rows(int b) {
@@ -405,11 +497,24 @@ hipError_t band_factor(hipStream_t st, int n, int b, int nz, cpx<double>* W, int
   if (n <= 0 || nz <= 0) return hipSuccess;
   const int nb = band_panel_width(b);
   const size_t lds = band_lds_bytes(b);
-  hipError_t e = hipFuncSetAttribute((const void*)k_band_factor,
+  hipError_t e = hipFuncSetAttribute((const void*)k_band_panel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_band_factor, dim3(nz), dim3(kFactorThreads), lds, st, n, b, nb, W,
-                     (size_t)n * (b + 1), info);
+  e = hipMemsetAsync(info, 0, nz * sizeof(int), st);
+  if (e != hipSuccess) return e;
+  const size_t stride = (size_t)n * (b + 1);
+  // panel by panel, all shifts together: the panel (one workgroup per
+  // shift), then its window's Schur complement over many workgroups
+  for (int c = 0; c < n; c += nb) {
+    hipLaunchKernelGGL(k_band_panel, dim3(nz), dim3(kPanelThreads), lds, st, n, b, nb, c, W,
+                       stride, info);
+    const int end = std::min(c + nb, n), m = std::min(n, end + b) - end;
+    if (m > 0) {
+      const int mb = (m + kSchurBlock - 1) / kSchurBlock;
+      hipLaunchKernelGGL(k_band_schur, dim3(mb * (mb + 1) / 2, nz), dim3(256), 0, st, n, b, nb,
+                         c, W, stride, info);
+    }
+  }
   return hipGetLastError();
 }
 
