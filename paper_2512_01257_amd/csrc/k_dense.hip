@@ -63,65 +63,134 @@ __global__ __launch_bounds__(256) void k_spmm_f64(int n, int k, const int* __res
   }
 }
 
-// Two columns per lane (16-byte loads) and 64 / L rows per wave, L the
-// power of two of lanes that covers k / 2 columns pairs (k even, ld even and
-// 16-byte aligned blocks): each load instruction moves twice the bytes of the
-// one-column form, and a wave serves several short rows at once.  Nonzeros
-// go to two partial sums (even and odd positions) in row order.
+// Entry U of a round, loaded by lane U of each group of L lanes, handed to
+// every lane of its group (a row's lanes): a lane swizzle within 32 lanes,
+// or a read of lane U when the row has the whole wave.
+template <int L, int U>
+__device__ __forceinline__ int group_bcast(int v) {
+  if constexpr (L == 64)
+    return __builtin_amdgcn_readlane(v, U);
+  else
+    return __builtin_amdgcn_ds_swizzle(v, (0x1f & ~(L - 1)) | (U << 5));
+}
+
+template <int L, int U, int C>
+struct RoundBcast {
+  __device__ __forceinline__ static void run(int jv, double av, int* j, double* a) {
+    j[U] = group_bcast<L, U>(jv);
+    const long long ab = __double_as_longlong(av);
+    const int lo = group_bcast<L, U>((int)(ab & 0xffffffffLL));
+    const int hi = group_bcast<L, U>((int)(ab >> 32));
+    a[U] = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    RoundBcast<L, U + 1, C>::run(jv, av, j, a);
+  }
+};
+template <int L, int C>
+struct RoundBcast<L, C, C> {
+  __device__ __forceinline__ static void run(int, double, int*, double*) {}
+};
+
+// A row's extent and the first round of its entries (lane u < C of the
+// row's lanes holds entry u), loaded ahead of the row's gathers.
+struct RowHead {
+  int s, e, jv;
+  double av;
+};
+
+// Every load of the SpMM below runs on every lane, at an index that is in
+// range whether or not its value is used (an unused row reads row 0, an
+// unused entry reads entry 0, an unused gather reads row j of entry 0 or
+// column grp * kg), and unused values are dropped where they are consumed:
+// with no lane-masked branch around the loads and no select right after
+// them, the compiler counts the loads in flight and waits only for the ones
+// a step needs.  The matrix has at least one nonzero (checked at launch).
+__device__ __forceinline__ void head_bounds(RowHead& h, int row, bool live,
+                                            const int* __restrict__ rowptr) {
+  const int r = live ? row : 0;
+  h.s = __builtin_nontemporal_load(rowptr + r);
+  h.e = __builtin_nontemporal_load(rowptr + r + 1);
+}
+
+template <int C>
+__device__ __forceinline__ void head_entries(RowHead& h, int sub, int t0,
+                                             const int* __restrict__ col,
+                                             const double* __restrict__ val) {
+  // the matrix streams past L2 (it is read once per column group), which
+  // keeps L2 for the gathered rows of X
+  const int t = sub < C && t0 + sub < h.e ? t0 + sub : 0;
+  h.jv = __builtin_nontemporal_load(col + t);
+  h.av = __builtin_nontemporal_load(val + t);
+}
+
+// One row of Y (the columns of group grp) for the lanes of sub-index sub.
+// h holds the row's extent and its first round of entries; later rounds and
+// later column passes load their own.
 template <int L>
-__global__ __launch_bounds__(256) void k_spmm_f64_x2(int n, int k, const int* __restrict__ rowptr,
-                                                     const int* __restrict__ col,
-                                                     const double* __restrict__ val,
-                                                     const double* __restrict__ X, int ldx,
-                                                     double* __restrict__ Y, int ldy, double alpha,
-                                                     double beta, const double* __restrict__ X2,
-                                                     int ldx2, double gamma) {
-  constexpr int RW = 64 / L;  // rows per wave
-  const int lane = threadIdx.x & 63;
-  const int row = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RW + lane / L;
-  if (row >= n) return;
-  const int sub = lane % L;
-  const int s = rowptr[row], e = rowptr[row + 1];
-  for (int c0 = 0; c0 < k; c0 += 2 * L) {
+__device__ __forceinline__ void spmm_x2_row(int row, int sub, int grp, int k, int kg,
+                                            const RowHead& h, const int* __restrict__ col,
+                                            const double* __restrict__ val,
+                                            const double* __restrict__ X, int ldx,
+                                            double* __restrict__ Y, int ldy, double alpha,
+                                            double beta, const double* __restrict__ X2, int ldx2,
+                                            double gamma) {
+  constexpr int C = L < 8 ? L : 8;  // nonzeros per round
+  const int s = h.s, e = h.e;
+  const int cend = min(k, (grp + 1) * kg);
+  // round 0 (positions s .. s + C - 1): lane u < C of the row's lanes holds
+  // entry u; handed round the row's lanes once, kept for every column pass
+  int j0[C];
+  double a0[C];
+  RoundBcast<L, 0, C>::run(h.jv, h.av, j0, a0);
+  for (int c0 = grp * kg; c0 < cend; c0 += 2 * L) {
     const int c = c0 + 2 * sub;
-    const bool ok = c < k;
+    const bool ok = c < cend;
+    const int cs = ok ? c : grp * kg;  // an in-range column for the idle lanes
     double2 acc0 = make_double2(0.0, 0.0), acc1 = acc0;
-    int t = s;
-    for (; t + 3 < e; t += 4) {
-      const int j0 = col[t], j1 = col[t + 1], j2 = col[t + 2], j3 = col[t + 3];
-      const double a0 = val[t], a1 = val[t + 1], a2 = val[t + 2], a3 = val[t + 3];
-      if (ok) {
-        const double2 x0 = *reinterpret_cast<const double2*>(X + (size_t)j0 * ldx + c);
-        const double2 x1 = *reinterpret_cast<const double2*>(X + (size_t)j1 * ldx + c);
-        const double2 x2 = *reinterpret_cast<const double2*>(X + (size_t)j2 * ldx + c);
-        const double2 x3 = *reinterpret_cast<const double2*>(X + (size_t)j3 * ldx + c);
-        acc0.x += a0 * x0.x;
-        acc0.y += a0 * x0.y;
-        acc1.x += a1 * x1.x;
-        acc1.y += a1 * x1.y;
-        acc0.x += a2 * x2.x;
-        acc0.y += a2 * x2.y;
-        acc1.x += a3 * x3.x;
-        acc1.y += a3 * x3.y;
+    // the gathered rows of a round are loaded together; even and odd
+    // positions of the row go to two partial sums, in order (a round of one
+    // entry alternates between them)
+    {
+      double2 x[C];
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        x[u] = *reinterpret_cast<const double2*>(X + (size_t)j0[u] * ldx + cs);
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        if (s + u < e) {
+          if (u & 1) {
+            acc1.x += a0[u] * x[u].x;
+            acc1.y += a0[u] * x[u].y;
+          } else {
+            acc0.x += a0[u] * x[u].x;
+            acc0.y += a0[u] * x[u].y;
+          }
+        }
       }
     }
-    for (; t + 1 < e; t += 2) {
-      const int j0 = col[t], j1 = col[t + 1];
-      const double a0 = val[t], a1 = val[t + 1];
-      if (ok) {
-        const double2 x0 = *reinterpret_cast<const double2*>(X + (size_t)j0 * ldx + c);
-        const double2 x1 = *reinterpret_cast<const double2*>(X + (size_t)j1 * ldx + c);
-        acc0.x += a0 * x0.x;
-        acc0.y += a0 * x0.y;
-        acc1.x += a1 * x1.x;
-        acc1.y += a1 * x1.y;
+    // later rounds (rows longer than C): their entries are loaded here
+    for (int t0 = s + C; t0 < e; t0 += C) {
+      RowHead r = h;
+      head_entries<C>(r, sub, t0, col, val);
+      int j[C];
+      double a[C];
+      RoundBcast<L, 0, C>::run(r.jv, r.av, j, a);
+      double2 x[C];
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+        x[u] = *reinterpret_cast<const double2*>(X + (size_t)j[u] * ldx + cs);
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        if (t0 + u < e) {
+          const bool odd = C == 1 ? ((t0 - s) & 1) != 0 : (u & 1) != 0;
+          if (odd) {
+            acc1.x += a[u] * x[u].x;
+            acc1.y += a[u] * x[u].y;
+          } else {
+            acc0.x += a[u] * x[u].x;
+            acc0.y += a[u] * x[u].y;
+          }
+        }
       }
-    }
-    if (t < e && ok) {
-      const double a0 = val[t];
-      const double2 x0 = *reinterpret_cast<const double2*>(X + (size_t)col[t] * ldx + c);
-      acc0.x += a0 * x0.x;
-      acc0.y += a0 * x0.y;
     }
     if (ok) {
       double2 y = make_double2(alpha * (acc0.x + acc1.x), alpha * (acc0.y + acc1.y));
@@ -135,26 +204,118 @@ __global__ __launch_bounds__(256) void k_spmm_f64_x2(int n, int k, const int* __
         y.x += gamma * x2r.x;
         y.y += gamma * x2r.y;
       }
-      *reinterpret_cast<double2*>(Y + (size_t)row * ldy + c) = y;
+      // Y is not read again here: streamed past L2, which keeps the gathered rows
+      typedef double d2v __attribute__((ext_vector_type(2)));
+      d2v yv;
+      yv.x = y.x;
+      yv.y = y.y;
+      __builtin_nontemporal_store(yv, reinterpret_cast<d2v*>(Y + (size_t)row * ldy + c));
     }
   }
 }
 
+// Two columns per lane (16-byte loads) and 64 / L rows per wave, L the
+// power of two of lanes that covers kg / 2 column pairs (k even, ld even and
+// 16-byte aligned blocks): each load instruction moves twice the bytes of the
+// one-column form, and a wave serves several short rows at once.  Nonzeros
+// go to two partial sums (even and odd positions) in row order.
+//
+// Placement: workgroup b runs on XCD b mod 8 (dispatch deals workgroup ids
+// to the eight XCDs in turn).  XCD x owns the x-th contiguous eighth of the
+// row blocks (rbx of them) and sweeps it once per group of kg columns, in
+// row order, so a gathered row X[j, group] is fetched into that XCD's L2
+// once and reused by the rows around j that need it, as long as the rows
+// within the matrix's span of j fit in L2 for one group (the host picks kg
+// for that).  A workgroup takes rpb consecutive row blocks of 4 * 64 / L
+// rows, one after the other, as a pipeline: while a block's gathers are in
+// flight, the next block's first entries and the extents of the block after
+// it are loaded.
+template <int L>
+__global__ __launch_bounds__(256) void k_spmm_f64_x2(int n, int k, int kg, int rbx, int rpb,
+                                                     const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ X, int ldx,
+                                                     double* __restrict__ Y, int ldy, double alpha,
+                                                     double beta, const double* __restrict__ X2,
+                                                     int ldx2, double gamma) {
+  constexpr int RW = 64 / L;  // rows per wave
+  constexpr int C = L < 8 ? L : 8;
+  const int b = (int)blockIdx.x;
+  const int i = b >> 3;
+  const int nbx = (rbx + rpb - 1) / rpb;  // workgroups per XCD and group
+  const int grp = i / nbx;
+  const int rb0 = (i - grp * nbx) * rpb;
+  const int rb1 = min(rbx, rb0 + rpb);
+  const int lane = threadIdx.x & 63;
+  const int sub = lane % L;
+  auto row_of = [&](int rbl) {
+    return (((b & 7) * rbx + rbl) * 4 + (int)(threadIdx.x >> 6)) * RW + lane / L;
+  };
+  auto live = [&](int rbl, int r) { return rbl < rb1 && r < n; };
+  int row = row_of(rb0), nrow = row_of(rb0 + 1);
+  RowHead h, nh;
+  head_bounds(h, row, live(rb0, row), rowptr);
+  head_bounds(nh, nrow, live(rb0 + 1, nrow), rowptr);
+  head_entries<C>(h, sub, h.s, col, val);
+  for (int rbl = rb0; rbl < rb1; ++rbl) {
+    if (row >= n) break;
+    const int nnrow = row_of(rbl + 2);
+    RowHead nnh;
+    head_bounds(nnh, nnrow, live(rbl + 2, nnrow), rowptr);
+    head_entries<C>(nh, sub, nh.s, col, val);
+    spmm_x2_row<L>(row, sub, grp, k, kg, h, col, val, X, ldx, Y, ldy, alpha, beta, X2, ldx2,
+                   gamma);
+    h = nh;
+    nh = nnh;
+    row = nrow;
+    nrow = nnrow;
+  }
+}
+
+// Row blocks a workgroup of the two-column SpMM sweeps.
+#ifndef RAFEAST_SPMM_RPB
+#define RAFEAST_SPMM_RPB 4
+#endif
+
+// Bytes of an XCD's L2 (4 MiB) given to the gathered rows of one column group.
+#ifndef RAFEAST_SPMM_L2_BYTES
+#define RAFEAST_SPMM_L2_BYTES (3 << 20)
+#endif
+
+int spmm_group_cols(int k, int64_t span) {
+  // the rows a gather can reach around row j span 2 * span + 1 rows of a
+  // group's kg FP64 columns: the fewest equal groups (kg even, at least 8)
+  // whose rows fit the budget
+  for (int ng = 1;; ++ng) {
+    int kg = (k + ng - 1) / ng;
+    kg += kg & 1;
+    if (kg <= 8 || (2 * span + 1) * (int64_t)kg * 8 <= (int64_t)RAFEAST_SPMM_L2_BYTES)
+      return kg < k ? kg : k;
+  }
+}
+
 hipError_t launch_spmm_f64(hipStream_t st, int n, int k, const int* rowptr, const int* col,
-                           const double* val, const double* X, int ldx, double* Y, int ldy,
-                           double alpha, double beta, const double* X2, int ldx2, double gamma) {
+                           const double* val, int64_t nnz, const double* X, int ldx, double* Y,
+                           int ldy, double alpha, double beta, const double* X2, int ldx2,
+                           double gamma, int64_t span) {
   if (n <= 0 || k <= 0) return hipSuccess;
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   const bool x2_ok = X2 == nullptr || (ldx2 % 2 == 0 && al16(X2));
-  if (k % 2 == 0 && ldx % 2 == 0 && ldy % 2 == 0 && al16(X) && al16(Y) && x2_ok) {
-    // lanes per row: the power of two covering k / 2 column pairs (<= 64)
+  if (nnz > 0 && k % 2 == 0 && ldx % 2 == 0 && ldy % 2 == 0 && al16(X) && al16(Y) && x2_ok) {
+    const int kg = span > 0 ? spmm_group_cols(k, span) : k;
+    const int ng = (k + kg - 1) / kg;
+    // lanes per row: the power of two covering kg / 2 column pairs (<= 64)
     int L = 1;
-    while (L < 64 && 2 * L < k) L *= 2;
+    while (L < 64 && 2 * L < kg) L *= 2;
     const int rw = 64 / L;
-    const dim3 grid((unsigned)((n + 4 * rw - 1) / (4 * rw)));
-#define RAFEAST_SPMM_X2(LL)                                                                      \
-  hipLaunchKernelGGL(k_spmm_f64_x2<LL>, grid, dim3(256), 0, st, n, k, rowptr, col, val, X, ldx, \
-                     Y, ldy, alpha, beta, X2, ldx2, gamma)
+    const int rblocks = (n + 4 * rw - 1) / (4 * rw);
+    const int rbx = (rblocks + 7) / 8;
+    const int rpb = RAFEAST_SPMM_RPB;
+    const dim3 grid((unsigned)(8 * ng * ((rbx + rpb - 1) / rpb)));
+#define RAFEAST_SPMM_X2(LL)                                                                     \
+  hipLaunchKernelGGL(k_spmm_f64_x2<LL>, grid, dim3(256), 0, st, n, k, kg, rbx, rpb, rowptr, col, \
+                     val, X, ldx, Y, ldy, alpha, beta, X2, ldx2, gamma)
     switch (L) {
       case 1: RAFEAST_SPMM_X2(1); break;
       case 2: RAFEAST_SPMM_X2(2); break;

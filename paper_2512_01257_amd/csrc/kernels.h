@@ -14,9 +14,13 @@ namespace rafeast {
 
 // ---- sparse x dense (FP64, real) ------------------------------------------
 // Y = alpha * A X + beta * X + gamma * X2 (X2 may be null), CSR A (FP64).
+// span: max |i - j| over the nonzeros a_ij (0: unknown); it sets how many
+// columns one sweep over the rows gathers (spmm_group_cols).
 hipError_t launch_spmm_f64(hipStream_t st, int n, int k, const int* rowptr, const int* col,
-                           const double* val, const double* X, int ldx, double* Y, int ldy,
-                           double alpha, double beta, const double* X2, int ldx2, double gamma);
+                           const double* val, int64_t nnz, const double* X, int ldx, double* Y,
+                           int ldy, double alpha, double beta, const double* X2, int ldx2,
+                           double gamma, int64_t span);
+int spmm_group_cols(int k, int64_t span);
 
 // ---- tall-skinny products (FP64 MFMA) ----------------------------------------
 // Number of row chunks the Gram splits n into, and the partial buffer it needs.

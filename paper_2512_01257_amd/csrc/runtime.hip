@@ -54,6 +54,7 @@ struct rafeast_plan_s {
   int* d_rowptr = nullptr;
   int* d_col = nullptr;
   double* d_val = nullptr;
+  int64_t span = 0;  // max |i - j| over the nonzeros (sets the SpMM's column groups)
   SellMatrix sell;
   int* d_sbase = nullptr;
   int* d_perm = nullptr;
@@ -754,8 +755,8 @@ rafeast_status spmm(rafeast_plan_s* P, int k, const double* X, int ldx, double* 
     }
     return RAFEAST_OK;
   }
-  HIPCHK(P, launch_spmm_f64(P->st, (int)P->n, k, P->d_rowptr, P->d_col, P->d_val, X, ldx, Y, ldy,
-                            alpha, beta, X2, ldx2, gamma));
+  HIPCHK(P, launch_spmm_f64(P->st, (int)P->n, k, P->d_rowptr, P->d_col, P->d_val, P->nnz, X, ldx,
+                            Y, ldy, alpha, beta, X2, ldx2, gamma, P->span));
   return RAFEAST_OK;
 }
 
@@ -1742,6 +1743,9 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
     std::vector<int> rp(n + 1), cl(nnz);
     for (int64_t i = 0; i <= n; ++i) rp[i] = A->rowptr[i] - base;
     for (int64_t t = 0; t < nnz; ++t) cl[t] = A->colind[t] - base;
+    for (int64_t i = 0; i < n; ++i)
+      for (int t = rp[i]; t < rp[i + 1]; ++t)
+        P->span = std::max<int64_t>(P->span, std::abs((int64_t)cl[t] - i));
     PRCHK(dalloc(P, &P->d_rowptr, n + 1, "rowptr"));
     PRCHK(dalloc(P, &P->d_col, nnz, "colind"));
     PRCHK(dalloc(P, &P->d_val, nnz, "values"));

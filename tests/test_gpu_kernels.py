@@ -72,6 +72,30 @@ def test_spmm_parity(small_plan, torch_dev):
         assert np.all(np.abs(Y.cpu().numpy() - ref) <= bound + 1e-300), k
 
 
+def test_spmm_column_groups(gpu_lib, torch_dev):
+    # a 64 x 64 x 40 grid in natural order: a row reaches 4096 rows either
+    # side, so wide blocks are swept in column groups (64 -> 2 x 32,
+    # 84 -> 2 x 42, 130 -> 44 + 44 + 42), narrow ones in one; odd k takes the
+    # one-column kernel
+    torch = torch_dev
+    csr = grid_laplacian((64, 64, 40), 0.01)
+    plan = _plan(gpu_lib, csr, engine="stream")
+    A = csr.to_scipy()
+    rng = np.random.default_rng(7)
+    try:
+        for k in (64, 84, 130, 16, 9):
+            X = rng.standard_normal((csr.n, k))
+            Y = torch.full((csr.n, k), float("nan"), dtype=torch.float64, device="cuda")
+            plan.spmm(torch.from_numpy(X).cuda(), Y, alpha=0.75, beta=-1.5)
+            ref = 0.75 * (A @ X) - 1.5 * X
+            bound = 1.01 * 10 * U * (0.75 * (abs(A) @ np.abs(X)) + 1.5 * np.abs(X))
+            got = Y.cpu().numpy()
+            assert np.isfinite(got).all(), k
+            assert np.all(np.abs(got - ref) <= bound + 1e-300), k
+    finally:
+        plan.close()
+
+
 @pytest.mark.parametrize("n,k,cond", [(5000, 64, 1e2), (5000, 64, 1e10), (999, 37, 1e6),
                                       (20000, 148, 1e4), (300, 1, 1.0)])
 def test_cholqr2(small_plan, torch_dev, n, k, cond):
