@@ -24,7 +24,10 @@
  *    A and all workspace.  A plan is not thread-safe; distinct plans are
  *    independent.  All work is enqueued on the plan's stream
  *    (rafeast_params.hip_stream, or a stream the plan creates when NULL);
- *    every call returns after its work on that stream has completed.
+ *    every call returns after its work on that stream has completed.  Device
+ *    inputs must be complete when that stream reaches the call: work of the
+ *    caller's on another stream that writes them is the caller's to finish
+ *    (or order) first.
  */
 #ifndef RAFEAST_H
 #define RAFEAST_H

@@ -317,7 +317,8 @@ class Plan:
         st = L.rafeast_plan(C.byref(A), C.byref(prm), C.byref(h))
         if st != 0:
             raise RafeastError(st, L.rafeast_last_error(None).decode())
-        self._setup(h, int(csr.n), m0, nc, lmin, lmax, precision, p, owned=True)
+        self._setup(h, int(csr.n), m0, nc, lmin, lmax, precision, p, owned=True,
+                    own_stream=stream is None)
 
     @classmethod
     def _from_dense(cls, make, n, lmin, lmax, m0, kw):
@@ -334,7 +335,7 @@ class Plan:
             raise RafeastError(st, lib().rafeast_last_error(None).decode())
         self = cls.__new__(cls)
         self._setup(h, int(n), m0, opts["nc"], lmin, lmax, opts["precision"], opts["p"],
-                    owned=True)
+                    owned=True, own_stream=stream is None)
         return self
 
     @classmethod
@@ -359,9 +360,10 @@ class Plan:
             lambda prm, h: lib().rafeast_plan_gram(rows, n, _dptr(X), rows, sc, prm, h),
             n, lmin, lmax, m0, kw)
 
-    def _setup(self, h, n, m0, nc, lmin, lmax, precision, p, owned):
+    def _setup(self, h, n, m0, nc, lmin, lmax, precision, p, owned, own_stream=True):
         self._h = h
         self._owned = owned
+        self._own_stream = own_stream
         self.n = n
         self.m0 = m0
         self.nc = nc
@@ -387,6 +389,15 @@ class Plan:
 
     def __exit__(self, *a):
         self.close()
+
+    def _ready(self):
+        # A plan made without a stream runs on a stream of its own: device
+        # tensors that torch is still writing on its current stream (a fill,
+        # a copy) must be complete before the plan reads them.
+        if self._own_stream:
+            import torch
+
+            torch.cuda.current_stream().synchronize()
 
     def _check(self, st):
         if st != 0:
@@ -415,6 +426,7 @@ class Plan:
     # ------------------------------------------- learned preconditioner
     def pc_samples(self, z, R, theta_lo, theta_hi):
         """(X, G, h, rr) device tensors for real residuals R (device n x k FP64)."""
+        self._ready()
         import torch
 
         z = np.asarray(z, dtype=np.complex128)
@@ -436,6 +448,7 @@ class Plan:
         samples from the COCG residuals of the plan's own shifted systems
         after each count of plain COCG iterations in steps (right-hand sides:
         the residual block of the plan's last Rayleigh-Ritz step)."""
+        self._ready()
         import torch
 
         st = np.ascontiguousarray(steps, dtype=np.int32)
@@ -453,6 +466,7 @@ class Plan:
 
     def pc_normalize(self, X, W):
         """rafeast_pc_normalize: W's input standardization from features X."""
+        self._ready()
         import torch
 
         self._check(lib().rafeast_pc_normalize(self._h, X.shape[0], _tptr(X, torch.float64),
@@ -460,11 +474,13 @@ class Plan:
 
     def pc_attach(self, W):
         """rafeast_pc_attach: the plan copies the FP32 network parameters W."""
+        self._ready()
         import torch
 
         self._check(lib().rafeast_pc_attach(self._h, _tptr(W, torch.float32)))
 
     def pc_forward(self, X, W):
+        self._ready()
         import torch
 
         Y = torch.empty((X.shape[0], 16), dtype=torch.float32, device="cuda")
@@ -473,6 +489,7 @@ class Plan:
         return Y
 
     def pc_gradient(self, X, G, h, rr, W):
+        self._ready()
         import torch
 
         g = torch.empty(lib().rafeast_pc_param_count(), dtype=torch.float32, device="cuda")
@@ -484,6 +501,7 @@ class Plan:
 
     def pc_train(self, X, G, h, rr, W, order, batch, lr):
         """Adam on W (device FP32, in place); order: host int32 [steps * batch]."""
+        self._ready()
         import torch
 
         order = np.ascontiguousarray(order, dtype=np.int32)
@@ -498,6 +516,7 @@ class Plan:
     def pc_solve(self, z, B, X, tol, coef=None):
         """Preconditioned (coef: [nz][8] complex) or plain FP64 COCG; X device
         complex128 n x (nz*k).  Returns (iters, resid)."""
+        self._ready()
         import torch
 
         z = np.asarray(z, dtype=np.complex128)
@@ -570,6 +589,7 @@ class Plan:
 
     def solve_device(self, lam, resid, X=None, Q_init=None):
         """rafeast_solve with RAFEAST_PTR_DEVICE outputs into torch tensors."""
+        self._ready()
         import torch
 
         qi = None
@@ -591,6 +611,7 @@ class Plan:
 
     # ------------------------------------------------ step-level (device) ---
     def spmm(self, X, Y, alpha=1.0, beta=0.0):
+        self._ready()
         import torch
 
         k = X.shape[1]
@@ -598,6 +619,7 @@ class Plan:
                                        _tptr(Y, torch.float64), Y.stride(0), alpha, beta))
 
     def gram(self, X, Y, G):
+        self._ready()
         import torch
 
         self._check(lib().rafeast_gram(self._h, X.shape[0], X.shape[1], Y.shape[1],
@@ -606,6 +628,7 @@ class Plan:
                                        _tptr(G, torch.float64), G.stride(0)))
 
     def cholqr2(self, Y):
+        self._ready()
         import torch
 
         info = C.c_int32()
@@ -614,6 +637,7 @@ class Plan:
         return info.value
 
     def syev(self, H, theta, S):
+        self._ready()
         import torch
 
         self._check(lib().rafeast_syev(self._h, H.shape[0], _tptr(H, torch.float64),
@@ -621,6 +645,7 @@ class Plan:
 
     def shifted_solve(self, z, B, X, tol):
         """X[:, j*k + c] = (z_j I - A)^{-1} B[:, c]; X complex64 (fp32 plan) or complex128."""
+        self._ready()
         import torch
 
         z = np.asarray(z, dtype=np.complex128)
@@ -636,6 +661,7 @@ class Plan:
         return np.array(it[:], dtype=np.int64), rs
 
     def gaussian(self, Omega, seed):
+        self._ready()
         import torch
 
         self._check(lib().rafeast_gaussian(self._h, Omega.shape[1], seed,

@@ -186,6 +186,22 @@ def test_gaussian_matches_oracle_philox(small_plan, torch_dev, seed):
         np.testing.assert_allclose(O.cpu().numpy(), ref, rtol=1e-14, atol=1e-14)
 
 
+def test_plan_waits_for_torch_stream(small_plan, torch_dev):
+    # a plan made without a stream runs on its own; an output tensor whose
+    # fill torch has queued behind long work on its current stream must be
+    # filled before the plan writes it (else the late fill overwrites it)
+    torch = torch_dev
+    csr, plan = small_plan
+    M = torch.randn((4096, 4096), dtype=torch.float32, device="cuda")
+    for _ in range(6):
+        M = torch.tanh(M @ M)
+    O = torch.full((csr.n, 21), 7.0, dtype=torch.float64, device="cuda")
+    plan.gaussian(O, 99)
+    ref = philox.gaussian_sketch(csr.n, 21, 99)
+    np.testing.assert_allclose(O.cpu().numpy(), ref, rtol=1e-14, atol=1e-14)
+    assert torch.isfinite(M).all()
+
+
 @pytest.mark.parametrize("engine", ["resident", "stream"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("fp32", 1e-10)])
 def test_shifted_solve_cocg(gpu_lib, torch_dev, precision, tol, engine):
