@@ -113,6 +113,18 @@ __device__ __forceinline__ void st(cpx<T>* __restrict__ p, const Chunk<T, CPL>& 
   for (int q = 0; q < CPL; ++q) p[q] = c.v[q];
 }
 
+// The same as a non-temporal store: the value streams past L2 (written once,
+// read by a later kernel), which keeps L2 for the rows a gather reuses.
+template <typename T, int CPL>
+__device__ __forceinline__ void st_nt(cpx<T>* __restrict__ p, const Chunk<T, CPL>& c) {
+  T* f = reinterpret_cast<T*>(p);
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    __builtin_nontemporal_store(c.v[q].re, f + 2 * q);
+    __builtin_nontemporal_store(c.v[q].im, f + 2 * q + 1);
+  }
+}
+
 // Sum the 4 waves' per-lane partials and store the workgroup's partials at
 // part[(blockIdx.x * Bp + c) * NQ + u].
 template <int CPL, int NQ>
@@ -323,7 +335,7 @@ __global__ __launch_bounds__(kST) void k_s_spmm(int n, const int* __restrict__ r
       acc[q][0] += pr * wr_ - pi * wi;
       acc[q][1] += pr * wi + pi * wr_;
     }
-    st<T, CPL>(w + ro, ww);
+    st_nt<T, CPL>(w + ro, ww);  // read by the update kernel, not by this sweep
     s = s2;
     e = e2;
     mc = mc2;
