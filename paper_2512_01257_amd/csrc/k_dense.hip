@@ -345,6 +345,10 @@ hipError_t launch_spmm_f64(hipStream_t st, int n, int k, const int* rowptr, cons
 // Rows are split into chunks (grid.x); each wave owns one 16-row tile strip of
 // G and four 16-column tiles; partial Grams are summed in chunk order.
 // ============================================================================
+// Word 3 of a raw buffer descriptor on gfx9-family GPUs (no format, no
+// swizzle, stride 0): reads past num_records bytes return zero.
+constexpr int kBufferWord3 = 0x00020000;
+
 int gram_chunks(int64_t n) {
   int64_t c = (n + 127) / 128;
   if (c > 256) c = 256;
@@ -356,83 +360,123 @@ size_t gram_partial_doubles(int64_t n, int k1, int k2) {
   return (size_t)gram_chunks(n) * (size_t)k1 * (size_t)k2;
 }
 
-// Each wave owns a TA x TB block of 16 x 16 output tiles: per 4-row step it
-// loads TA + TB operand fragments and issues TA * TB MFMAs on them, so each
-// fragment feeds several MFMAs (a 1 x 4 block loads 5 fragments for 4).
-template <int TA, int TB>
+// A workgroup owns a TA x TB block of 16 x 16 output tiles of one row chunk;
+// its 4 waves split the chunk's rows (wave w takes batches w, w + 4, ...)
+// and add their partial blocks through LDS in wave order.  Per 4-row step a
+// wave loads TA + TB operand fragments and issues TA * TB MFMAs on them.
+// Rows go in batches of U steps (4 U rows) whose loads are issued together,
+// unconditionally (a column past k reads column k - 1, which only feeds rows
+// or columns of G that are not stored; a row past the chunk reads zero), and
+// every tile's MFMA is issued, so no branch separates the loads from the
+// MFMAs.
+template <int TA, int TB, int U>
 __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k1, int k2,
                                                       const double* __restrict__ X, int ldx,
                                                       const double* __restrict__ Y, int ldy,
                                                       double* __restrict__ part,
                                                       int64_t rows_per_chunk) {
+  constexpr int kBlockVals = TA * TB * 256;  // one wave's partial block
+  __shared__ double sh[4 * kBlockVals];
   const int chunk = blockIdx.x;
   const int64_t r_begin = (int64_t)chunk * rows_per_chunk;
   int64_t r_end = r_begin + rows_per_chunk;
   if (r_end > n) r_end = n;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int ta_n = (k1 + 15) >> 4, tb_n = (k2 + 15) >> 4;
   const int bb_n = (tb_n + TB - 1) / TB;  // tile blocks per block row
-  const int blk = blockIdx.y * 4 + wave;
+  const int blk = blockIdx.y;
   const int ta0 = (blk / bb_n) * TA, tb0 = (blk % bb_n) * TB;
-  if (ta0 >= ta_n) return;
   const int li = lane & 15, lk = lane >> 4;
-  const int na = min(TA, ta_n - ta0), nb = min(TB, tb_n - tb0);  // wave-uniform
   int a_col[TA], b_col[TB];
-  bool a_ok[TA], b_ok[TB];
 #pragma unroll
-  for (int i = 0; i < TA; ++i) {
-    a_col[i] = (ta0 + i) * 16 + li;
-    a_ok[i] = i < na && a_col[i] < k1;
-  }
+  for (int i = 0; i < TA; ++i) a_col[i] = (ta0 + i) * 16 + li;
 #pragma unroll
-  for (int j = 0; j < TB; ++j) {
-    b_col[j] = (tb0 + j) * 16 + li;
-    b_ok[j] = j < nb && b_col[j] < k2;
-  }
+  for (int j = 0; j < TB; ++j) b_col[j] = (tb0 + j) * 16 + li;
   v4d acc[TA][TB];
 #pragma unroll
   for (int i = 0; i < TA; ++i)
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int64_t r = r_begin; r < r_end; r += 4) {
-    const int64_t rr = r + lk;
-    const bool r_ok = rr < r_end;
-    double a[TA], b[TB];
+
+  // Loads go through buffer descriptors covering exactly the chunk's rows of
+  // X and Y: an address is a per-lane 32-bit byte offset (lane row lk, tile
+  // column) plus a wave-uniform row offset, and a read past the chunk's last
+  // row returns zero, so the last partial batch needs no guard.
+  constexpr int BR = 4 * U;  // rows per batch
+  const int64_t nrows = r_end > r_begin ? r_end - r_begin : 0;
+  const int64_t nbatch = (nrows + BR - 1) / BR;
+  const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(X + r_begin * ldx), (short)0, (int)(nrows * ldx * 8), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t ys = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(Y + r_begin * ldy), (short)0, (int)(nrows * ldy * 8), kBufferWord3);
+  int xo[TA], yo[TB];
 #pragma unroll
-    for (int i = 0; i < TA; ++i) a[i] = (a_ok[i] && r_ok) ? X[rr * ldx + a_col[i]] : 0.0;
+  for (int i = 0; i < TA; ++i) xo[i] = (lk * ldx + min(a_col[i], k1 - 1)) * 8;
 #pragma unroll
-    for (int j = 0; j < TB; ++j) b[j] = (b_ok[j] && r_ok) ? Y[rr * ldy + b_col[j]] : 0.0;
+  for (int j = 0; j < TB; ++j) yo[j] = (lk * ldy + min(b_col[j], k2 - 1)) * 8;
+  for (int64_t bt = wave; bt < nbatch; bt += 4) {
+    const int r = (int)(bt * BR);  // row within the chunk
+    double a[U][TA], b[U][TB];
 #pragma unroll
-    for (int i = 0; i < TA; ++i)
+    for (int u = 0; u < U; ++u) {
+      const int xrow = (r + 4 * u) * ldx * 8, yrow = (r + 4 * u) * ldy * 8;
+#pragma unroll
+      for (int i = 0; i < TA; ++i)
+        a[u][i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xs, xo[i], xrow, 0));
 #pragma unroll
       for (int j = 0; j < TB; ++j)
-        if (i < na && j < nb)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        b[u][j] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ys, yo[j], yrow, 0));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < TA; ++i)
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][i], b[u][j], acc[i][j], 0, 0, 0);
   }
-  double* P = part + (size_t)chunk * k1 * k2;
+  // the 4 waves' blocks, summed in wave order; element (i, j, v, l) of a
+  // block is D[l / 16 + 4 v][l % 16] of tile (i, j)
 #pragma unroll
   for (int i = 0; i < TA; ++i)
 #pragma unroll
-    for (int j = 0; j < TB; ++j) {
-      if (!(i < na && j < nb)) continue;
+    for (int j = 0; j < TB; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = (ta0 + i) * 16 + lk + 4 * v;
-        const int gj = (tb0 + j) * 16 + li;
-        if (gi < k1 && gj < k2) P[(size_t)gi * k2 + gj] = acc[i][j][v];
-      }
-    }
+      for (int v = 0; v < 4; ++v)
+        sh[wave * kBlockVals + ((i * TB + j) * 4 + v) * 64 + lane] = acc[i][j][v];
+  __syncthreads();
+  double* P = part + (size_t)chunk * k1 * k2;
+  for (int e = threadIdx.x; e < kBlockVals; e += 256) {
+    const int l = e & 63, v = (e >> 6) & 3, t = e >> 8;
+    const int i = t / TB, j = t % TB;
+    const int gi = (ta0 + i) * 16 + (l >> 4) + 4 * v;
+    const int gj = (tb0 + j) * 16 + (l & 15);
+    if (gi < k1 && gj < k2)
+      P[(size_t)gi * k2 + gj] =
+          ((sh[e] + sh[kBlockVals + e]) + sh[2 * kBlockVals + e]) + sh[3 * kBlockVals + e];
+  }
 }
 
+// G = the sum of the chunks' partial Grams: a workgroup takes 64 consecutive
+// elements, wave w sums the w-th quarter of the chunks for them (coalesced
+// across the lanes), and the four quarter sums are added in wave order.
 __global__ __launch_bounds__(256) void k_gram_reduce(int chunks, int k1, int k2,
                                                      const double* __restrict__ part,
                                                      double* __restrict__ G, int ldg) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= k1 * k2) return;
-  const size_t stride = (size_t)k1 * k2;
+  __shared__ double sh[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 64 + lane;
+  const int total = k1 * k2;
+  const size_t stride = (size_t)total;
+  const int q = (chunks + 3) / 4;
+  const int c0 = wave * q, c1 = min(chunks, c0 + q);
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * stride + e];
-  G[(size_t)(e / k2) * ldg + (e % k2)] = s;
+  if (e < total)
+    for (int c = c0; c < c1; ++c) s += part[(size_t)c * stride + e];
+  sh[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && e < total)
+    G[(size_t)(e / k2) * ldg + (e % k2)] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
 }
 
 hipError_t launch_gram(hipStream_t st, int64_t n, int k1, int k2, const double* X, int ldx,
@@ -449,21 +493,21 @@ hipError_t launch_gram_chunks(hipStream_t st, int64_t n, int k1, int k2, const d
   int64_t rpc = (n + chunks - 1) / chunks;
   rpc = (rpc + 3) & ~int64_t(3);
   const int ta_n = (k1 + 15) / 16, tb_n = (k2 + 15) / 16;
-  // the largest tile block that still gives three or more workgroups per
-  // chunk (the chip holds several per CU), else 2 x 2
+  // one workgroup per tile block and chunk: 3 x 3 blocks when that still
+  // gives twelve or more per chunk, else 2 x 2
   auto nblk = [&](int ta, int tb) { return ((ta_n + ta - 1) / ta) * ((tb_n + tb - 1) / tb); };
-  const bool big = (nblk(3, 3) + 3) / 4 >= 3;
+  const bool big = nblk(3, 3) >= 12;
   const int blocks = big ? nblk(3, 3) : nblk(2, 2);
-  dim3 grid(chunks, (blocks + 3) / 4);
+  dim3 grid(chunks, blocks);
   if (big)
-    hipLaunchKernelGGL((k_gram_partial<3, 3>), grid, dim3(256), 0, st, n, k1, k2, X, ldx, Y,
+    hipLaunchKernelGGL((k_gram_partial<3, 3, 2>), grid, dim3(256), 0, st, n, k1, k2, X, ldx, Y,
                        ldy, part, rpc);
   else
-    hipLaunchKernelGGL((k_gram_partial<2, 2>), grid, dim3(256), 0, st, n, k1, k2, X, ldx, Y,
+    hipLaunchKernelGGL((k_gram_partial<2, 2, 4>), grid, dim3(256), 0, st, n, k1, k2, X, ldx, Y,
                        ldy, part, rpc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((k1 * k2 + 255) / 256), dim3(256), 0, st, chunks, k1,
+  hipLaunchKernelGGL(k_gram_reduce, dim3((k1 * k2 + 63) / 64), dim3(256), 0, st, chunks, k1,
                      k2, part, G, ldg);
   return hipGetLastError();
 }
