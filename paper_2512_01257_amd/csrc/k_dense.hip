@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k1, int k2,
   int64_t r_end = r_begin + rows_per_chunk;
   if (r_end > n) r_end = n;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int ta_n = (k1 + 15) >> 4, tb_n = (k2 + 15) >> 4;
+  const int tb_n = (k2 + 15) >> 4;
   const int bb_n = (tb_n + TB - 1) / TB;  // tile blocks per block row
   const int blk = blockIdx.y;
   const int ta0 = (blk / bb_n) * TA, tb0 = (blk % bb_n) * TB;
@@ -563,12 +563,92 @@ __global__ __launch_bounds__(256) void k_tsmm(int64_t n, int k, int k2,
   }
 }
 
+// The same product with the workgroup's TB * 16 columns of S staged in LDS
+// (zero past k and k2) and read from there by every wave, where k_tsmm
+// re-reads them from L2 for each 16-row strip.  A workgroup of 8 waves
+// takes RW blocks of 128 rows (16 per wave) in turn; a wave loads its A
+// fragments 8 k-steps at a time, all issued together through a buffer
+// descriptor over its 16 rows (a row past n reads zero; a column past k
+// reads column k - 1, which meets a zero row of S), then issues the MFMAs.
+constexpr int kTsmmThreads = 512;
+constexpr int kTsmmRW = 4;
+constexpr int kTsmmMaxLds = 128 * 1024;
+
+template <int TB>
+__global__ __launch_bounds__(kTsmmThreads) void k_tsmm_lds(int64_t n, int k, int k2,
+                                                           const double* __restrict__ X, int ldx,
+                                                           const double* __restrict__ S, int lds,
+                                                           double* __restrict__ Y, int ldy) {
+  extern __shared__ double sl[];  // kp x (16 TB), row-major
+  constexpr int SC = 16 * TB;
+  const int kp = (k + 3) & ~3;
+  const int tb0 = blockIdx.y * TB;
+  for (int e = threadIdx.x; e < kp * SC; e += kTsmmThreads) {
+    const int a = e / SC, gc = tb0 * 16 + e % SC;
+    sl[e] = (a < k && gc < k2) ? S[(size_t)a * lds + gc] : 0.0;
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nsteps = kp >> 2;
+  constexpr int KB = 8;  // k-steps per batch of A loads
+  for (int rb = 0; rb < kTsmmRW; ++rb) {
+    const int64_t r0 = (((int64_t)blockIdx.x * kTsmmRW + rb) * (kTsmmThreads / 64) + wave) * 16;
+    if (r0 >= n) break;  // wave-uniform
+    const int rows = (int)min<int64_t>(16, n - r0);
+    const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(X + r0 * ldx), (short)0, rows * ldx * 8, kBufferWord3);
+    v4d acc[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < nsteps; s0 += KB) {
+      double a[KB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int col = min(4 * (s0 + u) + lk, k - 1);
+        a[u] = __builtin_bit_cast(double,
+                                  __builtin_amdgcn_raw_buffer_load_b64(xs, (li * ldx + col) * 8, 0, 0));
+      }
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        // steps past kp meet rows of sl that do not exist: skip them (uniform)
+        if (s0 + u >= nsteps) break;
+        const double* srow = sl + (4 * (s0 + u) + lk) * SC + li;
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], srow[16 * t], acc[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      const int c = (tb0 + t) * 16 + li;
+      if (c >= k2) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + lk + 4 * v;
+        if (r < n) Y[r * ldy + c] = acc[t][v];
+      }
+    }
+  }
+}
+
 hipError_t launch_tsmm(hipStream_t st, int64_t n, int k, int k2, const double* X, int ldx,
                        const double* S, int lds, double* Y, int ldy) {
   if (n <= 0 || k2 <= 0) return hipSuccess;
   const int tb_n = (k2 + 15) / 16;
   // one wave covers up to six column tiles, so X is read once for k2 <= 96
   constexpr int TB = 6;
+  const size_t lds_bytes = (size_t)((k + 3) & ~3) * 16 * TB * sizeof(double);
+  if (k >= 1 && lds_bytes <= (size_t)kTsmmMaxLds && n >= 4096) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_tsmm_lds<TB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    const int64_t rows_per_wg = (int64_t)kTsmmRW * (kTsmmThreads / 64) * 16;
+    dim3 grid((unsigned)((n + rows_per_wg - 1) / rows_per_wg), (tb_n + TB - 1) / TB);
+    hipLaunchKernelGGL(k_tsmm_lds<TB>, grid, dim3(kTsmmThreads), lds_bytes, st, n, k, k2, X, ldx,
+                       S, lds, Y, ldy);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((n + 63) / 64), (tb_n + TB - 1) / TB);
   hipLaunchKernelGGL(k_tsmm<TB>, grid, dim3(256), 0, st, n, k, k2, X, ldx, S, lds, Y, ldy);
   return hipGetLastError();
