@@ -362,7 +362,7 @@ size_t gram_partial_doubles(int64_t n, int k1, int k2) {
 
 // A workgroup owns a TA x TB block of 16 x 16 output tiles of one row chunk;
 // its 4 waves split the chunk's rows (wave w takes batches w, w + 4, ...)
-// and add their partial blocks through LDS in wave order.  Per 4-row step a
+// and add their partial blocks through LDS in a fixed order.  Per 4-row step a
 // wave loads TA + TB operand fragments and issues TA * TB MFMAs on them.
 // Rows go in batches of U steps (4 U rows) whose loads are issued together,
 // unconditionally (a column past k reads column k - 1, which only feeds rows
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k1, int k2,
                                                       double* __restrict__ part,
                                                       int64_t rows_per_chunk) {
   constexpr int kBlockVals = TA * TB * 256;  // one wave's partial block
-  __shared__ double sh[4 * kBlockVals];
+  __shared__ double sh[2 * kBlockVals];
   const int chunk = blockIdx.x;
   const int64_t r_begin = (int64_t)chunk * rows_per_chunk;
   int64_t r_end = r_begin + rows_per_chunk;
@@ -435,31 +435,52 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k1, int k2,
         for (int j = 0; j < TB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][i], b[u][j], acc[i][j], 0, 0, 0);
   }
-  // the 4 waves' blocks, summed in wave order; element (i, j, v, l) of a
-  // block is D[l / 16 + 4 v][l % 16] of tile (i, j)
+  // the 4 waves' blocks summed in a fixed order, (w0 + w2) + (w1 + w3), in
+  // two rounds through half the LDS; element (i, j, v, l) of a block is
+  // D[l / 16 + 4 v][l % 16] of tile (i, j)
+  auto idx = [&](int i, int j, int v) { return ((i * TB + j) * 4 + v) * 64 + lane; };
+  if (wave >= 2) {
 #pragma unroll
-  for (int i = 0; i < TA; ++i)
+    for (int i = 0; i < TA; ++i)
 #pragma unroll
-    for (int j = 0; j < TB; ++j)
+      for (int j = 0; j < TB; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        sh[wave * kBlockVals + ((i * TB + j) * 4 + v) * 64 + lane] = acc[i][j][v];
+        for (int v = 0; v < 4; ++v) sh[(wave - 2) * kBlockVals + idx(i, j, v)] = acc[i][j][v];
+  }
   __syncthreads();
-  double* P = part + (size_t)chunk * k1 * k2;
-  for (int e = threadIdx.x; e < kBlockVals; e += 256) {
-    const int l = e & 63, v = (e >> 6) & 3, t = e >> 8;
-    const int i = t / TB, j = t % TB;
-    const int gi = (ta0 + i) * 16 + (l >> 4) + 4 * v;
-    const int gj = (tb0 + j) * 16 + (l & 15);
-    if (gi < k1 && gj < k2)
-      P[(size_t)gi * k2 + gj] =
-          ((sh[e] + sh[kBlockVals + e]) + sh[2 * kBlockVals + e]) + sh[3 * kBlockVals + e];
+  if (wave < 2) {
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] += sh[wave * kBlockVals + idx(i, j, v)];
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sh[idx(i, j, v)] = acc[i][j][v];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double* P = part + (size_t)chunk * k1 * k2;
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = (ta0 + i) * 16 + lk + 4 * v;
+          const int gj = (tb0 + j) * 16 + li;
+          if (gi < k1 && gj < k2) P[(size_t)gi * k2 + gj] = acc[i][j][v] + sh[idx(i, j, v)];
+        }
   }
 }
 
-// G = the sum of the chunks' partial Grams: a workgroup takes 64 consecutive
-// elements, wave w sums the w-th quarter of the chunks for them (coalesced
-// across the lanes), and the four quarter sums are added in wave order.
 __global__ __launch_bounds__(256) void k_gram_reduce(int chunks, int k1, int k2,
                                                      const double* __restrict__ part,
                                                      double* __restrict__ G, int ldg) {
