@@ -660,7 +660,9 @@ hipError_t launch_tsmm(hipStream_t st, int64_t n, int k, int k2, const double* X
   // one wave covers up to six column tiles, so X is read once for k2 <= 96
   constexpr int TB = 6;
   const size_t lds_bytes = (size_t)((k + 3) & ~3) * 16 * TB * sizeof(double);
-  if (k >= 1 && lds_bytes <= (size_t)kTsmmMaxLds && n >= 4096) {
+  // staging S pays once there are enough rows to give every CU a workgroup
+  // of 512 rows; below that the per-strip kernel spreads wider
+  if (k >= 1 && lds_bytes <= (size_t)kTsmmMaxLds && n >= (int64_t)1 << 17) {
     hipError_t e = hipFuncSetAttribute((const void*)k_tsmm_lds<TB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
