@@ -96,8 +96,11 @@ def test_spmm_column_groups(gpu_lib, torch_dev):
         plan.close()
 
 
+# the last three have n >= 2^17, where the TSMM stages S in LDS (ragged
+# row count; k not a multiple of 4; 113 KiB of S)
 @pytest.mark.parametrize("n,k,cond", [(5000, 64, 1e2), (5000, 64, 1e10), (999, 37, 1e6),
-                                      (20000, 148, 1e4), (300, 1, 1.0)])
+                                      (20000, 148, 1e4), (300, 1, 1.0), (131077, 84, 1e4),
+                                      (140001, 37, 1e6), (131113, 148, 1e2)])
 def test_cholqr2(small_plan, torch_dev, n, k, cond):
     torch = torch_dev
     _, plan = small_plan
