@@ -513,6 +513,8 @@ hipError_t launch_gram_chunks(hipStream_t st, int64_t n, int k1, int k2, const d
   if (chunks > gram_chunks(n)) chunks = gram_chunks(n);
   int64_t rpc = (n + chunks - 1) / chunks;
   rpc = (rpc + 3) & ~int64_t(3);
+  // a chunk's rows are addressed through 32-bit buffer offsets
+  if (rpc * (int64_t)(ldx > ldy ? ldx : ldy) * 8 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
   const int ta_n = (k1 + 15) / 16, tb_n = (k2 + 15) / 16;
   // one workgroup per tile block and chunk: 3 x 3 blocks when that still
   // gives twelve or more per chunk, else 2 x 2
