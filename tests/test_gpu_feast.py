@@ -220,7 +220,7 @@ def test_knn8000_parity(gpu_lib, nc, ws_op, engine, relaxed):
     assert sin_theta(X, ref["X"]).max() <= max(1e-8, 2 * np.linalg.norm(R) / gap)
 
 
-@pytest.mark.parametrize("engine", ["auto", "stream"])
+@pytest.mark.parametrize("engine", ["auto", "stream", "multishift"])
 @pytest.mark.parametrize("relaxed", [1e-2, 0.5])
 def test_relaxed_phase2_solves(gpu_lib, engine, relaxed):
     # Phase 2 with relaxed solves (Section 3.3; Theorem 2): the eigenpairs
@@ -234,11 +234,14 @@ def test_relaxed_phase2_solves(gpu_lib, engine, relaxed):
     vals, V = window_basis(dims, shift, lmin, lmax)
     allv, _ = grid_eigs(dims, shift)
     om = gaussian(csr.n, 40, 0)
+    # the multi-shift engine computes in FP64 only
+    prec = "fp64" if engine == "multishift" else "fp32"
     with gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10, tol_solve_relaxed=relaxed,
-                      engine=engine) as plan:
+                      engine=engine, precision=prec) as plan:
         plan.warmstart(omega=om)
         out = plan.solve()
-    with gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10, engine=engine) as plan:
+    with gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10, engine=engine,
+                      precision=prec) as plan:
         plan.warmstart(omega=om)
         fixed = plan.solve()
     assert out["status"] == "OK"
