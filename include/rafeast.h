@@ -309,7 +309,10 @@ int32_t rafeast_plan_engine(rafeast_plan_t plan);
  * from the smallest that fits up to the maximum timed on the plan's own
  * matrix (64 COCG iterations of the first min(systems, CUs) systems on
  * Gaussian right-hand sides); the fastest is used.  RAFEAST_TUNE=0 in the
- * environment keeps the smallest.  Out: *chosen (0 for the streaming engine,
+ * environment keeps the smallest; RAFEAST_RESIDENT_SLOTS=r takes candidate r
+ * untimed (rafeast_plan fails with INVALID_ARG if r is not a candidate).  The
+ * count sets the order of the SpMV's row sums, so plans with equal counts
+ * give bitwise equal results.  Out: *chosen (0 for the streaming engine,
  * which is not tuned), *count candidates, and up to max of them in cand[]
  * with their measured milliseconds in ms[] (0 when untimed: a single
  * candidate or tuning off).  Host pointers owned by the caller.  Errors:

@@ -205,11 +205,16 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
     int max_npad) {
   // Dynamic LDS only (so p starts at address 0 and a gather address is the
   // entry's stored byte offset): p | r (sized for the graph of the current
-  // item) ... reduction slots | work item (after room for the largest graph).
+  // item) ... | zero row | trash row | reduction slots | work item (after
+  // room for the largest graph).  The vector loops read every slot
+  // unconditionally, so that a wave issues all its LDS loads before the
+  // first wait: a slot past the wave's last slice reads the zero row (its
+  // terms are exact zeros) and writes the trash row, which nothing reads.
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* P = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int zoff = 2 * max_npad, toff = zoff + 64;
   double(*red)[kResWaves][4] = reinterpret_cast<double(*)[kResWaves][4]>(
-      smem_raw + (size_t)max_npad * 2 * sizeof(cpx<T>));
+      smem_raw + ((size_t)max_npad * 2 + 128) * sizeof(cpx<T>));
   int& s_item = *reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(red) +
                                         2 * kResWaves * 4 * sizeof(double));
   const int tid = threadIdx.x;
@@ -281,6 +286,7 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
   }
 
   cpx<T> w[RPT], xr[RPT];
+  if (tid < 64) P[zoff + tid] = cpx<T>{T(0), T(0)};  // ordered by the loop's first barrier
 
   for (;;) {
     if (tid == 0) s_item = atomicAdd(counter, 1);
@@ -321,6 +327,8 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
         iters[ocol] = 0;
         if (resid_out) resid_out[ocol] = 0.0;
       }
+      // see the barrier that ends an item
+      __syncthreads();
       continue;
     }
     const double scale = 1.0 / sqrt(bn2);
@@ -483,16 +491,18 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       }
       T mu_t[2] = {T(0), T(0)};
       const T zrt = T(zr), zit = T(zi);
+      // this thread's p and r stay in registers until the p update (p is
+      // not written before it, r only by this thread's own update)
+      cpx<T> pv[RPT], rv[RPT];
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) pv[t] = P[(slc[t] >= 0 ? slc[t] * 64 : zoff) + ln];
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        const int slice = slc[t];
-        if (slice >= 0) {
-          const cpx<T> pr = P[slice * 64 + ln];
-          w[t].re = zrt * pr.re - zit * pr.im - acc_re[t];
-          w[t].im = zrt * pr.im + zit * pr.re - acc_im[t];
-          mu_t[0] += pr.re * w[t].re - pr.im * w[t].im;
-          mu_t[1] += pr.re * w[t].im + pr.im * w[t].re;
-        }
+        // an empty slot has p = 0 and no entries: w = 0, no term
+        w[t].re = zrt * pv[t].re - zit * pv[t].im - acc_re[t];
+        w[t].im = zrt * pv[t].im + zit * pv[t].re - acc_im[t];
+        mu_t[0] += pv[t].re * w[t].re - pv[t].im * w[t].im;
+        mu_t[1] += pv[t].re * w[t].im + pv[t].im * w[t].re;
       }
       double mo[4];
       block_sum_fin<2, 4>(mu_t, mo, red, 0, [&](const double* t, double* r) {
@@ -512,22 +522,20 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
         // ---- x += alpha p, r -= alpha w, rho' = r^T r, ||r||^2 ----
         T s3_t[3] = {T(0), T(0), T(0)};
         const T alr = T(alpha.re), ali = T(alpha.im);
+        const int roff = (int)(R - P);
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) rv[t] = P[(slc[t] >= 0 ? roff + slc[t] * 64 : zoff) + ln];
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
-          const int slice = slc[t];
-          if (slice >= 0) {
-            const int s = slice * 64 + ln;
-            const cpx<T> pr = P[s];
-            xr[t].re += alr * pr.re - ali * pr.im;
-            xr[t].im += alr * pr.im + ali * pr.re;
-            cpx<T> rv = R[s];
-            rv.re -= alr * w[t].re - ali * w[t].im;
-            rv.im -= alr * w[t].im + ali * w[t].re;
-            R[s] = rv;
-            s3_t[0] += rv.re * rv.re - rv.im * rv.im;
-            s3_t[1] += T(2) * rv.re * rv.im;
-            s3_t[2] += rv.re * rv.re + rv.im * rv.im;
-          }
+          // empty slots: p = w = r = 0, so x stays 0 and no term is added
+          xr[t].re += alr * pv[t].re - ali * pv[t].im;
+          xr[t].im += alr * pv[t].im + ali * pv[t].re;
+          rv[t].re -= alr * w[t].re - ali * w[t].im;
+          rv[t].im -= alr * w[t].im + ali * w[t].re;
+          P[(slc[t] >= 0 ? roff + slc[t] * 64 : toff) + ln] = rv[t];
+          s3_t[0] += rv[t].re * rv[t].re - rv[t].im * rv[t].im;
+          s3_t[1] += T(2) * rv[t].re * rv[t].im;
+          s3_t[2] += rv[t].re * rv[t].re + rv[t].im * rv[t].im;
         }
         double so[5];
         block_sum_fin<3, 5>(s3_t, so, red, 1, [&](const double* t, double* r) {
@@ -550,15 +558,10 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
           rho_im = s3[1];
           const T br = T(beta.re), bi = T(beta.im);
 #pragma unroll
-          for (int t = 0; t < RPT; ++t) {
-            const int slice = slc[t];
-            if (slice >= 0) {
-              const int s = slice * 64 + ln;
-              const cpx<T> pr = P[s];
-              const cpx<T> rv = R[s];
-              P[s] = cpx<T>{rv.re + br * pr.re - bi * pr.im, rv.im + br * pr.im + bi * pr.re};
-            }
-          }
+          for (int t = 0; t < RPT; ++t)
+            P[(slc[t] >= 0 ? slc[t] * 64 : toff) + ln] =
+                cpx<T>{rv[t].re + br * pv[t].re - bi * pv[t].im,
+                       rv[t].im + br * pv[t].im + bi * pv[t].re};
           __syncthreads();
         }
       }
@@ -658,6 +661,11 @@ __global__ __launch_bounds__(kResThreads) void k_cocg_resident(
       if (nref) atomicAdd(&stats[0], nref);
       if (nbd > 3) atomicAdd(&stats[1], 1);
     }
+    // A barrier between this thread-0 block and the thread-0 fetch of the
+    // next item: without it the compiler may merge the two blocks and send
+    // the other threads straight to the fetch's barrier, where they would
+    // read the old item again while thread 0 still waits to run.
+    __syncthreads();
   }
 }
 
@@ -710,7 +718,8 @@ std::vector<int> cocg_resident_wave_table(const std::vector<int>& widths, int rp
 
 size_t cocg_resident_lds(int n, bool fp32) {
   const size_t nsl = (size_t)(n + 63) / 64;
-  return nsl * 64 * 2 * (fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>)) +
+  // p and r, the zero and trash rows, the reduction slots, the work item
+  return (nsl * 64 * 2 + 128) * (fp32 ? sizeof(cpx<float>) : sizeof(cpx<double>)) +
          2 * kResWaves * 4 * sizeof(double) + 16;
 }
 

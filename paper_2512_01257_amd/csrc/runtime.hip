@@ -1488,7 +1488,10 @@ void rafeast_destroy(rafeast_plan_t plan) { free_plan(plan); }
 // systems of the solve order (the hardest shift first) on Gaussian
 // right-hand sides, run for a fixed 64 iterations (tolerance 0), one untimed
 // launch and then the best of two timed ones; the fastest count wins (ties
-// to fewer slots).  RAFEAST_TUNE=0 keeps the smallest count.
+// to fewer slots).  RAFEAST_TUNE=0 keeps the smallest count;
+// RAFEAST_RESIDENT_SLOTS=r takes candidate r untimed (plan creation fails if
+// r is not a candidate), so that two plans can be given the same layout and
+// hence the same summation order.
 rafeast_status tune_resident(rafeast_plan_s* P) {
   const int maxr = P->fp32 ? 8 : 4;
   std::vector<std::vector<int>> tabs;
@@ -1501,6 +1504,20 @@ rafeast_status tune_resident(rafeast_plan_s* P) {
   }
   P->tune_ms.assign(P->tune_cand.size(), 0.0f);
   P->tune_choice = P->sell.wave_rpt;
+  if (const char* forced = std::getenv("RAFEAST_RESIDENT_SLOTS")) {
+    size_t c = 0;
+    while (c < P->tune_cand.size() && std::to_string(P->tune_cand[c]) != forced) ++c;
+    if (c == P->tune_cand.size())
+      return fail(P, RAFEAST_INVALID_ARG,
+                  std::string("RAFEAST_RESIDENT_SLOTS=") + forced +
+                      " is not a slot count this matrix can use");
+    HIPCHK(P, hipMemcpyAsync(P->d_wtab, tabs[c].data(), tabs[c].size() * sizeof(int),
+                             hipMemcpyHostToDevice, P->st));
+    HIPCHK(P, hipStreamSynchronize(P->st));
+    P->tune_choice = P->tune_cand[c];
+    P->sell.wave_rpt = P->tune_choice;
+    return RAFEAST_OK;
+  }
   const char* env = std::getenv("RAFEAST_TUNE");
   if (P->tune_cand.size() < 2 || (env && std::strcmp(env, "0") == 0)) return RAFEAST_OK;
   const int m0 = P->m0, ld = P->ld;

@@ -59,7 +59,7 @@ RELAXED = [0.5, 1e-2, 1e-2, 0.0, 0.5, 1e-2]
 
 
 @pytest.mark.parametrize("precision,relaxed", [("fp32", False), ("fp64", False), ("fp32", True)])
-def test_batch_parity(gpu_lib, precision, relaxed):
+def test_batch_parity(gpu_lib, precision, relaxed, monkeypatch):
     members = _members()
     rel = RELAXED if relaxed else [0.0] * len(members)
     probs = [{k: m[k] for k in ("csr", "lmin", "lmax", "m0")} for m in members]
@@ -70,6 +70,9 @@ def test_batch_parity(gpu_lib, precision, relaxed):
         # the 100 x 100 grid is too large for the shared launch: multi-shift, FP64
         engines = [m.engine for m in B.members]
         assert engines == ["resident", "multishift"] + ["resident"] * 4
+        # the shared launch gives every resident member the largest slot
+        # count the members' own tunings chose
+        slots = max(m.tuning["chosen"] for m in B.members if m.engine == "resident")
         for g, m in enumerate(B.members):
             m.warmstart(omega=gaussian(m.n, m.w, g))
         outs, t_ms, status = B.solve()
@@ -86,8 +89,10 @@ def test_batch_parity(gpu_lib, precision, relaxed):
         assert (np.linalg.norm(R, axis=0) / s_win).max() <= 1.0001e-10, g
         assert np.abs(X.T @ X - np.eye(X.shape[1])).max() < 1e-12, g
         assert sin_theta(X, V_ref).max() <= max(1e-8, 2 * np.linalg.norm(R) / gap), g
-    # each member alone, on the eager single-plan path: same iteration counts,
-    # same eigenvalues
+    # each member alone, on the eager single-plan path with the slot layout it
+    # had in the shared launch (so the same summation order): same iteration
+    # counts, same eigenvalues
+    monkeypatch.setenv("RAFEAST_RESIDENT_SLOTS", str(slots))
     for g, (m, out) in enumerate(zip(members, outs)):
         ms = engines[g] == "multishift"
         with gpu_lib.Plan(m["csr"], m["lmin"], m["lmax"], m["m0"], nc=4, q=2, p=10,

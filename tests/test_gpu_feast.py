@@ -305,5 +305,18 @@ def test_resident_autotune(gpu_lib, monkeypatch):
         np.testing.assert_allclose(out["lam"], vals, atol=1e-10 * lmax)
         lam[tune] = out["lam"]
     np.testing.assert_allclose(lam["1"], lam["0"], atol=1e-10 * lmax)
+    # a forced count is taken untimed; one that is not a candidate is refused
+    monkeypatch.delenv("RAFEAST_TUNE")
+    monkeypatch.setenv("RAFEAST_RESIDENT_SLOTS", str(cands[-1]))
+    with gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10) as plan:
+        t = plan.tuning
+        assert t["chosen"] == cands[-1] and all(ms == 0 for _, ms in t["candidates"])
+        plan.warmstart(omega=gaussian(csr.n, plan.w, 0))
+        out = plan.solve(want_vectors=False)
+    np.testing.assert_allclose(out["lam"], vals, atol=1e-10 * lmax)
+    monkeypatch.setenv("RAFEAST_RESIDENT_SLOTS", "3")
+    with pytest.raises(gpu_lib.RafeastError, match="RAFEAST_RESIDENT_SLOTS"):
+        gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10)
+    monkeypatch.delenv("RAFEAST_RESIDENT_SLOTS")
     with gpu_lib.Plan(csr, lmin, lmax, 30, nc=4, q=2, p=10, engine="stream") as plan:
         assert plan.tuning == dict(chosen=0, candidates=[])
