@@ -48,23 +48,65 @@ namespace rafeast {
 constexpr int kResThreads = 1024;
 constexpr int kResWaves = kResThreads / 64;
 
+// Sums of values over the 16 lanes of row 0, read from lane 0: the DPP
+// steps of wave_sum_f64 stay inside a row of 16 lanes, so rows 1 to 3 (which
+// the callers fill with copies) take no part.
+template <int NV>
+__device__ __forceinline__ void row0_sums_f64(double (&v)[NV]) {
+  // step by step over all values, so that the NV chains interleave
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += dpp_f64(v[q], c);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = readlane_f64(v[q], 0);
+}
+static_assert(kResWaves == 16, "wave 0 sums the per-wave partials over one 16-lane row");
+
+// wave_sum_f32 / wave_sum_f64 of NV values at once, step by step over all
+// values so that the chains interleave (each value's arithmetic unchanged)
+template <int NV, typename A>
+__device__ __forceinline__ void wave_sums(const A (&part)[NV], double (&ws)[NV]) {
+  A v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = part[q];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      if constexpr (sizeof(A) == 4)
+        v[q] += dpp_f32(v[q], c);
+      else
+        v[q] += dpp_f64(v[q], c);
+    }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if constexpr (sizeof(A) == 4) {
+      const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[q]), 0));
+      const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[q]), 16));
+      const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[q]), 32));
+      const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[q]), 48));
+      ws[q] = (double)((r0 + r1) + (r2 + r3));
+    } else {
+      ws[q] = (readlane_f64(v[q], 0) + readlane_f64(v[q], 16)) +
+              (readlane_f64(v[q], 32) + readlane_f64(v[q], 48));
+    }
+  }
+}
+
 // Workgroup sum of NV values given per-thread partials of type A (float or
 // double): DPP wave sums (no LDS), one LDS slot per wave, a barrier, then
 // wave 0 adds the kResWaves wave sums in FP64 (fixed order) and publishes the
 // totals in LDS for a second barrier.  One wave finishing the sum, instead of
-// every wave repeating it, frees the SIMDs for the other waves' work.
+// every wave repeating it, frees the SIMDs for the other waves' work.  Wave
+// 0 reads all NV slots unconditionally (lane l reads wave l mod 16's), so
+// the reads are in flight together.
 template <int NV, typename A>
 __device__ __forceinline__ void block_sum(const A (&part)[NV], double (&v)[NV],
                                           double (*red)[kResWaves][4], int set) {
   const int wv = threadIdx.x >> 6;
   double ws[NV];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    if constexpr (sizeof(A) == 4)
-      ws[q] = (double)wave_sum_f32(part[q]);
-    else
-      ws[q] = wave_sum_f64(part[q]);
-  }
+  wave_sums(part, ws);
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) red[set][wv][q] = ws[q];
@@ -76,12 +118,12 @@ __device__ __forceinline__ void block_sum(const A (&part)[NV], double (&v)[NV],
   // the next call on the same set writes its partials.
   const int ln = threadIdx.x & 63;
   if (wv == 0) {
-    double t[NV];
+    double x[NV], t[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const double x = ln < kResWaves ? red[set][ln][q] : 0.0;
-      t[q] = wave_sum_f64(x);
-    }
+    for (int q = 0; q < NV; ++q) x[q] = red[set][ln & (kResWaves - 1)][q];
+    row0_sums_f64(x);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) t[q] = x[q];
     if (ln == 0) {
 #pragma unroll
       for (int q = 0; q < NV; ++q) red[set][0][q] = t[q];
@@ -99,13 +141,7 @@ __device__ __forceinline__ void block_sum_fin(const A (&part)[NV], double (&o)[N
                                               double (*red)[kResWaves][4], int set, F fin) {
   const int wv = threadIdx.x >> 6;
   double ws[NV];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    if constexpr (sizeof(A) == 4)
-      ws[q] = (double)wave_sum_f32(part[q]);
-    else
-      ws[q] = wave_sum_f64(part[q]);
-  }
+  wave_sums(part, ws);
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) red[set][wv][q] = ws[q];
@@ -114,12 +150,12 @@ __device__ __forceinline__ void block_sum_fin(const A (&part)[NV], double (&o)[N
   const int ln = threadIdx.x & 63;
   double* flat = &red[set][0][0];
   if (wv == 0) {
-    double t[NV], r[NO];
+    double x[NV], t[NV], r[NO];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const double x = ln < kResWaves ? red[set][ln][q] : 0.0;
-      t[q] = wave_sum_f64(x);
-    }
+    for (int q = 0; q < NV; ++q) x[q] = red[set][ln & (kResWaves - 1)][q];
+    row0_sums_f64(x);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) t[q] = x[q];
     fin(t, r);
     if (ln == 0) {
 #pragma unroll
