@@ -818,6 +818,9 @@ def main():
                     help="starting COCG tolerance of the relaxed Phase-2 figures (0: skip)")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
                     help="stats: COCG precision (complex FP32 with FP64 reliable updates, or FP64)")
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="headline: RA-FEAST steps timed with FP64 solves on the streaming and "
+                         "the multi-shift engine (0: skip)")
     ap.add_argument("--relaxed-phase2", action="store_true",
                     help="grid64, batch32, rgg (RA configurations only): relaxed Phase-2 solves "
                          "starting at --relaxed")
@@ -1023,6 +1026,36 @@ def main():
                 relaxed["ra"]["value"] / relaxed["plain"]["value"], 3)
             relaxed["speedup_vs_plain_fixed_tol"] = round(relaxed["ra"]["value"] / plain_value, 3)
 
+    # The same RA-FEAST steps with FP64 solves.  The FP64 resident engine
+    # holds at most 4096 rows, so at n = 8000 FP64 runs on the streaming or
+    # the multi-shift engine: what the complex-FP32 form with FP64 reliable
+    # updates gains over the faster of them, at the same eigenpair target.
+    fp64 = None
+    if args.fp64_steps > 0:
+        def fp64_run(engine, steps):
+            pl = native.Plan(csr, lmin, lmax, m0, nc=w["nc_ra"], q=w["q"], p=w["p"],
+                             tol_eig=w["tol_eig"], tol_solve=w["tol_solve"], precision="fp64",
+                             ws_op="auto", seed=0, engine=engine)
+            run_steps(pl, 1, lam, res, X, warmstart=True)
+            s_, r_ = run_steps(pl, steps, lam, res, X, warmstart=True)
+            eng = pl.engine
+            pl.close()
+            for _, o in r_:
+                if o["status"] != "OK" or o["M"] != win["count"]:
+                    raise RuntimeError(f"FP64-solve step ({engine}) did not converge: {o}")
+            e_ = float(np.abs(lam.cpu().numpy()[: win["count"]] - ev).max())
+            if e_ > 1e-10 * lmax:
+                raise RuntimeError(f"FP64-solve eigenvalue error {e_:.3e} above 1e-10 * s_win")
+            o = r_[-1][1]
+            return dict(engine=eng, value=round(sum(x["M"] for _, x in r_) / s_, 3),
+                        ms_per_step=round(s_ / steps * 1e3, 4), feast_iters=o["iters"],
+                        cocg_iters=int(o["cocg_iters"]), max_eig_error_vs_reference=e_)
+        log(f"timing {args.fp64_steps} RA-FEAST step(s) with FP64 solves on each FP64 engine")
+        fp64 = dict(stream=fp64_run("stream", args.fp64_steps),
+                    multishift=fp64_run("multishift", args.fp64_steps))
+        best = max(fp64["stream"]["value"], fp64["multishift"]["value"])
+        fp64["fp32_speedup_over_best_fp64"] = round(value / best, 3)
+
     # dominant kernel: the resident COCG engine (one launch per FEAST
     # iteration), timed by the library with HIP events on its own stream.  It
     # keeps every vector of a system in one CU's LDS and registers, so what
@@ -1094,6 +1127,7 @@ def main():
         "speedup_vs_plain_exact_solves": None if exact is None else round(
             value / exact["value"], 3),
         "relaxed_phase2": relaxed,
+        "fp64_solves": fp64,
         "plan_ms": round(plan_ms, 2),
         "ra_phase_ms_per_step": phases,
         "feast_iters_per_step": round(sum(o["iters"] for _, o in recs) / args.steps, 2),
