@@ -16,6 +16,19 @@ __device__ __forceinline__ int packed_index(int k, int i, int j) {  // i <= j
   return i * k - (i * (i - 1)) / 2 + (j - i);
 }
 
+// Sum over an aligned group of 2^lg lanes (lg = 2, 3 or 4, inside a 16-lane
+// row), in every lane of the group: the butterfly over lanes l ^ 1, l ^ 2,
+// l ^ 4, l ^ 8 as DPP steps.  After the first two steps all lanes of a quad
+// hold the same value, so the half-row and row mirrors fetch the values the
+// l ^ 4 and l ^ 8 partners hold, and each sum is formed as in the butterfly.
+__device__ __forceinline__ double group_sum_f64(double v, int lg) {
+  v += dpp_f64(v, 0);
+  v += dpp_f64(v, 1);
+  if (lg >= 3) v += dpp_f64(v, 2);
+  if (lg >= 4) v += dpp_f64(v, 3);
+  return v;
+}
+
 // ============================================================================
 // CholQR factor.  LDS: dsc[k] (column scales) | U (packed upper, k(k+1)/2)
 // [| X = U^{-1} (packed upper) when kXInLds].  Right-looking Cholesky with
@@ -123,7 +136,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_inv(int k, double shift_
         for (int t = i + qd; t < j; t += L)
           part += X[packed_index(k, i, t)] * U[packed_index(k, t, j)];
       }
-      for (int o = 1; o < L; o <<= 1) part += __shfl_xor(part, o, 64);
+      part = group_sum_f64(part, lg);
       if (i < j && qd == 0) X[packed_index(k, i, j)] = -part / ujj;
       if (tid == kSmallThreads - 1) X[packed_index(k, j, j)] = 1.0 / ujj;
       __syncthreads();
@@ -144,7 +157,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_inv(int k, double shift_
         for (int t = i + qd; t < j; t += L)
           part += M[(size_t)i * ldm + t] * U[packed_index(k, t, j)];
       }
-      for (int o = 1; o < L; o <<= 1) part += __shfl_xor(part, o, 64);
+      part = group_sum_f64(part, lg);
       if (i < j && qd == 0) M[(size_t)i * ldm + j] = -part / ujj;
       if (tid == kSmallThreads - 1) M[(size_t)j * ldm + j] = 1.0 / ujj;
       __syncthreads();
