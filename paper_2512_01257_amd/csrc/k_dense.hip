@@ -882,19 +882,20 @@ hipError_t launch_colmajor_to_rowmajor(hipStream_t st, int64_t n, int k, const d
 }
 
 __global__ void k_copy_cols(int64_t n, int k, const double* __restrict__ src, int lds,
-                            double* __restrict__ dst, int ldd) {
+                            double* __restrict__ dst, int ldd, const int* __restrict__ status) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * k) return;
+  if (status && *status == 2) return;  // a failed factorization: dst keeps its values
   const int64_t r = e / k;
   const int c = (int)(e % k);
   dst[r * ldd + c] = src[r * lds + c];
 }
 
 hipError_t launch_copy_cols(hipStream_t st, int64_t n, int k, const double* src, int lds,
-                            double* dst, int ldd) {
+                            double* dst, int ldd, const int* status) {
   const int64_t tot = n * k;
   hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, k,
-                     src, lds, dst, ldd);
+                     src, lds, dst, ldd, status);
   return hipGetLastError();
 }
 

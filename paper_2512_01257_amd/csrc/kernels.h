@@ -68,8 +68,10 @@ hipError_t launch_colmajor_to_rowmajor(hipStream_t st, int64_t n, int k, const d
 // `part` holds 3 * cnt * gram_chunks(n) doubles + cnt ints of scratch.
 hipError_t launch_export_vectors(hipStream_t st, int64_t n, int cnt, const int* sel,
                                  const double* src, int lds, double* dst, double* part);
+// dst[:, 0..k) = src[:, 0..k); with status, nothing is written when *status
+// is 2 (the failed Cholesky of a CholQR pass).
 hipError_t launch_copy_cols(hipStream_t st, int64_t n, int k, const double* src, int lds,
-                            double* dst, int ldd);
+                            double* dst, int ldd, const int* status = nullptr);
 // p[0..n) = v by a kernel (usable inside a captured graph, unlike a memset).
 hipError_t launch_fill_int(hipStream_t st, int* p, int v, int n);
 

@@ -93,7 +93,7 @@ struct rafeast_plan_s {
   int* d_counter = nullptr;  // 1
   int* d_iters = nullptr;    // nc m0
   int* d_stats = nullptr;    // 2
-  int* d_flag = nullptr;     // 1
+  int* d_flag = nullptr;     // 3: one Cholesky status per CholQR pass
   int* d_sel = nullptr;      // m0
   void* d_xhi = nullptr;     // FP64 solution scratch of the resident COCG engine
   size_t xhi_slots = 0;
@@ -763,22 +763,19 @@ rafeast_status spmm(rafeast_plan_s* P, int k, const double* X, int ldx, double* 
 // CholQR2 on Y (n x k, ld) in place through P->d_T; *info as in rafeast_cholqr2.
 // With track (k = m0), the product of the passes' transforms is formed on the
 // device in d_mtot (pass 0 copies M, later passes multiply it on the right).
+// A pass whose factorization failed writes nothing back to Y (the copy reads
+// the pass's status on the device), so Y keeps the last good pass; the passes
+// therefore run back to back and their statuses are read once at the end (a
+// third pass follows when the first needed the shift).  d_mtot is not kept
+// across a failure; the callers stop, or stop using it, on one.
 rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, int* info,
                        double* tmp, int ldt, bool track = false) {
   int worst = 0;
-  int passes = 2;
+  int passes = 2, read = 0;
+  int flags[3] = {0, 0, 0};
   for (int pass = 0; pass < passes; ++pass) {
     HIPCHK(P, launch_gram(P->st, n, k, k, Y, ldy, Y, ldy, P->d_G, k, P->d_part));
-    HIPCHK(P, launch_chol_inv(P->st, k, n, P->d_G, k, P->d_M, k, P->d_flag));
-    int flag = 0;
-    HIPCHK(P, hipMemcpyAsync(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, P->st));
-    HIPCHK(P, hipStreamSynchronize(P->st));
-    if (flag == 2) {
-      if (info) *info = 2;
-      return RAFEAST_OK;  // Y (and d_mtot) keep the last good pass
-    }
-    if (flag == 1 && pass == 0) passes = 3;
-    worst = std::max(worst, flag);
+    HIPCHK(P, launch_chol_inv(P->st, k, n, P->d_G, k, P->d_M, k, P->d_flag + pass));
     if (track) {
       if (pass == 0) {
         HIPCHK(P, hipMemcpyAsync(P->d_mtot, P->d_M, (size_t)k * k * sizeof(double),
@@ -789,7 +786,21 @@ rafeast_status cholqr2(rafeast_plan_s* P, int64_t n, int k, double* Y, int ldy, 
       }
     }
     HIPCHK(P, launch_tsmm(P->st, n, k, k, Y, ldy, P->d_M, k, tmp, ldt));
-    HIPCHK(P, launch_copy_cols(P->st, n, k, tmp, ldt, Y, ldy));
+    HIPCHK(P, launch_copy_cols(P->st, n, k, tmp, ldt, Y, ldy, P->d_flag + pass));
+    if (pass == passes - 1) {
+      HIPCHK(P, hipMemcpyAsync(flags + read, P->d_flag + read, (pass + 1 - read) * sizeof(int),
+                               hipMemcpyDeviceToHost, P->st));
+      HIPCHK(P, hipStreamSynchronize(P->st));
+      for (int q = read; q <= pass; ++q) {
+        if (flags[q] == 2) {
+          if (info) *info = 2;
+          return RAFEAST_OK;  // Y keeps the last good pass
+        }
+        worst = std::max(worst, flags[q]);
+      }
+      read = pass + 1;
+      if (flags[0] == 1 && passes == 2) passes = 3;
+    }
   }
   if (info) *info = worst;
   return RAFEAST_OK;
@@ -2046,7 +2057,7 @@ static rafeast_status plan_create(const rafeast_csr* A, const DenseSpec* D,
   PRCHK(dalloc(P, &P->d_counter, 1, "counter"));
   PRCHK(dalloc(P, &P->d_iters, (size_t)P->nitems, "iters"));
   PRCHK(dalloc(P, &P->d_stats, 2, "stats"));
-  PRCHK(dalloc(P, &P->d_flag, 1, "flag"));
+  PRCHK(dalloc(P, &P->d_flag, 3, "flag"));
   PRCHK(dalloc(P, &P->d_sel, P->m0, "sel"));
   if (P->engine == RAFEAST_ENGINE_RESIDENT) {
     P->xhi_slots = cocg_resident_xhi_slots((int)n, P->num_cu);

@@ -130,6 +130,8 @@ def test_cholqr2_rank_deficient(small_plan, torch_dev):
     X[:, 7] = 0.0
     Yd = torch.from_numpy(X).cuda()
     assert plan.cholqr2(Yd) == 2
+    # a failed pass writes nothing back: Y is the input, bit for bit
+    assert np.array_equal(Yd.cpu().numpy(), X)
 
 
 # H and V in LDS up to k = 98, H alone up to 128, both in global memory above
