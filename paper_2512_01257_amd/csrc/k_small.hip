@@ -214,13 +214,16 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
   __shared__ int rp[kSmallMaxK / 2 + 1], rq[kSmallMaxK / 2 + 1], perm[kSmallMaxK];
   __shared__ double rc[kSmallMaxK / 2 + 1], rs[kSmallMaxK / 2 + 1], dg[kSmallMaxK];
   __shared__ double red[2][kSmallThreads / 64];
+  // In LDS, H and V rows are k | 1 doubles apart (an odd stride): the rows a
+  // wave touches in one access then start in different banks.
+  const int hs = kHInLds ? (k | 1) : k, vs = kVInLds ? (k | 1) : k;
   double* H = kHInLds ? sh_h : work;
-  double* V = kVInLds ? sh_h + (size_t)k * k : work + (size_t)k * k;
+  double* V = kVInLds ? sh_h + (size_t)k * hs : work + (size_t)k * k;
   const int tid = threadIdx.x;
   for (int e = tid; e < k * k; e += kSmallThreads) {
     const int i = e / k, j = e % k;
-    H[e] = 0.5 * (Hin[(size_t)i * ldh + j] + Hin[(size_t)j * ldh + i]);
-    V[e] = (i == j) ? 1.0 : 0.0;
+    H[i * hs + j] = 0.5 * (Hin[(size_t)i * ldh + j] + Hin[(size_t)j * ldh + i]);
+    V[i * vs + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int kk = k + (k & 1);
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
     double off = 0.0, tot = 0.0;
     for (int i = tid >> 5; i < k; i += kSmallThreads / 32)
       for (int j = tid & 31; j < k; j += 32) {
-        const double h = H[i * k + j];
+        const double h = H[i * hs + j];
         tot += h * h;
         if (i != j) off += h * h;
       }
@@ -267,12 +270,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
         }
         double c = 1.0, s = 0.0;
         if (p < k && q < k) {
-          const double apq = H[p * k + q];
+          const double apq = H[p * hs + q];
           if (fabs(apq) >= 0x1.0p-1000) {
             // this phase is one wave's latency per round: reciprocals and
             // square roots from Newton-refined hardware estimates (a few ulp;
             // the rotation stays orthogonal to working precision)
-            const double tau = (H[q * k + q] - H[p * k + p]) * rcp_nr(2.0 * apq);
+            const double tau = (H[q * hs + q] - H[p * hs + p]) * rcp_nr(2.0 * apq);
             double tt;
             if (fabs(tau) > 1e150) {
               tt = 0.5 / tau;
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
             c = rsq_nr(fma(tt, tt, 1.0));
             s = tt * c;
           } else if (apq != 0.0) {
-            const double tau = (H[q * k + q] - H[p * k + p]) / (2.0 * apq);
+            const double tau = (H[q * hs + q] - H[p * hs + p]) / (2.0 * apq);
             const double tt = fabs(tau) > 1e150 ? 0.5 / tau
                               : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
@@ -302,35 +305,35 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
         const int p1 = rp[t1], q1 = rq[t1], p2 = rp[t2], q2 = rq[t2];
         const double c1 = rc[t1], s1 = rs[t1], c2 = rc[t2], s2 = rs[t2];
         const bool v_p1 = p1 < k, v_q1 = q1 < k, v_p2 = p2 < k, v_q2 = q2 < k;
-        const double h00 = (v_p1 && v_p2) ? H[p1 * k + p2] : 0.0;
-        const double h01 = (v_p1 && v_q2) ? H[p1 * k + q2] : 0.0;
-        const double h10 = (v_q1 && v_p2) ? H[q1 * k + p2] : 0.0;
-        const double h11 = (v_q1 && v_q2) ? H[q1 * k + q2] : 0.0;
+        const double h00 = (v_p1 && v_p2) ? H[p1 * hs + p2] : 0.0;
+        const double h01 = (v_p1 && v_q2) ? H[p1 * hs + q2] : 0.0;
+        const double h10 = (v_q1 && v_p2) ? H[q1 * hs + p2] : 0.0;
+        const double h11 = (v_q1 && v_q2) ? H[q1 * hs + q2] : 0.0;
         // rows: J^T
         const double g00 = c1 * h00 - s1 * h10, g01 = c1 * h01 - s1 * h11;
         const double g10 = s1 * h00 + c1 * h10, g11 = s1 * h01 + c1 * h11;
         // columns: J
         const double f00 = c2 * g00 - s2 * g01, f01 = s2 * g00 + c2 * g01;
         const double f10 = c2 * g10 - s2 * g11, f11 = s2 * g10 + c2 * g11;
-        if (v_p1 && v_p2) H[p1 * k + p2] = f00;
-        if (v_p1 && v_q2) H[p1 * k + q2] = f01;
-        if (v_q1 && v_p2) H[q1 * k + p2] = f10;
-        if (v_q1 && v_q2) H[q1 * k + q2] = f11;
+        if (v_p1 && v_p2) H[p1 * hs + p2] = f00;
+        if (v_p1 && v_q2) H[p1 * hs + q2] = f01;
+        if (v_q1 && v_p2) H[q1 * hs + p2] = f10;
+        if (v_q1 && v_q2) H[q1 * hs + q2] = f11;
       }
       for (int e = tid; e < k * np; e += kSmallThreads) {
         const int row = (int)(((float)e + 0.5f) * inv_np), t = e - row * np;
         const int p = rp[t], q = rq[t];
         if (p < k && q < k) {
           const double c = rc[t], s = rs[t];
-          const double vp = V[row * k + p], vq = V[row * k + q];
-          V[row * k + p] = c * vp - s * vq;
-          V[row * k + q] = s * vp + c * vq;
+          const double vp = V[row * vs + p], vq = V[row * vs + q];
+          V[row * vs + p] = c * vp - s * vq;
+          V[row * vs + q] = s * vp + c * vq;
         }
       }
       __syncthreads();
     }
   }
-  for (int i = tid; i < k; i += kSmallThreads) dg[i] = H[i * k + i];
+  for (int i = tid; i < k; i += kSmallThreads) dg[i] = H[i * hs + i];
   __syncthreads();
   for (int i = tid; i < k; i += kSmallThreads) {
     const double d = dg[i];
@@ -342,14 +345,15 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi(int k, const double* _
   __syncthreads();
   for (int e = tid; e < k * k; e += kSmallThreads) {
     const int row = e / k, c = e % k;
-    S[(size_t)row * lds + c] = V[row * k + perm[c]];
+    S[(size_t)row * lds + c] = V[row * vs + perm[c]];
   }
 }
 
 hipError_t launch_jacobi(hipStream_t st, int k, const double* H, int ldh, double* theta,
                          double* S, int lds, double* work) {
   if (k < 1 || k > kSmallMaxK) return hipErrorInvalidValue;
-  const size_t hb = sizeof(double) * (size_t)k * k;
+  // H (and V) in LDS with rows k | 1 doubles apart
+  const size_t hb = sizeof(double) * (size_t)k * (size_t)(k | 1);
   if (2 * hb <= kSmallLdsMax) {
     hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<true, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * hb));
