@@ -89,6 +89,49 @@ def test_forced_breakdown_is_reported(gpu_lib, torch_dev, engine, precision):
                                                       / np.linalg.norm(B[:, c])), (c, r, rs[c])
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_zero_right_hand_sides_among_others(gpu_lib, torch_dev, precision):
+    # more systems than workgroups on the resident engine (3 shifts x 100
+    # columns), every other right-hand side zero: a workgroup that meets a
+    # zero column ends that item early and takes the next one; zero columns
+    # give zero solutions, zero iterations and zero residuals, and the others
+    # converge in the same launch
+    torch = torch_dev
+    dims, shift = (20, 20), 0.01
+    csr = grid_laplacian(dims, shift)
+    A = csr.to_scipy()
+    n = csr.n
+    z = np.array([0.3 + 0.05j, 1.0 + 0.2j, 4.0 + 0.1j])
+    k = 100
+    B = np.random.default_rng(5).standard_normal((n, k))
+    B[:, 0::2] = 0.0
+    tol = 1e-8
+    with gpu_lib.Plan(csr, 0.0, 0.2, 4, nc=2, q=1, p=4, precision=precision,
+                      engine="resident") as plan:
+        assert plan.engine == "resident"
+        want = torch.complex64 if precision == "fp32" else torch.complex128
+        X = torch.zeros((n, len(z) * k), dtype=want, device="cuda")
+        its, rs = plan.shifted_solve(z, torch.from_numpy(B).cuda(), X, tol)
+    Xh = X.cpu().numpy().astype(np.complex128)
+    for j in range(len(z)):
+        for c in range(k):
+            col = j * k + c
+            if c % 2 == 0:
+                assert its[col] == 0 and rs[col] == 0.0, (j, c, its[col], rs[col])
+                assert np.abs(Xh[:, col]).max() == 0.0, (j, c)
+            else:
+                assert its[col] > 0 and rs[col] <= 1.01 * tol, (j, c, its[col], rs[col])
+    lam = grid_eigs(dims, shift)[0]
+    M = A.toarray()
+    out_round = 2.0 ** -24 if precision == "fp32" else 0.0
+    for j in range(len(z)):
+        kappa = np.abs(z[j] - lam).max() / np.abs(z[j] - lam).min()
+        for c in (1, 51, 99):
+            ref = np.linalg.solve(z[j] * np.eye(n) - M, B[:, c])
+            err = np.linalg.norm(Xh[:, j * k + c] - ref) / np.linalg.norm(ref)
+            assert err <= 1.1 * kappa * tol + out_round * 4 + 1e-13, (j, c, err)
+
+
 def test_multishift_rejects_real_shifts(gpu_lib, torch_dev):
     torch = torch_dev
     csr = grid_laplacian(DIMS, SHIFT)
